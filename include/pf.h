@@ -1,0 +1,201 @@
+/*
+ * pf.h -- partition-method factor-and-solve for structured linear systems on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: the "parallel factorization" A = F T G of Amodio & Brugnano,
+ * "Parallel factorizations in numerical analysis", Sec. 2, eqs. (parpart),
+ * (parfact)-(parG), (parblock) with the LU local factorization, the reduced
+ * matrices of eqs. (redmatr) and (redmatr1), and the ODE-IVP reading of
+ * Sec. 3 (eqs. (D), (recur), (pups)).  The unknowns are split into
+ * partitions separated by single separator blocks; every partition is
+ * eliminated independently (one group of lanes per partition), the small
+ * reduced system on the separators is assembled from the partitions'
+ * contributions and solved by applying the same method to it recursively,
+ * and the partitions are then back-substituted independently.
+ *
+ * All functions are plain C.  Pointers named "device" must be HIP device
+ * memory; everything else is host memory.  Streams are hipStream_t passed as
+ * void* (NULL = the default stream).
+ *
+ * Matrix storage (caller-owned DEVICE memory, FP64, never modified):
+ *   an m x m block is column-major: entry (i,j) at blk[i + j*m]; a block
+ *   array is a contiguous sequence of blocks (block k at offset k*m*m).
+ *   PF_BTRI (block tridiagonal; m == 1 is scalar tridiagonal):
+ *       D[k]  = A(k,k)    for k = 0..nb-1
+ *       Lo[k] = A(k+1,k)  for k = 0..nb-2
+ *       Up[k] = A(k,k+1)  for k = 0..nb-2          (C must be NULL)
+ *   PF_BABD (lower block bidiagonal plus a top-right corner block: BABD
+ *       matrices from one-step ODE-BVP methods with non-separated boundary
+ *       conditions, circulant-like matrices after a row permutation, and the
+ *       discrete IVP of Sec. 3 with C = 0; the form after eq. (redmatr1)):
+ *       D[k]  = A(k,k)    for k = 0..nb-1  (D[0] = B0, D[k+1] = R_k)
+ *       Lo[k] = A(k+1,k)  for k = 0..nb-2  (S_k)
+ *       C     = A(0,nb-1)                  (B1; Up must be NULL)
+ * Right-hand sides and solutions are n x nrhs column-major (n = m*nb) with
+ * a leading dimension >= n, in DEVICE memory.
+ *
+ * Errors: 0 = success; negative = invalid argument number -k (checked on
+ * the host before any work is queued); positive = a PF_E* code below.
+ * Numeric problems found on the device (an exactly zero pivot) are reported
+ * by pf_sync_status / pf_solve with info != NULL.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { PF_BTRI = 0, PF_BABD = 1 } pf_kind;
+
+/* PF_FP64: every elimination in FP64.
+ * PF_FP32_IR: the finest-level eliminations in FP32 (factors stored in
+ * FP32), the reduced separator systems in FP64, and FP64 iterative
+ * refinement on the FP64 residual r = f - A x until the normwise backward
+ * error eta <= tol. */
+typedef enum { PF_FP64 = 0, PF_FP32_IR = 1 } pf_prec;
+
+enum {
+    PF_OK = 0,
+    PF_ESINGULAR = 1,   /* exactly zero pivot inside a pivot block            */
+    PF_ENOCONV = 2,     /* refinement stagnated or hit max_refine            */
+    PF_ENOMEM = 3,      /* device allocation failed                          */
+    PF_EHIP = 4,        /* a HIP runtime call failed                         */
+    PF_EUNSUPPORTED = 5 /* block size beyond what the library instantiates   */
+};
+
+enum { PF_FLAG_ETA = 1 }; /* pf_solve in FP64 also computes eta (one residual pass) */
+
+typedef struct {
+    int32_t kind;       /* pf_kind                                            */
+    int32_t m;          /* block size, 1 <= m <= 32                           */
+    int64_t nb;         /* number of block rows (= unknown blocks), >= 2      */
+    const double *D;    /* device, nb blocks                                  */
+    const double *Lo;   /* device, nb-1 blocks                                */
+    const double *Up;   /* device, nb-1 blocks (PF_BTRI) or NULL (PF_BABD)    */
+    const double *C;    /* device, 1 block (PF_BABD) or NULL (PF_BTRI)        */
+} pf_matrix;
+
+typedef struct {
+    int32_t partitions; /* partitions p of the finest level; 0 = planner.
+                           PF_BTRI: 1 <= p <= (nb+1)/2;
+                           PF_BABD: 1 <= p <= (nb-1)/2                        */
+    int32_t prec;       /* pf_prec                                            */
+    int32_t max_refine; /* PF_FP32_IR iteration cap; <= 0 means 10           */
+    int32_t block_rows; /* blocks per partition at the finest level when
+                           partitions == 0; 0 = autotuned table               */
+    int32_t flags;      /* PF_FLAG_*                                          */
+    int32_t reserved;
+    double tol;         /* PF_FP32_IR target eta; <= 0 means 1e-12            */
+} pf_opts;
+
+typedef struct {
+    int32_t status;       /* PF_OK or a PF_E* code                           */
+    int32_t refine_iters; /* refinement corrections applied (PF_FP32_IR)     */
+    int32_t bad_level;    /* level of the first zero pivot (0 = input)        */
+    int32_t reserved;
+    int64_t bad_block;    /* block row of that pivot at that level, else -1  */
+    double eta;           /* normwise backward error
+                             ||f-Ax||/(||A|| ||x|| + ||f||) (inf-norms, max
+                             over right-hand sides); -1 when not computed    */
+} pf_info;
+
+typedef struct pf_factor_s *pf_factor_t;
+
+/* Factor A (eqs. (parfact), (parblock) with the LU variant, applied
+ * recursively to the reduced matrix (redmatr)/(redmatr1)).
+ * The handle keeps pointers to A's arrays (PF_FP32_IR refinement and the
+ * forward solve read them): A must stay valid and unmodified until
+ * pf_destroy.  Work is queued on `stream`; numeric status is read by
+ * pf_sync_status.  Returns 0, -k for invalid argument k, PF_ENOMEM, PF_EHIP
+ * or PF_EUNSUPPORTED. */
+int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t *out);
+
+/* Solve A x = f with the factors (the F, T and G solves of Sec. 2: parallel
+ * forward sweeps, the recursive reduced solve, parallel back substitution;
+ * for PF_FP32_IR also the FP64 refinement loop).  f and x may be the same
+ * buffer.  If info != NULL the call synchronizes `stream` and fills it;
+ * otherwise it is fully asynchronous (PF_FP64) -- PF_FP32_IR always
+ * synchronizes once per refinement step to test eta. */
+int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
+             int64_t ldx, void *stream, pf_info *info);
+
+/* Factor and solve nsys independent systems.  All systems that share a block
+ * size run in the same kernel launches (one launch per level and phase per
+ * block size), and the whole sequence is recorded once into a HIP graph that
+ * is replayed for the batch.  A, nrhs, f, ldf, x, ldx are HOST arrays of
+ * length nsys whose elements describe device buffers.  If factors != NULL,
+ * factors[i] receives a handle for system i that the caller destroys;
+ * otherwise the factors are released before returning.  info (nsys entries,
+ * may be NULL) receives per-system status; the call synchronizes `stream`. */
+int pf_solve_batch(int32_t nsys, const pf_matrix *A, const pf_opts *opts,
+                   const int32_t *nrhs, const double *const *f, const int64_t *ldf,
+                   double *const *x, const int64_t *ldx, void *stream,
+                   pf_factor_t *factors, pf_info *info);
+
+/* Device bytes pf_factor allocates for A with these options (admission
+ * control), and that pf_solve adds per right-hand side. */
+size_t pf_factor_bytes(const pf_matrix *A, const pf_opts *opts);
+size_t pf_solve_bytes_per_rhs(const pf_matrix *A, const pf_opts *opts);
+
+/* Synchronize the factor's stream and report the device-side status of the
+ * factorization (zero pivots). */
+int pf_sync_status(pf_factor_t F, pf_info *info);
+
+/* Release the factor's device memory (synchronizes its stream first). */
+void pf_destroy(pf_factor_t F);
+
+const char *pf_strerror(int code);
+
+/* ---- plan inspection (host) ------------------------------------------- */
+/* Number of levels of the recursion, and for level l its kind, block count
+ * and partition count. */
+int pf_factor_levels(pf_factor_t F);
+int pf_factor_level(pf_factor_t F, int level, int32_t *kind, int64_t *nb, int64_t *p);
+
+/* The level plan pf_factor would use, computed on the host without any
+ * device work: returns the number of levels L (or a negative argument
+ * error) and fills up to max_levels entries of kinds/nbs/ps (any may be
+ * NULL).  Level 0 is A itself; level l+1 is the reduced matrix of level l
+ * (p-1 blocks for PF_BTRI, p+1 for PF_BABD); the last level has p = 1. */
+int pf_plan(const pf_matrix *A, const pf_opts *opts, int32_t max_levels, int32_t *kinds,
+            int64_t *nbs, int64_t *ps);
+
+/* Block size the kernels run at: m rounded up to a power of two (the matrix
+ * is padded with identity diagonal entries when it differs from m). */
+int pf_factor_block_size(pf_factor_t F);
+
+/* Copy the reduced system that level `level` produced for level+1 into host
+ * buffers (FP64, blocks column-major, of the pf_factor_block_size): PF_BTRI gives the (p-1)-block block
+ * tridiagonal matrix of eq. (redmatr) (D with the two neighbours'
+ * contributions summed, Lo, Up); PF_BABD gives the (p+1)-block BABD of
+ * eq. (redmatr1) (D, Lo, C in Up's place).  Synchronizes. */
+int pf_factor_export_reduced(pf_factor_t F, int level, double *D, double *Lo, double *Up);
+
+/* ---- structure mapping (device kernels, stream-ordered) ----------------- */
+/* Banded matrix (kl sub-, ku super-diagonals; LAPACK band storage: A(i,j) at
+ * ab[ku + i - j + j*ldab], ldab >= kl+ku+1) -> PF_BTRI blocks with block size
+ * m = max(kl,ku), the block form of a banded matrix in Sec. 2.  n must be a
+ * multiple of m.  D, Lo, Up are device outputs of n/m, n/m-1, n/m-1 blocks. */
+int pf_band_to_btri(int64_t n, int32_t kl, int32_t ku, const double *ab, int64_t ldab,
+                    double *D, double *Lo, double *Up, void *stream);
+
+/* ABD matrix from a one-step method with separated boundary conditions
+ * (Sec. 3): qa rows Ba (qa x m) at t0, N step rows [S_k R_k] (m x 2m,
+ * S and R as block arrays), qb = m - qa rows Bb (qb x m) at t_N.  Rows are
+ * regrouped into N+1 block rows of m rows (row 0 = [Ba; last qb rows of
+ * step 0]; row k = [first qa rows of step k-1; last qb rows of step k];
+ * row N = [first qa rows of step N-1; Bb]), which is block tridiagonal.
+ * Ba, Bb are column-major with leading dimensions qa, qb.  Outputs: N+1, N,
+ * N blocks. */
+int pf_abd_to_btri(int32_t m, int64_t N, int32_t qa, const double *Ba, const double *S,
+                   const double *R, const double *Bb, double *D, double *Lo, double *Up,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -1,0 +1,288 @@
+// Bandwidth-bound helper kernels: FP64 residual and norms (refinement and
+// the backward-error gate), padding of block sizes without an instantiation,
+// and the structure mappings of Sec. 2 (banded and ABD -> block tridiagonal).
+#include "pf_internal.h"
+
+namespace pf {
+namespace {
+
+__device__ __forceinline__ unsigned long long dbits(double v)
+{
+    return (unsigned long long)__double_as_longlong(v);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// One thread per (row, right-hand side); blockIdx.y = right-hand side, so
+// every wave reduces its three norms before one atomic each.
+__global__ __launch_bounds__(256) void k_residual(int kind, int m, int64_t nb,
+                                                  const double *__restrict__ D,
+                                                  const double *__restrict__ Lo,
+                                                  const double *__restrict__ Up,
+                                                  const double *__restrict__ C,
+                                                  const double *__restrict__ f, int64_t ldf,
+                                                  const double *__restrict__ x, int64_t ldx,
+                                                  double *__restrict__ r, int64_t ldr,
+                                                  unsigned long long *norms)
+{
+    const int64_t n = (int64_t)m * nb;
+    const int64_t mm = (int64_t)m * m;
+    const int c = blockIdx.y;
+    const double *xc = x + c * ldx;
+    double mr = 0.0, mx = 0.0, mf = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = row / m;
+        const int i = (int)(row - k * m);
+        const double fv = f[row + c * ldf];
+        double s = fv;
+        const double *dk = D + k * mm + i;
+        const double *xk = xc + k * m;
+        for (int j = 0; j < m; ++j) s = fma(-dk[(int64_t)j * m], xk[j], s);
+        if (k > 0) {
+            const double *lk = Lo + (k - 1) * mm + i;
+            const double *xp = xc + (k - 1) * m;
+            for (int j = 0; j < m; ++j) s = fma(-lk[(int64_t)j * m], xp[j], s);
+        }
+        if (kind == 0 && k + 1 < nb) {
+            const double *uk = Up + k * mm + i;
+            const double *xn = xc + (k + 1) * m;
+            for (int j = 0; j < m; ++j) s = fma(-uk[(int64_t)j * m], xn[j], s);
+        }
+        if (kind == 1 && k == 0) {
+            const double *ck = C + i;
+            const double *xl = xc + (nb - 1) * m;
+            for (int j = 0; j < m; ++j) s = fma(-ck[(int64_t)j * m], xl[j], s);
+        }
+        if (r) r[row + c * ldr] = s;
+        mr = fmax(mr, fabs(s));
+        mx = fmax(mx, fabs(xc[row]));
+        mf = fmax(mf, fabs(fv));
+    }
+    mr = wave_max(mr);
+    mx = wave_max(mx);
+    mf = wave_max(mf);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(norms + 3 * c + 0, dbits(mr));
+        atomicMax(norms + 3 * c + 1, dbits(mx));
+        atomicMax(norms + 3 * c + 2, dbits(mf));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_norminf(int kind, int m, int64_t nb,
+                                                 const double *__restrict__ D,
+                                                 const double *__restrict__ Lo,
+                                                 const double *__restrict__ Up,
+                                                 const double *__restrict__ C,
+                                                 unsigned long long *out)
+{
+    const int64_t n = (int64_t)m * nb;
+    const int64_t mm = (int64_t)m * m;
+    double best = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = row / m;
+        const int i = (int)(row - k * m);
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += fabs(D[k * mm + i + (int64_t)j * m]);
+        if (k > 0)
+            for (int j = 0; j < m; ++j) s += fabs(Lo[(k - 1) * mm + i + (int64_t)j * m]);
+        if (kind == 0 && k + 1 < nb)
+            for (int j = 0; j < m; ++j) s += fabs(Up[k * mm + i + (int64_t)j * m]);
+        if (kind == 1 && k == 0)
+            for (int j = 0; j < m; ++j) s += fabs(C[i + (int64_t)j * m]);
+        best = fmax(best, s);
+    }
+    best = wave_max(best);
+    if ((threadIdx.x & 63) == 0) atomicMax(out, dbits(best));
+}
+
+__global__ void k_axpy(int64_t n, const double *__restrict__ d, int64_t ldd,
+                       double *__restrict__ x, int64_t ldx)
+{
+    const int c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i + c * ldx] += d[i + c * ldd];
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t count, unsigned long long v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_pad_blocks(int m, int M, int64_t count, const double *__restrict__ src,
+                             double *__restrict__ dst, double diag)
+{
+    const int64_t MM = (int64_t)M * M, mm = (int64_t)m * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count * MM;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / MM;
+        const int rem = (int)(e - k * MM);
+        const int j = rem / M, i = rem - j * M;
+        double v;
+        if (i < m && j < m) v = src[k * mm + i + (int64_t)j * m];
+        else v = (i == j) ? diag : 0.0;
+        dst[e] = v;
+    }
+}
+
+__global__ void k_pad_rhs(int m, int M, int64_t nb, const double *__restrict__ src, int64_t lds,
+                          double *__restrict__ dst, int64_t ldd, int to_padded)
+{
+    const int c = blockIdx.y;
+    const int64_t nP = (int64_t)M * nb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nP;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / M;
+        const int i = (int)(e - k * M);
+        if (to_padded) {
+            dst[e + c * ldd] = (i < m) ? src[k * m + i + c * lds] : 0.0;
+        } else if (i < m) {
+            dst[k * m + i + c * ldd] = src[e + c * lds];
+        }
+    }
+}
+
+// A(r, c) from LAPACK band storage, zero outside the band.
+__device__ __forceinline__ double band_at(int64_t n, int kl, int ku, const double *ab,
+                                          int64_t ldab, int64_t r, int64_t c)
+{
+    if (r < 0 || c < 0 || r >= n || c >= n) return 0.0;
+    if (r - c > kl || c - r > ku) return 0.0;
+    return ab[(ku + r - c) + c * ldab];
+}
+
+__global__ void k_band_to_btri(int64_t n, int kl, int ku, const double *__restrict__ ab,
+                               int64_t ldab, int m, double *D, double *Lo, double *Up)
+{
+    const int64_t nb = n / m, mm = (int64_t)m * m;
+    const int64_t total = nb * mm;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / mm;
+        const int rem = (int)(e - k * mm);
+        const int j = rem / m, i = rem - j * m;
+        D[e] = band_at(n, kl, ku, ab, ldab, k * m + i, k * m + j);
+        if (k + 1 < nb) {
+            Lo[e] = band_at(n, kl, ku, ab, ldab, (k + 1) * m + i, k * m + j);
+            Up[e] = band_at(n, kl, ku, ab, ldab, k * m + i, (k + 1) * m + j);
+        }
+    }
+}
+
+// Row regrouping of an ABD matrix (separated boundary conditions) into a
+// block tridiagonal one; see pf_abd_to_btri.
+__global__ void k_abd_to_btri(int m, int64_t N, int qa, const double *__restrict__ Ba,
+                              const double *__restrict__ S, const double *__restrict__ R,
+                              const double *__restrict__ Bb, double *D, double *Lo, double *Up)
+{
+    const int qb = m - qa;
+    const int64_t mm = (int64_t)m * m;
+    const int64_t total = (N + 1) * mm;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / mm;
+        const int rem = (int)(e - k * mm);
+        const int j = rem / m, i = rem - j * m;
+        double dv;
+        if (i < qa) dv = (k == 0) ? Ba[i + (int64_t)j * qa] : R[(k - 1) * mm + i + (int64_t)j * m];
+        else dv = (k == N) ? Bb[(i - qa) + (int64_t)j * qb] : S[k * mm + i + (int64_t)j * m];
+        D[e] = dv;
+        if (k < N) {
+            Lo[e] = (i < qa) ? S[k * mm + i + (int64_t)j * m] : 0.0;   // A(k+1, k)
+            Up[e] = (i < qa) ? 0.0 : R[k * mm + i + (int64_t)j * m];  // A(k, k+1)
+        }
+    }
+}
+
+inline unsigned grid1(int64_t work, int block)
+{
+    int64_t g = (work + block - 1) / block;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const double *Lo,
+                           const double *Up, const double *C, int32_t nrhs, const double *f,
+                           int64_t ldf, const double *x, int64_t ldx, double *r, int64_t ldr,
+                           unsigned long long *norms, hipStream_t s)
+{
+    const int64_t n = (int64_t)m * nb;
+    hipLaunchKernelGGL(k_residual, dim3(grid1(n, 256), nrhs), dim3(256), 0, s, kind, m, nb, D,
+                       Lo, Up, C, f, ldf, x, ldx, r, ldr, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_norminf(int kind, int m, int64_t nb, const double *D, const double *Lo,
+                          const double *Up, const double *C, unsigned long long *out,
+                          hipStream_t s)
+{
+    const int64_t n = (int64_t)m * nb;
+    hipLaunchKernelGGL(k_norminf, dim3(grid1(n, 256)), dim3(256), 0, s, kind, m, nb, D, Lo, Up,
+                       C, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, double *x,
+                       int64_t ldx, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(grid1(n, 256), nrhs), dim3(256), 0, s, n, d, ldd, x, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(count, 256)), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_blocks(int m, int M, int64_t count, const double *src, double *dst,
+                             double diag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pad_blocks, dim3(grid1(count * M * M, 256)), dim3(256), 0, s, m, M,
+                       count, src, dst, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_rhs(int m, int M, int64_t nb, int32_t nrhs, const double *src,
+                          int64_t lds, double *dst, int64_t ldd, bool to_padded,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pad_rhs, dim3(grid1((int64_t)M * nb, 256), nrhs), dim3(256), 0, s, m,
+                       M, nb, src, lds, dst, ldd, to_padded ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_to_btri(int64_t n, int kl, int ku, const double *ab, int64_t ldab,
+                               int m, double *D, double *Lo, double *Up, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_band_to_btri, dim3(grid1(n * m, 256)), dim3(256), 0, s, n, kl, ku, ab,
+                       ldab, m, D, Lo, Up);
+    return hipGetLastError();
+}
+
+hipError_t launch_abd_to_btri(int m, int64_t N, int qa, const double *Ba, const double *S,
+                              const double *R, const double *Bb, double *D, double *Lo,
+                              double *Up, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_abd_to_btri, dim3(grid1((N + 1) * m * m, 256)), dim3(256), 0, s, m, N,
+                       qa, Ba, S, R, Bb, D, Lo, Up);
+    return hipGetLastError();
+}
+
+}  // namespace pf

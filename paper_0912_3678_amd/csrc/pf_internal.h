@@ -1,0 +1,90 @@
+// Internal interface between the host planner (api.cpp) and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pf {
+
+// Block sizes with kernel instantiations; other m are padded up to the next.
+constexpr int kMaxM = 32;
+
+// One level of the recursion: the matrix this level factors and the reduced
+// matrix it produces for the next level.
+struct LevelArgs {
+    int64_t nb;            // block rows of this level's matrix
+    int64_t p;             // partitions
+    const double *D;       // nb blocks
+    const double *Dadd;    // optional second addend of D (reduced levels), or null
+    const double *Lo;      // nb-1 blocks
+    const double *Up;      // nb-1 blocks (BTRI) or null
+    const double *C;       // BABD corner or null
+    void *E;               // per block row: inverse of the eliminated pivot block
+    void *R;               // per block row: left-separator spike row (BTRI)
+    void *Z;               // per block row: left-separator spike column
+    void *X;               // per block row: D'^{-1} Up (BTRI)
+    double *nD;            // next level: diagonal blocks
+    double *nDadd;         // next level: second addend of the diagonal (BTRI)
+    double *nLo;           // next level: sub-diagonal blocks
+    double *nUp;           // next level: super-diagonal blocks (BTRI)
+    double *nC;            // next level: corner (BABD)
+    unsigned long long *status;  // packed (level << 40 | block); atomicMin
+    int level;
+};
+
+// One level of a solve.
+struct SolveArgs {
+    int64_t nb, p;
+    int32_t nrhs;
+    const double *Lo;      // this level's sub-diagonal blocks (forward sweep)
+    const void *E, *R, *Z, *X;
+    const double *F;       // right-hand sides of this level (ld ldf)
+    const double *Fadd;    // optional second addend (reduced levels)
+    int64_t ldf;
+    double *Y;             // forward: t; backward: x (ld ldy)
+    int64_t ldy;
+    double *nF;            // next level right-hand side (ld ldn)
+    double *nFadd;
+    int64_t ldn;
+    const double *Xsep;    // backward: next level's solution (ld ldn)
+};
+
+// Launchers (kernels.hip).  M must be 1, 2, 4, 8, 16 or 32.
+hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s);
+hipError_t launch_btri_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
+hipError_t launch_btri_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
+hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s);
+hipError_t launch_babd_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
+hipError_t launch_babd_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
+
+// Utility kernels (kernels_util.hip).
+// Copy m x m blocks into M x M blocks (M >= m); the extra diagonal entries
+// are set to `diag` (1 for diagonal blocks, 0 otherwise).
+hipError_t launch_pad_blocks(int m, int M, int64_t count, const double *src, double *dst,
+                             double diag, hipStream_t s);
+// Copy n x nrhs (ld ldsrc) between an m-block and an M-block row layout.
+hipError_t launch_pad_rhs(int m, int M, int64_t nb, int32_t nrhs, const double *src,
+                          int64_t lds, double *dst, int64_t ldd, bool to_padded,
+                          hipStream_t s);
+// r = f - A x (FP64) with the max-abs norms of r, x, f per right-hand side
+// accumulated into norms[3*c + {0,1,2}] (as ordered uint64 bit patterns).
+hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const double *Lo,
+                           const double *Up, const double *C, int32_t nrhs, const double *f,
+                           int64_t ldf, const double *x, int64_t ldx, double *r, int64_t ldr,
+                           unsigned long long *norms, hipStream_t s);
+// ||A||_inf into *out (uint64 bit pattern of a non-negative double; caller zeroes).
+hipError_t launch_norminf(int kind, int m, int64_t nb, const double *D, const double *Lo,
+                          const double *Up, const double *C, unsigned long long *out,
+                          hipStream_t s);
+// x += d
+hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, double *x,
+                       int64_t ldx, hipStream_t s);
+// Fill count 64-bit words with a value (kernel, capture-safe).
+hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v,
+                           hipStream_t s);
+hipError_t launch_band_to_btri(int64_t n, int kl, int ku, const double *ab, int64_t ldab,
+                               int m, double *D, double *Lo, double *Up, hipStream_t s);
+hipError_t launch_abd_to_btri(int m, int64_t N, int qa, const double *Ba, const double *S,
+                              const double *R, const double *Bb, double *D, double *Lo,
+                              double *Up, hipStream_t s);
+
+}  // namespace pf

@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in ``include/pf.h`` (ctypes; argument
+marshalling only -- every step of the method runs in the HIP library).
+
+Device buffers are torch tensors on a HIP device; streams are torch streams.
+The library must be built (``paper_0912_3678_amd.build``); importing the
+binding without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpf.so")
+
+PF_BTRI, PF_BABD = 0, 1
+PF_FP64, PF_FP32_IR = 0, 1
+PF_OK, PF_ESINGULAR, PF_ENOCONV, PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED = 0, 1, 2, 3, 4, 5
+PF_FLAG_ETA = 1
+
+EXPORTED = [
+    "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",
+    "pf_sync_status", "pf_destroy", "pf_strerror", "pf_factor_levels", "pf_factor_level",
+    "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
+    "pf_plan",
+]
+
+
+class pf_matrix(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("nb", ctypes.c_int64),
+                ("D", ctypes.c_void_p), ("Lo", ctypes.c_void_p), ("Up", ctypes.c_void_p),
+                ("C", ctypes.c_void_p)]
+
+
+class pf_opts(ctypes.Structure):
+    _fields_ = [("partitions", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("block_rows", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
+
+
+class pf_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
+                ("bad_level", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bad_block", ctypes.c_int64), ("eta", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_0912_3678_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    sigs = {
+        "pf_factor": (ctypes.c_int, [P(pf_matrix), P(pf_opts), vp, P(vp)]),
+        "pf_solve": (ctypes.c_int, [vp, i32, vp, i64, vp, i64, vp, P(pf_info)]),
+        "pf_solve_batch": (ctypes.c_int, [i32, P(pf_matrix), P(pf_opts), P(i32), P(vp), P(i64),
+                                          P(vp), P(i64), vp, P(vp), P(pf_info)]),
+        "pf_factor_bytes": (ctypes.c_size_t, [P(pf_matrix), P(pf_opts)]),
+        "pf_solve_bytes_per_rhs": (ctypes.c_size_t, [P(pf_matrix), P(pf_opts)]),
+        "pf_sync_status": (ctypes.c_int, [vp, P(pf_info)]),
+        "pf_destroy": (None, [vp]),
+        "pf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "pf_factor_levels": (ctypes.c_int, [vp]),
+        "pf_plan": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, P(i32), P(i64), P(i64)]),
+        "pf_factor_level": (ctypes.c_int, [vp, ctypes.c_int, P(i32), P(i64), P(i64)]),
+        "pf_factor_block_size": (ctypes.c_int, [vp]),
+        "pf_factor_export_reduced": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+        "pf_band_to_btri": (ctypes.c_int, [i64, i32, i32, vp, i64, vp, vp, vp, vp]),
+        "pf_abd_to_btri": (ctypes.c_int, [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PFError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = load().pf_strerror(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_matrix(kind, m, nb, D, Lo, Up=None, C=None) -> pf_matrix:
+    """Device tensors (column-major blocks, FP64, contiguous) -> pf_matrix."""
+    for t in (D, Lo, Up, C):
+        if t is not None:
+            if t.dtype.itemsize != 8 or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError("matrix arrays must be contiguous FP64 device tensors")
+    return pf_matrix(kind, m, nb, _ptr(D).value if D is not None else None,
+                     _ptr(Lo).value if Lo is not None else None,
+                     _ptr(Up).value if Up is not None else None,
+                     _ptr(C).value if C is not None else None)
+
+
+def make_opts(partitions=0, prec=PF_FP64, max_refine=0, block_rows=0, flags=0, tol=0.0):
+    return pf_opts(partitions, prec, max_refine, block_rows, flags, 0, tol)
+
+
+def pf_factor(A: pf_matrix, opts: pf_opts | None = None, stream=None):
+    h = ctypes.c_void_p()
+    rc = load().pf_factor(ctypes.byref(A), ctypes.byref(opts) if opts is not None else None,
+                          _stream(stream), ctypes.byref(h))
+    if rc != 0:
+        raise PFError(rc, "pf_factor")
+    return h
+
+
+def pf_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_info=True):
+    """f, x: device FP64 tensors holding n x nrhs column-major data (shape
+    (nrhs, n) or (n,)).  Returns a pf_info (synchronizing) or None."""
+    if nrhs is None:
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+    n = f.shape[-1]
+    ldf = n if ldf is None else ldf
+    ldx = n if ldx is None else ldx
+    info = pf_info() if want_info else None
+    rc = load().pf_solve(F, nrhs, _ptr(f), ldf, _ptr(x), ldx, _stream(stream),
+                         ctypes.byref(info) if info is not None else None)
+    if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
+        raise PFError(rc, "pf_solve")
+    return info
+
+
+def pf_sync_status(F) -> pf_info:
+    info = pf_info()
+    load().pf_sync_status(F, ctypes.byref(info))
+    return info
+
+
+def pf_destroy(F):
+    load().pf_destroy(F)
+
+
+def pf_factor_bytes(A: pf_matrix, opts: pf_opts | None = None) -> int:
+    return int(load().pf_factor_bytes(ctypes.byref(A), ctypes.byref(opts) if opts else None))
+
+
+def pf_solve_bytes_per_rhs(A: pf_matrix, opts: pf_opts | None = None) -> int:
+    return int(load().pf_solve_bytes_per_rhs(ctypes.byref(A),
+                                             ctypes.byref(opts) if opts else None))
+
+
+def pf_factor_levels(F):
+    lib = load()
+    out = []
+    for l in range(lib.pf_factor_levels(F)):
+        k, nb, p = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        lib.pf_factor_level(F, l, ctypes.byref(k), ctypes.byref(nb), ctypes.byref(p))
+        out.append((k.value, nb.value, p.value))
+    return out
+
+
+def pf_plan(A: pf_matrix, opts: pf_opts | None = None):
+    """Host-side level plan: list of (kind, nb, p)."""
+    lib = load()
+    K = (ctypes.c_int32 * 64)()
+    N = (ctypes.c_int64 * 64)()
+    P = (ctypes.c_int64 * 64)()
+    L = lib.pf_plan(ctypes.byref(A), ctypes.byref(opts) if opts else None, 64, K, N, P)
+    if L < 0:
+        raise PFError(L, "pf_plan")
+    return [(K[i], N[i], P[i]) for i in range(L)]
+
+
+def pf_factor_block_size(F) -> int:
+    return int(load().pf_factor_block_size(F))
+
+
+def pf_factor_export_reduced(F, level: int):
+    """Reduced matrix produced by `level` as numpy (D, Lo, Up-or-corner),
+    block arrays indexed [k, i, j]."""
+    import numpy as np
+    kind, nb, p = pf_factor_levels(F)[level]
+    M = pf_factor_block_size(F)
+    nr = (p - 1) if kind == PF_BTRI else (p + 1)
+    D = np.zeros((nr, M, M))
+    Lo = np.zeros((max(nr - 1, 1), M, M))
+    Up = np.zeros((max(nr - 1, 1) if kind == PF_BTRI else 1, M, M))
+    rc = load().pf_factor_export_reduced(F, level, D.ctypes.data, Lo.ctypes.data, Up.ctypes.data)
+    if rc != 0:
+        raise PFError(rc, "pf_factor_export_reduced")
+    tr = lambda a: np.ascontiguousarray(a.transpose(0, 2, 1))
+    return tr(D), tr(Lo[:nr - 1]), (tr(Up[:nr - 1]) if kind == PF_BTRI else tr(Up)[0])
+
+
+def pf_band_to_btri(n, kl, ku, ab, ldab, D, Lo, Up, stream=None):
+    rc = load().pf_band_to_btri(n, kl, ku, _ptr(ab), ldab, _ptr(D), _ptr(Lo), _ptr(Up),
+                                _stream(stream))
+    if rc != 0:
+        raise PFError(rc, "pf_band_to_btri")
+
+
+def pf_abd_to_btri(m, N, qa, Ba, S, R, Bb, D, Lo, Up, stream=None):
+    rc = load().pf_abd_to_btri(m, N, qa, _ptr(Ba), _ptr(S), _ptr(R), _ptr(Bb), _ptr(D),
+                               _ptr(Lo), _ptr(Up), _stream(stream))
+    if rc != 0:
+        raise PFError(rc, "pf_abd_to_btri")
+
+
+def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False):
+    """mats: list of pf_matrix; fs/xs: lists of device tensors (nrhs_i, n_i)."""
+    lib = load()
+    ns = len(mats)
+    A = (pf_matrix * ns)(*mats)
+    nr = (ctypes.c_int32 * ns)(*nrhs)
+    fp = (ctypes.c_void_p * ns)(*[f.data_ptr() for f in fs])
+    xp = (ctypes.c_void_p * ns)(*[x.data_ptr() for x in xs])
+    lf = (ctypes.c_int64 * ns)(*[f.shape[-1] for f in fs])
+    lx = (ctypes.c_int64 * ns)(*[x.shape[-1] for x in xs])
+    fac = (ctypes.c_void_p * ns)() if keep_factors else None
+    infos = (pf_info * ns)()
+    rc = lib.pf_solve_batch(ns, A, ctypes.byref(opts) if opts is not None else None, nr, fp, lf,
+                            xp, lx, _stream(stream), fac, infos)
+    if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
+        raise PFError(rc, "pf_solve_batch")
+    return list(infos), (list(fac) if keep_factors else None)

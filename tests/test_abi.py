@@ -1,0 +1,86 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/pf.h declares, validates arguments on the host, and plans the
+recursion as documented (no GPU work is issued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_0912_3678_amd import pf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = pf.load()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pf.EXPORTED)
+
+
+def _mat(kind=pf.PF_BTRI, m=8, nb=65537):
+    fake = 256  # never dereferenced by the host-side calls below
+    return pf.pf_matrix(kind, m, nb, fake, fake, fake if kind == pf.PF_BTRI else None,
+                        fake if kind == pf.PF_BABD else None)
+
+
+def test_argument_validation():
+    lib = pf.load()
+    h = ctypes.c_void_p()
+    assert lib.pf_factor(None, None, None, ctypes.byref(h)) == -1
+    bad = _mat(nb=1)
+    assert lib.pf_factor(ctypes.byref(bad), None, None, ctypes.byref(h)) == -1
+    mixed = pf.pf_matrix(pf.PF_BTRI, 4, 10, 256, 256, 256, 256)   # BTRI with a corner
+    assert lib.pf_factor(ctypes.byref(mixed), None, None, ctypes.byref(h)) == -1
+    big = _mat(m=33)
+    assert lib.pf_factor(ctypes.byref(big), None, None, ctypes.byref(h)) == pf.PF_EUNSUPPORTED
+    A = _mat(nb=11)
+    o = pf.make_opts(partitions=7)     # > (nb+1)/2
+    assert lib.pf_factor(ctypes.byref(A), ctypes.byref(o), None, ctypes.byref(h)) == -2
+    assert lib.pf_factor(ctypes.byref(A), None, None, None) == -4
+    assert lib.pf_solve(None, 1, None, 1, None, 1, None, None) == -1
+    assert lib.pf_strerror(pf.PF_ESINGULAR).decode().startswith("exactly zero")
+
+
+def test_plan_btri_levels_shrink_to_one_chain():
+    for nb in (2, 7, 100, 65537):
+        plan = pf.pf_plan(_mat(nb=nb))
+        assert plan[0][1] == nb
+        for (k, n, p), nxt in zip(plan, plan[1:]):
+            assert k == pf.PF_BTRI and 2 <= p <= (n + 1) // 2
+            assert nxt[1] == p - 1          # reduced matrix has p-1 blocks
+        assert plan[-1][2] == 1
+
+
+def test_plan_reduced_size_depends_only_on_p():
+    """The block size of T_p depends only on p, not on n (eq. (redmatr))."""
+    for nb in (1000, 5000, 65537):
+        plan = pf.pf_plan(_mat(nb=nb), pf.make_opts(partitions=256))
+        assert plan[0][2] == 256 and plan[1][1] == 255
+
+
+def test_plan_babd_levels():
+    for nb in (2, 3, 5, 262145):
+        plan = pf.pf_plan(_mat(pf.PF_BABD, 16, nb))
+        for (k, n, p), nxt in zip(plan, plan[1:]):
+            assert k == pf.PF_BABD and 1 <= p <= (n - 1) // 2
+            assert nxt[1] == p + 1          # reduced matrix has p+1 blocks
+        assert plan[-1] == (pf.PF_BTRI, 2, 1)
+
+
+def test_factor_bytes_grow_with_size_and_precision():
+    A = _mat(nb=65537)
+    b64 = pf.pf_factor_bytes(A, pf.make_opts())
+    b32 = pf.pf_factor_bytes(A, pf.make_opts(prec=pf.PF_FP32_IR))
+    assert b64 > 4 * 65537 * 64 * 8 * 0.99
+    assert b32 < b64
+    assert pf.pf_factor_bytes(_mat(nb=1000)) < b64

@@ -1,0 +1,158 @@
+"""GPU parity: the HIP partition-method solver against the CPU oracle, through
+the C ABI.  Sizes span many partitions per wave, several waves and ragged
+partition lengths; the full-size workloads are checked too."""
+import numpy as np
+import pytest
+
+from paper_0912_3678_amd import pf
+from paper_0912_3678_amd import workloads as wl
+
+from . import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# --------------------------------------------------------------------------
+# scalar tridiagonal (m = 1)
+@pytest.mark.parametrize("p", [16, 1, 2, 3, 7, 0, 2048])
+def test_scalar_tridiagonal_4096(p):
+    s = wl.scalar_tridiagonal(4096)
+    _say("scalar n=4096 p", p)
+    x, info, levels = G.gpu_solve(s, pf.make_opts(partitions=p))
+    assert info.status == 0
+    r = G.check(s, x, tag=f"p={p}")
+    if p:
+        assert levels[0][2] == p
+    _say(r, levels)
+
+
+def test_poisson_closed_form():
+    n = 4096
+    s = wl.poisson(n)
+    x, info, _ = G.gpu_solve(s)
+    i = np.arange(1, n + 1, dtype=np.float64)
+    xe = i * (n + 1 - i) / 2.0
+    kap = n * (n + 2) / 2
+    fe = G.fwd_err(x, xe)
+    _say("poisson fwd err", fe)
+    assert fe <= 1e3 * kap * G.EPS
+    assert G.eta(s, x) <= G.ETA_TOL
+
+
+# --------------------------------------------------------------------------
+# random block tridiagonal, all instantiated block sizes, ragged lengths
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("nb", [2, 3, 7, 50, 1001, 4099])
+def test_btri_random(m, nb):
+    s = wl.random_btri(nb, m, seed=100 + m * 7 + nb)
+    _say("btri m", m, "nb", nb)
+    x, info, levels = G.gpu_solve(s)
+    assert info.status == 0
+    G.check(s, x, tag=f"m={m} nb={nb} levels={levels}")
+
+
+@pytest.mark.parametrize("m", [4, 8])
+@pytest.mark.parametrize("nrhs", [2, 5, 9])
+def test_btri_multi_rhs(m, nrhs):
+    s = wl.random_btri(777, m, seed=300 + nrhs, nrhs=nrhs)
+    x, info, _ = G.gpu_solve(s)
+    assert info.status == 0
+    G.check(s, x, tag=f"m={m} nrhs={nrhs}")
+
+
+@pytest.mark.parametrize("m", [8])
+@pytest.mark.parametrize("p", [1, 2, 5, 64, 256, 0])
+def test_p_invariance(m, p):
+    s = wl.random_btri(1025, m, seed=41)
+    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=p))
+    x0 = G.oracle_solve(s)
+    assert G.fwd_err(x, x0) <= 1e-12
+    G.check(s, x, tag=f"p={p}")
+
+
+@pytest.mark.parametrize("br", [1, 2, 3, 5, 16, 40])
+def test_block_rows_invariance(br):
+    s = wl.random_btri(3001, 4, seed=42)
+    x, info, levels = G.gpu_solve(s, pf.make_opts(block_rows=br))
+    G.check(s, x, tag=f"block_rows={br} levels={levels}")
+
+
+@pytest.mark.parametrize("m", [3, 5, 6, 12])
+def test_btri_padded_block_sizes(m):
+    s = wl.random_btri(333, m, seed=500 + m, nrhs=2)
+    x, info, _ = G.gpu_solve(s)
+    assert info.status == 0
+    G.check(s, x, tag=f"m={m}")
+
+
+# --------------------------------------------------------------------------
+# ODE-BVP workloads
+def test_trapezoid_btri_small():
+    s = wl.trapezoid_bvp_btri(N=4096, m=8, seed=wl.seed_for(2, 1))
+    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=256))
+    _say(G.check(s, x, tag="trapezoid N=4096"))
+
+
+def test_trapezoid_btri_full():
+    """Block tridiagonal trapezoid BVP, N = 65536 steps, m = 8, 256 partitions."""
+    s = wl.trapezoid_bvp_btri(N=65536, m=8)
+    kap = G.kappa(s)
+    for p in (256, 0):
+        x, info, levels = G.gpu_solve(s, pf.make_opts(partitions=p))
+        assert info.status == 0
+        _say("trapezoid full p", p, levels, G.check(s, x, kap=kap, tag=f"full p={p}"))
+
+
+@pytest.mark.parametrize("m,nb", [(1, 9), (2, 3), (4, 40), (8, 101), (16, 1000), (8, 5)])
+def test_babd_random(m, nb):
+    s = wl.random_babd(nb, m, seed=600 + m + nb, nrhs=2)
+    x, info, levels = G.gpu_solve(s)
+    assert info.status == 0
+    G.check(s, x, tag=f"babd m={m} nb={nb} levels={levels}")
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 100, 0])
+def test_babd_trapezoid_small(p):
+    s = wl.trapezoid_babd(N=4096, m=16, seed=wl.seed_for(3, 1))
+    x, info, levels = G.gpu_solve(s, pf.make_opts(partitions=p))
+    assert info.status == 0
+    G.check(s, x, tag=f"babd N=4096 p={p}")
+
+
+def test_ivp_lower_bidiagonal():
+    """B1 = 0, B0 = I: the discrete IVP of Sec. 3 through the same path."""
+    s = wl.ivp_lower_bidiagonal(N=20000, m=4, seed=77)
+    x, info, _ = G.gpu_solve(s)
+    G.check(s, x, tag="ivp")
+
+
+def test_fp32_ir_babd_small():
+    s = wl.trapezoid_babd(N=4096, m=16, seed=wl.seed_for(3, 2))
+    x, info, _ = G.gpu_solve(s, pf.make_opts(prec=pf.PF_FP32_IR))
+    _say("fp32 ir", info.as_dict())
+    assert info.status == 0
+    assert info.eta <= 1e-12
+    G.check(s, x, tag="fp32ir")
+
+
+def test_fp32_ir_btri():
+    s = wl.random_btri(5000, 8, seed=88, nrhs=3)
+    x, info, _ = G.gpu_solve(s, pf.make_opts(prec=pf.PF_FP32_IR))
+    _say("fp32 ir btri", info.as_dict())
+    assert info.status == 0
+    G.check(s, x, tag="fp32ir btri")
+
+
+# --------------------------------------------------------------------------
+# error path: an exactly singular pivot block
+def test_singular_pivot_reported():
+    s = wl.random_btri(64, 4, seed=5)
+    s.D[0] = 0.0
+    s.Up[0] = 0.0
+    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=4))
+    assert info.status == pf.PF_ESINGULAR
+    assert info.bad_level == 0 and info.bad_block == 0
