@@ -114,6 +114,21 @@ typedef struct pf_factor_s *pf_factor_t;
  * or PF_EUNSUPPORTED. */
 int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t *out);
 
+/* Factor again, in the handle's memory, after the values of A's arrays
+ * changed (same pointers, same structure): the numeric refactorization of
+ * repeated solves (Newton steps, time stepping).  Allocates nothing.
+ * Returns 0 or PF_EHIP; numeric status as for pf_factor. */
+int pf_refactor(pf_factor_t F, void *stream);
+
+/* Per-kernel timing with HIP events recorded around every launch of the
+ * handle's factor and solve calls (on the stream they run on).  Off by
+ * default.  pf_profile_read synchronizes and returns the number of entries
+ * of the most recent factor/refactor and solve calls (up to max are copied):
+ * phase 0 = factor, 1 = forward sweep, 2 = back substitution; level = the
+ * recursion level; ms = the launch's duration. */
+int pf_profile_enable(pf_factor_t F, int enable);
+int pf_profile_read(pf_factor_t F, int32_t max, int32_t *phase, int32_t *level, float *ms);
+
 /* Solve A x = f with the factors (the F, T and G solves of Sec. 2: parallel
  * forward sweeps, the recursive reduced solve, parallel back substitution;
  * for PF_FP32_IR also the FP64 refinement loop).  f and x may be the same

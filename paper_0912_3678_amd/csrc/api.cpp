@@ -41,12 +41,23 @@ struct pf_factor_s {
     std::vector<void *> allocs;
     unsigned long long *d_status = nullptr;
     unsigned long long *d_norm = nullptr;  // ||A||_inf bits
+    void *d_dump = nullptr;                // target of masked stores (kDumpBytes)
     // solve workspace
     int rhs_cap = 0;
     std::vector<double *> wsF, wsFadd, wsY;
     double *wsPadF = nullptr, *wsPadX = nullptr, *wsR = nullptr, *wsD = nullptr;
     unsigned long long *d_norms = nullptr;
     std::vector<void *> ws_allocs;
+    // optional per-launch timing
+    struct ProfSlot {
+        int phase = 0, level = 0;
+        hipEvent_t a = nullptr, b = nullptr;
+    };
+    bool prof = false;
+    std::vector<ProfSlot> prof_fac, prof_sol;
+    size_t prof_fac_n = 0, prof_sol_n = 0;
+    // level-0 matrix padded to the instantiated block size (when M != m)
+    double *padD = nullptr, *padLo = nullptr, *padUp = nullptr, *padC = nullptr;
 };
 
 namespace {
@@ -184,6 +195,68 @@ int check_opts(const pf_matrix *A, const pf_opts &o)
         if (e_ != hipSuccess) return PF_EHIP;       \
     } while (0)
 
+// Run one launch, bracketed by HIP events on its stream when profiling.
+template <class Fn>
+hipError_t prof_launch(pf_factor_s *F, bool factor, int phase, int level, hipStream_t s, Fn fn)
+{
+    if (!F->prof) return fn();
+    auto &list = factor ? F->prof_fac : F->prof_sol;
+    size_t &n = factor ? F->prof_fac_n : F->prof_sol_n;
+    if (n >= list.size()) {
+        pf_factor_s::ProfSlot sl;
+        if (hipEventCreate(&sl.a) != hipSuccess || hipEventCreate(&sl.b) != hipSuccess)
+            return hipErrorOutOfMemory;
+        list.push_back(sl);
+    }
+    auto &sl = list[n++];
+    sl.phase = phase;
+    sl.level = level;
+    hipError_t e = hipEventRecord(sl.a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    return hipEventRecord(sl.b, s);
+}
+
+hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
+{
+    F->prof_fac_n = 0;
+    hipError_t e = launch_fill_u64(F->d_status, 1, ~0ull, s);
+    if (e != hipSuccess) return e;
+    if (F->M != F->m) {
+        const pf_matrix &A0 = F->A;
+        e = launch_pad_blocks(A0.m, F->M, A0.nb, A0.D, F->padD, 1.0, s);
+        if (e == hipSuccess) e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Lo, F->padLo, 0.0, s);
+        if (e == hipSuccess && F->padUp)
+            e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Up, F->padUp, 0.0, s);
+        if (e == hipSuccess && F->padC) e = launch_pad_blocks(A0.m, F->M, 1, A0.C, F->padC, 0.0, s);
+        if (e != hipSuccess) return e;
+    }
+    for (size_t l = 0; l < F->lv.size(); ++l) {
+        const Level &L = F->lv[l];
+        LevelArgs a{};
+        a.nb = L.nb; a.p = L.p;
+        a.D = L.D; a.Dadd = L.Dadd; a.Lo = L.Lo; a.Up = L.Up; a.C = L.C;
+        a.E = L.E; a.R = L.R; a.Z = L.Z; a.X = L.X;
+        a.nD = L.nD; a.nDadd = L.nDadd; a.nLo = L.nLo; a.nUp = L.nUp; a.nC = L.nC;
+        a.status = F->d_status;
+        a.dump = F->d_dump;
+        a.level = (int)l;
+        e = prof_launch(F, true, 0, (int)l, s, [&] {
+            return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
+                                       : launch_babd_factor(F->M, L.f32, a, s);
+        });
+        if (e != hipSuccess) return e;
+    }
+    const pf_matrix *A = &F->A;
+    if (F->opts.prec == PF_FP32_IR || (F->opts.flags & PF_FLAG_ETA)) {
+        e = launch_fill_u64(F->d_norm, 1, 0ull, s);
+        if (e != hipSuccess) return e;
+        e = launch_norminf(A->kind, A->m, A->nb, A->D, A->Lo, A->Up, A->C, F->d_norm, s);
+    }
+    return e;
+}
+
 int ensure_workspace(pf_factor_s *F, int nrhs)
 {
     if (nrhs <= F->rhs_cap) return 0;
@@ -247,6 +320,7 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
         SolveArgs &a = args[l];
         a = SolveArgs{};
         a.nb = lv.nb;
+        a.dump = (double *)F->d_dump;
         a.p = lv.p;
         a.nrhs = nrhs;
         a.Lo = lv.Lo;
@@ -269,15 +343,20 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
             a.ldn = 1;
         }
     }
+    F->prof_sol_n = 0;
     for (size_t l = 0; l < L; ++l) {
         const Level &lv = F->lv[l];
-        if (lv.kind == PF_BTRI) HIPCHK(launch_btri_fwd(M, lv.f32, args[l], s));
-        else HIPCHK(launch_babd_fwd(M, lv.f32, args[l], s));
+        HIPCHK(prof_launch(F, false, 1, (int)l, s, [&] {
+            return lv.kind == PF_BTRI ? launch_btri_fwd(M, lv.f32, args[l], s)
+                                      : launch_babd_fwd(M, lv.f32, args[l], s);
+        }));
     }
     for (size_t l = L; l-- > 0;) {
         const Level &lv = F->lv[l];
-        if (lv.kind == PF_BTRI) HIPCHK(launch_btri_bwd(M, lv.f32, args[l], s));
-        else HIPCHK(launch_babd_bwd(M, lv.f32, args[l], s));
+        HIPCHK(prof_launch(F, false, 2, (int)l, s, [&] {
+            return lv.kind == PF_BTRI ? launch_btri_bwd(M, lv.f32, args[l], s)
+                                      : launch_babd_bwd(M, lv.f32, args[l], s);
+        }));
     }
     if (M != F->m)
         HIPCHK(launch_pad_rhs(F->m, M, F->nb, nrhs, F->wsPadX, (int64_t)F->nb * M, x, ldx, false,
@@ -406,31 +485,28 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
         return fail(PF_ENOMEM);
     F->d_status = (unsigned long long *)p;
     F->d_norm = F->d_status + 1;
+    if (dalloc(F, &F->d_dump, kDumpBytes, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
     if (launch_fill_u64(F->d_status, 1, ~0ull, s) != hipSuccess) return fail(PF_EHIP);
     if (launch_fill_u64(F->d_norm, 1, 0ull, s) != hipSuccess) return fail(PF_EHIP);
 
-    // level-0 matrix (padded to an instantiated block size if needed)
+    // level-0 matrix (padded to an instantiated block size if needed; the
+    // padding itself runs in launch_factor_levels so refactor redoes it)
     const double *D0 = A->D, *Lo0 = A->Lo, *Up0 = A->Up, *C0 = A->C;
     if (M != A->m) {
         if (dalloc(F, &p, A->nb * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-        double *Dp = (double *)p;
+        F->padD = (double *)p;
         if (dalloc(F, &p, (A->nb - 1) * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-        double *Lp = (double *)p;
-        if (launch_pad_blocks(A->m, M, A->nb, A->D, Dp, 1.0, s) != hipSuccess) return fail(PF_EHIP);
-        if (launch_pad_blocks(A->m, M, A->nb - 1, A->Lo, Lp, 0.0, s) != hipSuccess)
-            return fail(PF_EHIP);
-        D0 = Dp;
-        Lo0 = Lp;
+        F->padLo = (double *)p;
+        D0 = F->padD;
+        Lo0 = F->padLo;
         if (A->kind == PF_BTRI) {
             if (dalloc(F, &p, (A->nb - 1) * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-            if (launch_pad_blocks(A->m, M, A->nb - 1, A->Up, (double *)p, 0.0, s) != hipSuccess)
-                return fail(PF_EHIP);
-            Up0 = (double *)p;
+            F->padUp = (double *)p;
+            Up0 = F->padUp;
         } else {
             if (dalloc(F, &p, bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-            if (launch_pad_blocks(A->m, M, 1, A->C, (double *)p, 0.0, s) != hipSuccess)
-                return fail(PF_EHIP);
-            C0 = (double *)p;
+            F->padC = (double *)p;
+            C0 = F->padC;
         }
     }
 
@@ -482,26 +558,43 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
             L.nC = (double *)p;
         }
     }
-    for (size_t l = 0; l < F->lv.size(); ++l) {
-        const Level &L = F->lv[l];
-        LevelArgs a{};
-        a.nb = L.nb; a.p = L.p;
-        a.D = L.D; a.Dadd = L.Dadd; a.Lo = L.Lo; a.Up = L.Up; a.C = L.C;
-        a.E = L.E; a.R = L.R; a.Z = L.Z; a.X = L.X;
-        a.nD = L.nD; a.nDadd = L.nDadd; a.nLo = L.nLo; a.nUp = L.nUp; a.nC = L.nC;
-        a.status = F->d_status;
-        a.level = (int)l;
-        hipError_t e = (L.kind == PF_BTRI) ? launch_btri_factor(M, L.f32, a, s)
-                                           : launch_babd_factor(M, L.f32, a, s);
-        if (e != hipSuccess) return fail(PF_EHIP);
-    }
-    if (o.prec == PF_FP32_IR || (o.flags & PF_FLAG_ETA)) {
-        if (launch_norminf(A->kind, A->m, A->nb, A->D, A->Lo, A->Up, A->C, F->d_norm, s) !=
-            hipSuccess)
-            return fail(PF_EHIP);
-    }
+    if (launch_factor_levels(F, s) != hipSuccess) return fail(PF_EHIP);
     *out = F;
     return 0;
+}
+
+int pf_refactor(pf_factor_t F, void *stream)
+{
+    if (!F) return -1;
+    hipStream_t s = stream ? (hipStream_t)stream : F->stream;
+    return launch_factor_levels(F, s) == hipSuccess ? 0 : PF_EHIP;
+}
+
+int pf_profile_enable(pf_factor_t F, int enable)
+{
+    if (!F) return -1;
+    F->prof = enable != 0;
+    return 0;
+}
+
+int pf_profile_read(pf_factor_t F, int32_t max, int32_t *phase, int32_t *level, float *ms)
+{
+    if (!F) return -1;
+    if (hipDeviceSynchronize() != hipSuccess) return PF_EHIP;
+    int n = 0;
+    for (int which = 0; which < 2; ++which) {
+        const auto &list = which == 0 ? F->prof_fac : F->prof_sol;
+        const size_t cnt = which == 0 ? F->prof_fac_n : F->prof_sol_n;
+        for (size_t i = 0; i < cnt; ++i, ++n) {
+            if (n >= max) continue;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, list[i].a, list[i].b) != hipSuccess) t = -1.f;
+            if (phase) phase[n] = list[i].phase;
+            if (level) level[n] = list[i].level;
+            if (ms) ms[n] = t;
+        }
+    }
+    return n;
 }
 
 int pf_sync_status(pf_factor_t F, pf_info *info)
@@ -581,6 +674,11 @@ void pf_destroy(pf_factor_t F)
     free_list(F, F->ws_allocs);
     free_list(F, F->allocs);
     hipStreamSynchronize(F->stream);
+    for (auto *list : {&F->prof_fac, &F->prof_sol})
+        for (auto &sl : *list) {
+            if (sl.a) hipEventDestroy(sl.a);
+            if (sl.b) hipEventDestroy(sl.b);
+        }
     delete F;
 }
 

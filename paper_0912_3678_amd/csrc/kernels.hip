@@ -18,8 +18,19 @@
 // through the group's own slice of LDS.  A group never leaves its wave, so
 // the only ordering needed between an LDS write and the reads of the other
 // lanes is the in-order LDS pipe of the wave plus a compiler fence
-// (wave_sync); no workgroup barrier is used, which keeps the global loads of
-// the next block row in flight across the whole step.
+// (wave_sync); no workgroup barrier is used.
+//
+// Memory discipline inside the chain loops: every load and store is issued
+// unconditionally (load indices are clamped to a valid block and the values
+// masked afterwards; stores of inactive iterations are redirected to a small
+// dump buffer) and the zero-pivot report is deferred to the end.  With no
+// memory operation under a branch, the compiler's wait counters stay exact:
+// a row waits for the loads it needs, never for the stores of earlier rows
+// (on this architecture stores and loads share one in-order counter).
+//
+// Factor storage: per block row g, column-major M x M blocks E (inverse of
+// the eliminated pivot block D'), X = E A(g,g+1), Zh (left spike column) and
+// R (left spike row) -- exactly the quantities the solve needs.
 //
 // Recurrences of one partition (global blocks g_1..g_n between the
 // separators sL = g_1 - 1 and sR = g_n + 1), block tridiagonal case:
@@ -118,27 +129,37 @@ __device__ __forceinline__ void add_vec(T (&v)[M], const double *__restrict__ p)
     for (int r = 0; r < M; ++r) v[r] += w[r];
 }
 
-// M contiguous T (factor storage) -> registers
+// registers -> M contiguous T (16-byte stores where the size allows)
 template <int M, typename T>
-__device__ __forceinline__ void ld_fac(T (&v)[M], const T *__restrict__ p)
+__device__ __forceinline__ void st_fac(T *__restrict__ p, const T (&v)[M])
 {
     if constexpr (sizeof(T) == 8 && M % 2 == 0) {
 #pragma unroll
-        for (int r = 0; r < M; r += 2) {
-            const double2 w = *reinterpret_cast<const double2 *>(p + r);
-            v[r] = w.x;
-            v[r + 1] = w.y;
-        }
+        for (int r = 0; r < M; r += 2)
+            *reinterpret_cast<double2 *>(p + r) = make_double2(v[r], v[r + 1]);
     } else if constexpr (sizeof(T) == 4 && M % 4 == 0) {
 #pragma unroll
-        for (int r = 0; r < M; r += 4) {
-            const float4 w = *reinterpret_cast<const float4 *>(p + r);
-            v[r] = w.x; v[r + 1] = w.y; v[r + 2] = w.z; v[r + 3] = w.w;
-        }
+        for (int r = 0; r < M; r += 4)
+            *reinterpret_cast<float4 *>(p + r) = make_float4(v[r], v[r + 1], v[r + 2], v[r + 3]);
     } else {
 #pragma unroll
-        for (int r = 0; r < M; ++r) v[r] = p[r];
+        for (int r = 0; r < M; ++r) p[r] = v[r];
     }
+}
+
+// row i of a column-major M x M block of T
+template <int M, typename T>
+__device__ __forceinline__ void ld_row(T (&v)[M], const T *__restrict__ blk, int i)
+{
+#pragma unroll
+    for (int l = 0; l < M; ++l) v[l] = blk[i + l * M];
+}
+
+template <int M, typename T>
+__device__ __forceinline__ void ld_row_d(T (&v)[M], const double *__restrict__ blk, int i)
+{
+#pragma unroll
+    for (int l = 0; l < M; ++l) v[l] = (T)blk[i + l * M];
 }
 
 template <int M, typename T>
@@ -146,6 +167,13 @@ __device__ __forceinline__ void zero(T (&v)[M])
 {
 #pragma unroll
     for (int r = 0; r < M; ++r) v[r] = T(0);
+}
+
+template <int M, typename T>
+__device__ __forceinline__ void mask(T (&v)[M], bool keep)
+{
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = keep ? v[r] : T(0);
 }
 
 // column j of an M x M LDS matrix (column-major) <- v
@@ -189,53 +217,49 @@ __device__ __forceinline__ void lds_gemv(const T *S, const T (&v)[M], T (&o)[M])
 
 // ---- Gauss-Jordan inversion of the pivot block with row partial pivoting --
 // Lane j holds column j of D' in d; on return e holds column j of D'^{-1}
-// and d the j-th unit column.  At step c the lane owning column c picks the
-// pivot row (first index of the largest magnitude among rows c..M-1) and
-// publishes its row-swapped column; every lane swaps the same two rows of
-// its own columns and eliminates column c above and below the pivot.
+// (d is consumed).  At step c every lane publishes its current column in the
+// group's LDS scratch SG and reads column c; the pivot is the first index of
+// the largest magnitude among rows c..M-1 of that column.  Every lane swaps
+// the same two rows of its own columns and eliminates column c above and
+// below the pivot.  Branch-free (selects only).  Returns true if a pivot was
+// exactly zero.
 template <int M, typename T>
-__device__ __forceinline__ void gj_invert(T (&d)[M], T (&e)[M], int j, T *sc, int *sp,
-                                          bool act, unsigned long long *status,
-                                          unsigned long long code)
+__device__ __forceinline__ bool gj_invert(T (&d)[M], T (&e)[M], int j, T *SG)
 {
+    bool sing = false;
 #pragma unroll
     for (int r = 0; r < M; ++r) e[r] = (r == j) ? T(1) : T(0);
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-        T *slot = sc + (c & 1) * M;
-        int *pslot = sp + (c & 1);
-        if (j == c) {
-            int pr = c;
-            T best = tabs(d[c]);
-            T dp = d[c];
-#pragma unroll
-            for (int r = c + 1; r < M; ++r) {
-                const T v = tabs(d[r]);
-                if (v > best) { best = v; pr = r; dp = d[r]; }
-            }
-            *pslot = pr;
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                T v = d[r];
-                if (r == c) v = dp;
-                else if (r > c && r == pr) v = d[c];
-                slot[r] = v;
-            }
-        }
+        lds_put_col<M, T>(SG, j, d);
         wave_sync();
-        const int pr = *pslot;
         T col[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) col[r] = slot[r];
+        for (int r = 0; r < M; ++r) col[r] = SG[r + c * M];
+        int pr = c;
+        T best = tabs(col[c]);
 #pragma unroll
         for (int r = c + 1; r < M; ++r) {
-            if (r == pr) {
-                T t = d[c]; d[c] = d[r]; d[r] = t;
-                t = e[c]; e[c] = e[r]; e[r] = t;
-            }
+            const T v = tabs(col[r]);
+            const bool gt = v > best;
+            best = gt ? v : best;
+            pr = gt ? r : pr;
+        }
+#pragma unroll
+        for (int r = c + 1; r < M; ++r) {
+            const bool sw = (r == pr);
+            T a0 = d[c], b0 = d[r];
+            d[c] = sw ? b0 : a0;
+            d[r] = sw ? a0 : b0;
+            a0 = e[c]; b0 = e[r];
+            e[c] = sw ? b0 : a0;
+            e[r] = sw ? a0 : b0;
+            a0 = col[c]; b0 = col[r];
+            col[c] = sw ? b0 : a0;
+            col[r] = sw ? a0 : b0;
         }
         const T pv = col[c];
-        if (act && pv == T(0) && j == 0) atomicMin(status, code);
+        sing = sing || (pv == T(0));
         const T inv = T(1) / pv;
         const T dc = d[c] * inv, ec = e[c] * inv;
 #pragma unroll
@@ -246,12 +270,15 @@ __device__ __forceinline__ void gj_invert(T (&d)[M], T (&e)[M], int j, T *sc, in
         }
         d[c] = dc;
         e[c] = ec;
+        wave_sync();
     }
+    return sing;
 }
 
 // ---------------------------------------------------------------------------
-// Block tridiagonal factor: one level.
-template <int M, typename T>
+// Block tridiagonal factor: one level.  ADD: the diagonal blocks are the sum
+// of two arrays (the two neighbours' contributions of the level above).
+template <int M, typename T, bool ADD>
 __global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
 {
     constexpr int GPW = WG / M;
@@ -259,20 +286,20 @@ __global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
     const int tid = threadIdx.x, grp = tid / M, j = tid % M;
     __shared__ __align__(16) T sA[GPW][M * M];
     __shared__ __align__(16) T sR[GPW][M * M];
-    __shared__ __align__(16) T sC[GPW][2 * M];
-    __shared__ int sP[GPW][2];
-    T *SA = sA[grp], *SR = sR[grp];
+    __shared__ __align__(16) T sG[GPW][M * M];
+    T *SA = sA[grp], *SR = sR[grp], *SG = sG[grp];
 
     const int64_t nb = a.nb;
     const int64_t part = (int64_t)blockIdx.x * GPW + grp;
     const Geo G = geometry<0>(nb, a.p, part);
     T *E = (T *)a.E, *R = (T *)a.R, *Zs = (T *)a.Z, *Xs = (T *)a.X;
+    T *dump = (T *)a.dump + tid * M;
 
     T d[M], z[M], rc[M], a1[M];
     zero<M, T>(d); zero<M, T>(z); zero<M, T>(rc); zero<M, T>(a1);
     if (G.valid) {
         ld_vec<M, T>(d, a.D + G.start * MM + j * M);
-        if (a.Dadd) add_vec<M, T>(d, a.Dadd + G.start * MM + j * M);
+        if constexpr (ADD) add_vec<M, T>(d, a.Dadd + G.start * MM + j * M);
     }
     if (G.hasL) {
         ld_vec<M, T>(z, a.Lo + (G.start - 1) * MM + j * M);   // A(g_1, sL)
@@ -280,52 +307,42 @@ __global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
     }
     lds_put_col<M, T>(SR, j, rc);
     wave_sync();
+    unsigned long long bad = ~0ull;
 
     for (int k = 0; k < G.kmax; ++k) {
         const bool act = k < G.len;
         const int64_t g = G.start + k;
         const bool nxt = act && (g + 1 < nb);
+        const int64_t gl = nxt ? g : 0, gd = nxt ? g + 1 : 0;
         T up[M], lo[M], dn[M];
-        zero<M, T>(up); zero<M, T>(lo); zero<M, T>(dn);
-        if (nxt) {
-            ld_vec<M, T>(up, a.Up + g * MM + j * M);
-            ld_vec<M, T>(lo, a.Lo + g * MM + j * M);
-            ld_vec<M, T>(dn, a.D + (g + 1) * MM + j * M);
-            if (a.Dadd) add_vec<M, T>(dn, a.Dadd + (g + 1) * MM + j * M);
-        }
-        // Gauss-Jordan consumes its input, and d must survive the trailing
-        // iterations of a partition shorter than kmax: invert a copy.
+        ld_vec<M, T>(up, a.Up + gl * MM + j * M);
+        ld_vec<M, T>(lo, a.Lo + gl * MM + j * M);
+        ld_vec<M, T>(dn, a.D + gd * MM + j * M);
+        if constexpr (ADD) add_vec<M, T>(dn, a.Dadd + gd * MM + j * M);
+        mask<M, T>(up, nxt);
+        mask<M, T>(lo, nxt);
+        mask<M, T>(dn, nxt);
+
         T e[M], dw[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) dw[r] = d[r];
-        gj_invert<M, T>(dw, e, j, sC[grp], sP[grp], act, a.status, status_code(a.level, g));
-        if (act) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) E[g * MM + r * M + j] = e[r];
-        }
+        const bool sing = gj_invert<M, T>(dw, e, j, SG);
+        const unsigned long long code = status_code(a.level, g);
+        bad = (act && sing && code < bad) ? code : bad;
+        st_fac<M, T>(act ? E + g * MM + j * M : dump, e);
         lds_put_col<M, T>(SA, j, e);
         wave_sync();
         T x[M], zh[M];
         lds_gemv2<M, T>(SA, up, z, x, zh);          // X_k, Zh_k
-        if (act) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                Xs[g * MM + r * M + j] = x[r];
-                Zs[g * MM + r * M + j] = zh[r];
-            }
-        }
+        st_fac<M, T>(act ? Xs + g * MM + j * M : dump, x);
+        st_fac<M, T>(act ? Zs + g * MM + j * M : dump, zh);
         T t1[M], rn[M];
         lds_gemv2<M, T>(SR, zh, x, t1, rn);         // R_k Zh_k, R_k X_k
-        if (act) {
-            if (G.hasL) {
+        st_fac<M, T>((act && G.hasL) ? R + g * MM + j * M : dump, rc);
 #pragma unroll
-                for (int r = 0; r < M; ++r) R[g * MM + r * M + j] = rc[r];
-            }
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                a1[r] -= t1[r];
-                rc[r] = -rn[r];
-            }
+        for (int r = 0; r < M; ++r) {
+            a1[r] = act ? a1[r] - t1[r] : a1[r];
+            rc[r] = act ? -rn[r] : rc[r];
         }
         wave_sync();
         lds_put_col<M, T>(SR, j, rc);
@@ -333,15 +350,14 @@ __global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
         wave_sync();
         T dl[M], zl[M];
         lds_gemv2<M, T>(SA, x, zh, dl, zl);         // Lo X_k, Lo Zh_k
-        if (act) {
 #pragma unroll
-            for (int r = 0; r < M; ++r) {
-                d[r] = dn[r] - dl[r];
-                z[r] = -zl[r];
-            }
+        for (int r = 0; r < M; ++r) {
+            d[r] = act ? dn[r] - dl[r] : d[r];
+            z[r] = act ? -zl[r] : z[r];
         }
         wave_sync();
     }
+    if (bad != ~0ull) atomicMin(a.status, bad);
     // contributions to the reduced matrix (eq. (redmatr)); separator j sits
     // between partitions j and j+1
     if (G.hasR) {
@@ -378,52 +394,46 @@ __global__ __launch_bounds__(WG) void k_babd_factor(LevelArgs a)
     constexpr size_t MM = (size_t)M * M;
     const int tid = threadIdx.x, grp = tid / M, j = tid % M;
     __shared__ __align__(16) T sA[GPW][M * M];
-    __shared__ __align__(16) T sC[GPW][2 * M];
-    __shared__ int sP[GPW][2];
-    T *SA = sA[grp];
+    __shared__ __align__(16) T sG[GPW][M * M];
+    T *SA = sA[grp], *SG = sG[grp];
 
     const int64_t part = (int64_t)blockIdx.x * GPW + grp;
     const Geo G = geometry<1>(a.nb, a.p, part);
     T *E = (T *)a.E, *Zs = (T *)a.Z;
+    T *dump = (T *)a.dump + tid * M;
 
     T z[M];
     zero<M, T>(z);
     if (G.valid) ld_vec<M, T>(z, a.Lo + (G.start - 1) * MM + j * M);   // A(g_1, sL)
+    unsigned long long bad = ~0ull;
 
     for (int k = 0; k < G.kmax; ++k) {
         const bool act = k < G.len;
         const int64_t g = G.start + k;
+        const int64_t gc = act ? g : 0;
         T d[M], lo[M];
-        zero<M, T>(d); zero<M, T>(lo);
-        if (act) {
-            ld_vec<M, T>(d, a.D + g * MM + j * M);
-            ld_vec<M, T>(lo, a.Lo + g * MM + j * M);                    // A(g+1, g)
-        }
+        ld_vec<M, T>(d, a.D + gc * MM + j * M);
+        ld_vec<M, T>(lo, a.Lo + gc * MM + j * M);                      // A(g+1, g)
         T e[M];
-        gj_invert<M, T>(d, e, j, sC[grp], sP[grp], act, a.status, status_code(a.level, g));
-        if (act) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) E[g * MM + r * M + j] = e[r];
-        }
+        const bool sing = gj_invert<M, T>(d, e, j, SG);
+        const unsigned long long code = status_code(a.level, g);
+        bad = (act && sing && code < bad) ? code : bad;
+        st_fac<M, T>(act ? E + g * MM + j * M : dump, e);
         lds_put_col<M, T>(SA, j, e);
         wave_sync();
         T zh[M];
         lds_gemv<M, T>(SA, z, zh);                  // Zh_k = E_k Z'_k
-        if (act) {
-#pragma unroll
-            for (int r = 0; r < M; ++r) Zs[g * MM + r * M + j] = zh[r];
-        }
+        st_fac<M, T>(act ? Zs + g * MM + j * M : dump, zh);
         wave_sync();
         lds_put_col<M, T>(SA, j, lo);
         wave_sync();
         T zl[M];
         lds_gemv<M, T>(SA, zh, zl);                 // A(g+1,g) Zh_k
-        if (act) {
 #pragma unroll
-            for (int r = 0; r < M; ++r) z[r] = -zl[r];
-        }
+        for (int r = 0; r < M; ++r) z[r] = act ? -zl[r] : z[r];
         wave_sync();
     }
+    if (bad != ~0ull) atomicMin(a.status, bad);
     if (G.valid) {
         const int64_t sR = G.start + G.len;
         double *ob = a.nLo + part * MM + j * M;
@@ -447,8 +457,9 @@ __global__ __launch_bounds__(WG) void k_babd_factor(LevelArgs a)
 
 // ---------------------------------------------------------------------------
 // Forward sweep of a solve (the F solve): t_k and the reduced right-hand side.
-// Lane i owns row i of KC right-hand-side columns.
-template <int KIND, int M, int KC, typename T>
+// Lane i owns row i of KC right-hand-side columns.  ADD: the right-hand side
+// is the sum of two arrays (reduced levels of block tridiagonal matrices).
+template <int KIND, int M, int KC, typename T, bool ADD>
 __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
 {
     constexpr int GPW = WG / M;
@@ -461,6 +472,11 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
     const int c0 = blockIdx.y * KC;
     const int kc = (a.nrhs - c0) < KC ? (a.nrhs - c0) : KC;
     const T *E = (const T *)a.E, *R = (const T *)a.R;
+    double *dump = a.dump + tid;
+
+    int64_t col[KC];   // column offsets, clamped to existing columns
+#pragma unroll
+    for (int c = 0; c < KC; ++c) col[c] = (int64_t)(c0 + (c < kc ? c : kc - 1));
 
     T fp[KC], gl[KC];
 #pragma unroll
@@ -468,9 +484,8 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
         fp[c] = T(0);
         gl[c] = T(0);
         if (G.valid && c < kc) {
-            const int64_t idx = G.start * M + i + (c0 + c) * a.ldf;
-            double v = a.F[idx];
-            if (a.Fadd) v += a.Fadd[G.start * M + i + (c0 + c) * a.ldf];
+            double v = a.F[G.start * M + i + col[c] * a.ldf];
+            if constexpr (ADD) v += a.Fadd[G.start * M + i + col[c] * a.ldf];
             fp[c] = (T)v;
         }
     }
@@ -478,25 +493,20 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
         const bool act = k < G.len;
         const int64_t g = G.start + k;
         const bool nxt = act && (g + 1 < a.nb);
+        const int64_t ge = act ? g : 0, gn = nxt ? g : 0;
         T er[M], lr[M], rr[M], fn[KC];
-        zero<M, T>(er); zero<M, T>(lr); zero<M, T>(rr);
-        if (act) {
-            ld_fac<M, T>(er, E + g * MM + i * M);
-            if (KIND == 0 && G.hasL) ld_fac<M, T>(rr, R + g * MM + i * M);
+        ld_row<M, T>(er, E + ge * MM, i);
+        ld_row_d<M, T>(lr, a.Lo + gn * MM, i);
+        if constexpr (KIND == 0) {
+            ld_row<M, T>(rr, R + ((act && G.hasL) ? g : 0) * MM, i);
+            mask<M, T>(rr, act && G.hasL);
         }
+        mask<M, T>(lr, nxt);
 #pragma unroll
-        for (int c = 0; c < KC; ++c) fn[c] = T(0);
-        if (nxt) {
-#pragma unroll
-            for (int l = 0; l < M; ++l) lr[l] = (T)a.Lo[g * MM + i + l * M];
-#pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                if (c < kc) {
-                    double v = a.F[(g + 1) * M + i + (c0 + c) * a.ldf];
-                    if (a.Fadd) v += a.Fadd[(g + 1) * M + i + (c0 + c) * a.ldf];
-                    fn[c] = (T)v;
-                }
-            }
+        for (int c = 0; c < KC; ++c) {
+            double v = a.F[(gn + (nxt ? 1 : 0)) * M + i + col[c] * a.ldf];
+            if constexpr (ADD) v += a.Fadd[(gn + (nxt ? 1 : 0)) * M + i + col[c] * a.ldf];
+            fn[c] = nxt ? (T)v : T(0);
         }
 #pragma unroll
         for (int c = 0; c < KC; ++c) SV[i + c * M] = fp[c];
@@ -510,10 +520,10 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
             t[c] = s;
         }
         wave_sync();
-        if (act) {
 #pragma unroll
-            for (int c = 0; c < KC; ++c)
-                if (c < kc) a.Y[g * M + i + (c0 + c) * a.ldy] = (double)t[c];
+        for (int c = 0; c < KC; ++c) {
+            double *dst = (act && c < kc) ? a.Y + g * M + i + col[c] * a.ldy : dump;
+            *dst = (double)t[c];
         }
 #pragma unroll
         for (int c = 0; c < KC; ++c) SV[i + c * M] = t[c];
@@ -525,25 +535,23 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
             for (int l = 0; l < M; ++l) {
                 const T tv = SV[l + c * M];
                 sl = fma(lr[l], tv, sl);
-                if (KIND == 0) sr = fma(rr[l], tv, sr);
+                if constexpr (KIND == 0) sr = fma(rr[l], tv, sr);
             }
-            if (act) {
-                fp[c] = fn[c] - sl;
-                if (KIND == 0) gl[c] -= sr;
-            }
+            fp[c] = act ? fn[c] - sl : fp[c];
+            if constexpr (KIND == 0) gl[c] = act ? gl[c] - sr : gl[c];
         }
         wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
         if (c >= kc) continue;
-        const int64_t col = (int64_t)(c0 + c) * a.ldn;
+        const int64_t cn = col[c] * a.ldn;
         if (KIND == 0) {
-            if (G.hasR) a.nF[part * M + i + col] = (double)fp[c];
-            if (G.hasL) a.nFadd[(part - 1) * M + i + col] = (double)gl[c];
+            if (G.hasR) a.nF[part * M + i + cn] = (double)fp[c];
+            if (G.hasL) a.nFadd[(part - 1) * M + i + cn] = (double)gl[c];
         } else if (G.valid) {
-            a.nF[(part + 1) * M + i + col] = (double)fp[c];
-            if (part == 0) a.nF[i + col] = a.F[i + (int64_t)(c0 + c) * a.ldf];
+            a.nF[(part + 1) * M + i + cn] = (double)fp[c];
+            if (part == 0) a.nF[i + cn] = a.F[i + col[c] * a.ldf];
         }
     }
 }
@@ -564,24 +572,28 @@ __global__ __launch_bounds__(WG) void k_bwd(SolveArgs a)
     const int c0 = blockIdx.y * KC;
     const int kc = (a.nrhs - c0) < KC ? (a.nrhs - c0) : KC;
     const T *Zs = (const T *)a.Z, *Xs = (const T *)a.X;
+    double *dump = a.dump + tid;
     const int64_t sR = G.start + G.len;
     // reduced-solution indices of the two separators
     const int64_t jl = (KIND == 0) ? part - 1 : part;
     const int64_t jr = (KIND == 0) ? part : part + 1;
 
+    int64_t col[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) col[c] = (int64_t)(c0 + (c < kc ? c : kc - 1));
+
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
         T xl = T(0), xr = T(0);
         if (c < kc) {
-            const int64_t col = (int64_t)(c0 + c) * a.ldn;
-            if (G.hasL) xl = (T)a.Xsep[jl * M + i + col];
+            const int64_t cn = col[c] * a.ldn;
+            if (G.hasL) xl = (T)a.Xsep[jl * M + i + cn];
             if (G.hasR) {
-                const double v = a.Xsep[jr * M + i + col];
+                const double v = a.Xsep[jr * M + i + cn];
                 xr = (T)v;
-                a.Y[sR * M + i + (int64_t)(c0 + c) * a.ldy] = v;
+                a.Y[sR * M + i + col[c] * a.ldy] = v;
             }
-            if (KIND == 1 && G.valid && part == 0)
-                a.Y[i + (int64_t)(c0 + c) * a.ldy] = a.Xsep[i + col];
+            if (KIND == 1 && G.valid && part == 0) a.Y[i + col[c] * a.ldy] = a.Xsep[i + cn];
         }
         SL[i + c * M] = xl;
         SV[i + c * M] = xr;
@@ -590,17 +602,12 @@ __global__ __launch_bounds__(WG) void k_bwd(SolveArgs a)
     for (int k = G.kmax - 1; k >= 0; --k) {
         const bool act = k < G.len;
         const int64_t g = G.start + k;
+        const int64_t ge = act ? g : 0;
         T zr[M], xrw[M], t[KC];
-        zero<M, T>(zr); zero<M, T>(xrw);
+        ld_row<M, T>(zr, Zs + ge * MM, i);
+        if constexpr (KIND == 0) ld_row<M, T>(xrw, Xs + ge * MM, i);
 #pragma unroll
-        for (int c = 0; c < KC; ++c) t[c] = T(0);
-        if (act) {
-            ld_fac<M, T>(zr, Zs + g * MM + i * M);
-            if (KIND == 0) ld_fac<M, T>(xrw, Xs + g * MM + i * M);
-#pragma unroll
-            for (int c = 0; c < KC; ++c)
-                if (c < kc) t[c] = (T)a.Y[g * M + i + (int64_t)(c0 + c) * a.ldy];
-        }
+        for (int c = 0; c < KC; ++c) t[c] = (T)a.Y[ge * M + i + col[c] * a.ldy];
         T xk[KC];
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
@@ -608,25 +615,20 @@ __global__ __launch_bounds__(WG) void k_bwd(SolveArgs a)
 #pragma unroll
             for (int l = 0; l < M; ++l) {
                 s = fma(-zr[l], SL[l + c * M], s);
-                if (KIND == 0) s = fma(-xrw[l], SV[l + c * M], s);
+                if constexpr (KIND == 0) s = fma(-xrw[l], SV[l + c * M], s);
             }
             xk[c] = s;
         }
-        if (KIND == 0) wave_sync();
-        if (act) {
+        if constexpr (KIND == 0) wave_sync();
 #pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                if (c < kc) a.Y[g * M + i + (int64_t)(c0 + c) * a.ldy] = (double)xk[c];
-                if (KIND == 0) SV[i + c * M] = xk[c];
-            }
+        for (int c = 0; c < KC; ++c) {
+            double *dst = (act && c < kc) ? a.Y + g * M + i + col[c] * a.ldy : dump;
+            *dst = (double)xk[c];
+            if constexpr (KIND == 0) SV[i + c * M] = act ? xk[c] : SV[i + c * M];
         }
-        if (KIND == 0) wave_sync();
+        if constexpr (KIND == 0) wave_sync();
     }
 }
-
-template <int M> struct IsSupported { static constexpr bool value = (M == 1 || M == 2 || M == 4 || M == 8 || M == 16 || M == 32); };
-
-inline int groups_per_wg(int M) { return WG / M; }
 
 template <typename F>
 hipError_t dispatch_M(int M, F &&f)
@@ -644,7 +646,7 @@ hipError_t dispatch_M(int M, F &&f)
 
 inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)
 {
-    const int64_t gpw = groups_per_wg(M);
+    const int64_t gpw = WG / M;
     return dim3((unsigned)((p + gpw - 1) / gpw), (unsigned)((nrhs + KC - 1) / KC), 1);
 }
 
@@ -655,8 +657,13 @@ hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
         const dim3 grid = grid_for(MV, a.p, 1, 1);
-        if (f32) hipLaunchKernelGGL((k_btri_factor<MV, float>), grid, dim3(WG), 0, s, a);
-        else hipLaunchKernelGGL((k_btri_factor<MV, double>), grid, dim3(WG), 0, s, a);
+        if (a.Dadd) {
+            if (f32) hipLaunchKernelGGL((k_btri_factor<MV, float, true>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_btri_factor<MV, double, true>), grid, dim3(WG), 0, s, a);
+        } else {
+            if (f32) hipLaunchKernelGGL((k_btri_factor<MV, float, false>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_btri_factor<MV, double, false>), grid, dim3(WG), 0, s, a);
+        }
         return hipGetLastError();
     });
 }
@@ -672,6 +679,15 @@ hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
     });
 }
 
+template <int KIND, int M, int KC, typename T>
+static void launch_fwd_kernel(const SolveArgs &a, dim3 grid, hipStream_t s)
+{
+    if (KIND == 0 && a.Fadd)
+        hipLaunchKernelGGL((k_fwd<KIND, M, KC, T, true>), grid, dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_fwd<KIND, M, KC, T, false>), grid, dim3(WG), 0, s, a);
+}
+
 template <int KIND, bool FWD>
 static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t s)
 {
@@ -680,8 +696,8 @@ static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t 
         if (a.nrhs == 1) {
             const dim3 grid = grid_for(MV, a.p, a.nrhs, 1);
             if (FWD) {
-                if (f32) hipLaunchKernelGGL((k_fwd<KIND, MV, 1, float>), grid, dim3(WG), 0, s, a);
-                else hipLaunchKernelGGL((k_fwd<KIND, MV, 1, double>), grid, dim3(WG), 0, s, a);
+                if (f32) launch_fwd_kernel<KIND, MV, 1, float>(a, grid, s);
+                else launch_fwd_kernel<KIND, MV, 1, double>(a, grid, s);
             } else {
                 if (f32) hipLaunchKernelGGL((k_bwd<KIND, MV, 1, float>), grid, dim3(WG), 0, s, a);
                 else hipLaunchKernelGGL((k_bwd<KIND, MV, 1, double>), grid, dim3(WG), 0, s, a);
@@ -689,8 +705,8 @@ static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t 
         } else {
             const dim3 grid = grid_for(MV, a.p, a.nrhs, 4);
             if (FWD) {
-                if (f32) hipLaunchKernelGGL((k_fwd<KIND, MV, 4, float>), grid, dim3(WG), 0, s, a);
-                else hipLaunchKernelGGL((k_fwd<KIND, MV, 4, double>), grid, dim3(WG), 0, s, a);
+                if (f32) launch_fwd_kernel<KIND, MV, 4, float>(a, grid, s);
+                else launch_fwd_kernel<KIND, MV, 4, double>(a, grid, s);
             } else {
                 if (f32) hipLaunchKernelGGL((k_bwd<KIND, MV, 4, float>), grid, dim3(WG), 0, s, a);
                 else hipLaunchKernelGGL((k_bwd<KIND, MV, 4, double>), grid, dim3(WG), 0, s, a);

@@ -28,8 +28,13 @@ struct LevelArgs {
     double *nUp;           // next level: super-diagonal blocks (BTRI)
     double *nC;            // next level: corner (BABD)
     unsigned long long *status;  // packed (level << 40 | block); atomicMin
+    void *dump;            // kDumpBytes of scratch that masked stores write into
     int level;
 };
+
+// Device scratch that receives the stores of inactive loop iterations (the
+// kernels keep every memory operation of a chain loop unconditional).
+constexpr size_t kDumpBytes = 64 * 1024;
 
 // One level of a solve.
 struct SolveArgs {
@@ -46,6 +51,7 @@ struct SolveArgs {
     double *nFadd;
     int64_t ldn;
     const double *Xsep;    // backward: next level's solution (ld ldn)
+    double *dump;          // kDumpBytes of scratch for masked stores
 };
 
 // Launchers (kernels.hip).  M must be 1, 2, 4, 8, 16 or 32.

@@ -22,7 +22,7 @@ EXPORTED = [
     "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",
     "pf_sync_status", "pf_destroy", "pf_strerror", "pf_factor_levels", "pf_factor_level",
     "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
-    "pf_plan",
+    "pf_plan", "pf_refactor", "pf_profile_enable", "pf_profile_read",
 ]
 
 
@@ -72,6 +72,9 @@ def load(path: str = LIB_PATH):
         "pf_destroy": (None, [vp]),
         "pf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "pf_factor_levels": (ctypes.c_int, [vp]),
+        "pf_refactor": (ctypes.c_int, [vp, vp]),
+        "pf_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+        "pf_profile_read": (ctypes.c_int, [vp, i32, P(i32), P(i32), P(ctypes.c_float)]),
         "pf_plan": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, P(i32), P(i64), P(i64)]),
         "pf_factor_level": (ctypes.c_int, [vp, ctypes.c_int, P(i32), P(i64), P(i64)]),
         "pf_factor_block_size": (ctypes.c_int, [vp]),
@@ -144,6 +147,32 @@ def pf_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_info=True
     if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
         raise PFError(rc, "pf_solve")
     return info
+
+
+def pf_refactor(F, stream=None):
+    rc = load().pf_refactor(F, _stream(stream))
+    if rc != 0:
+        raise PFError(rc, "pf_refactor")
+
+
+def pf_profile_enable(F, on=True):
+    load().pf_profile_enable(F, 1 if on else 0)
+
+
+PHASES = {0: "factor", 1: "forward", 2: "backward"}
+
+
+def pf_profile_read(F):
+    """[(phase name, level, ms)] of the latest factor/refactor and solve."""
+    lib = load()
+    n = 256
+    ph = (ctypes.c_int32 * n)()
+    lv = (ctypes.c_int32 * n)()
+    ms = (ctypes.c_float * n)()
+    cnt = lib.pf_profile_read(F, n, ph, lv, ms)
+    if cnt < 0:
+        raise PFError(cnt, "pf_profile_read")
+    return [(PHASES[ph[i]], lv[i], float(ms[i])) for i in range(min(cnt, n))]
 
 
 def pf_sync_status(F) -> pf_info:
