@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--m", type=int, default=8)
     ap.add_argument("--partitions", type=int, default=0, help="finest-level p (0 = planner)")
     ap.add_argument("--block-rows", type=int, default=0)
+    ap.add_argument("--coarse-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=10)
@@ -107,7 +108,8 @@ def main():
     f = wl.to_device_rhs(s.f, dev)
     x = torch.empty_like(f)
     A = pf.make_matrix(pf.PF_BTRI, m, nb, D, Lo, Up)
-    opts = pf.make_opts(partitions=args.partitions, block_rows=args.block_rows)
+    opts = pf.make_opts(partitions=args.partitions, block_rows=args.block_rows,
+                        coarse_rows=args.coarse_rows)
     F = pf.pf_factor(A, opts)
     levels = pf.pf_factor_levels(F)
     torch.cuda.synchronize()

@@ -88,7 +88,7 @@ typedef struct {
     int32_t block_rows; /* blocks per partition at the finest level when
                            partitions == 0; 0 = autotuned table               */
     int32_t flags;      /* PF_FLAG_*                                          */
-    int32_t reserved;
+    int32_t coarse_rows;/* blocks per partition on the reduced levels; 0 = table */
     double tol;         /* PF_FP32_IR target eta; <= 0 means 1e-12            */
 } pf_opts;
 
@@ -138,14 +138,45 @@ int pf_profile_read(pf_factor_t F, int32_t max, int32_t *phase, int32_t *level, 
 int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
              int64_t ldx, void *stream, pf_info *info);
 
-/* Factor and solve nsys independent systems.  All systems that share a block
- * size run in the same kernel launches (one launch per level and phase per
- * block size), and the whole sequence is recorded once into a HIP graph that
- * is replayed for the batch.  A, nrhs, f, ldf, x, ldx are HOST arrays of
- * length nsys whose elements describe device buffers.  If factors != NULL,
- * factors[i] receives a handle for system i that the caller destroys;
- * otherwise the factors are released before returning.  info (nsys entries,
- * may be NULL) receives per-system status; the call synchronizes `stream`. */
+/* ---- batches of independent systems ---------------------------------------
+ * The partitions of many systems run side by side: every system's
+ * per-partition work of one level and phase goes into one kernel launch per
+ * launch variant (kind, block size, precision), the partitions of all
+ * systems spread over the workgroups of that launch.  The factor and solve
+ * sequence of the whole batch is recorded once into a HIP graph and replayed.
+ *
+ * pf_batch_create: A, nrhs, f, ldf, x, ldx are HOST arrays of nsys entries
+ * describing DEVICE buffers (layouts as for pf_factor / pf_solve; nrhs[i] may
+ * be 0).  The batch keeps these pointers: pf_batch_run factors every A[i] as
+ * it is at that moment and solves into x[i] from f[i], so the caller may
+ * change the values (not the pointers) between runs.  One device allocation
+ * holds all factors and workspaces.  Synchronizes `stream` once.  Returns 0,
+ * -k for invalid argument k, PF_ENOMEM, PF_EHIP or PF_EUNSUPPORTED. */
+typedef struct pf_batch_s *pf_batch_t;
+int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts,
+                    const int32_t *nrhs, const double *const *f, const int64_t *ldf,
+                    double *const *x, const int64_t *ldx, void *stream, pf_batch_t *out);
+
+/* Replay the batch after the work queued so far on `stream`; later work on
+ * `stream` sees the solutions.  With info == NULL and PF_FP64 the call is
+ * asynchronous; otherwise it synchronizes and fills info[0..nsys) per system
+ * (PF_FP32_IR refines every system of the batch together until each meets
+ * tol or stops converging).  Returns 0 or the first nonzero per-system
+ * status.  Runs of one batch must not overlap. */
+int pf_batch_run(pf_batch_t B, void *stream, pf_info *info);
+
+/* Hand out the factor of system i as a handle (pf_solve, pf_refactor,
+ * pf_destroy work on it); each system can be handed out once.  The handle
+ * shares the batch's allocation, which lives until the batch and every
+ * handed-out handle are destroyed. */
+int pf_batch_factor(pf_batch_t B, int32_t i, pf_factor_t *out);
+
+/* Release the batch (synchronizes its internal stream). */
+void pf_batch_destroy(pf_batch_t B);
+
+/* One-shot batch: create, run, optionally hand out every factor
+ * (factors != NULL: factors[i] for the caller to destroy), destroy.
+ * Synchronizes `stream`. */
 int pf_solve_batch(int32_t nsys, const pf_matrix *A, const pf_opts *opts,
                    const int32_t *nrhs, const double *const *f, const int64_t *ldf,
                    double *const *x, const int64_t *ldx, void *stream,

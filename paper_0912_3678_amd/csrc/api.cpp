@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 using namespace pf;
@@ -29,6 +31,23 @@ struct PlanLevel {
     int64_t nb, p;
 };
 
+// One device allocation carved into the memory of many handles (a batch).
+// Shared by the batch and by the handles it hands out; freed by the last.
+struct Arena {
+    char *base = nullptr;
+    size_t off = 0, cap = 0;
+    bool counting = false;
+    int refs = 0;
+};
+
+void arena_release(Arena *ar, hipStream_t s)
+{
+    if (--ar->refs > 0) return;
+    hipStreamSynchronize(s);
+    if (ar->base) hipFree(ar->base);
+    delete ar;
+}
+
 }  // namespace
 
 struct pf_factor_s {
@@ -42,6 +61,7 @@ struct pf_factor_s {
     unsigned long long *d_status = nullptr;
     unsigned long long *d_norm = nullptr;  // ||A||_inf bits
     void *d_dump = nullptr;                // target of masked stores (kDumpBytes)
+    const double *d_zero = nullptr;        // kZeroBytes of zeros after the dump area
     // solve workspace
     int rhs_cap = 0;
     std::vector<double *> wsF, wsFadd, wsY;
@@ -58,6 +78,8 @@ struct pf_factor_s {
     size_t prof_fac_n = 0, prof_sol_n = 0;
     // level-0 matrix padded to the instantiated block size (when M != m)
     double *padD = nullptr, *padLo = nullptr, *padUp = nullptr, *padC = nullptr;
+    // set when the handle's memory is a slice of a batch's arena
+    Arena *arena = nullptr;
 };
 
 namespace {
@@ -72,12 +94,16 @@ int padded_block(int m)
 // Blocks per partition (the chain length of one group of lanes).  Short
 // chains give many partitions (parallelism, latency hiding); the reduced
 // system then has about nb/(L+1) blocks and is solved by the next level.
-int target_rows(int M, bool f32, int level, int user)
+int target_rows(int M, bool f32, int level, const pf_opts &o)
 {
-    if (level == 0 && user > 0) return user;
+    if (level == 0 && o.block_rows > 0) return o.block_rows;
+    if (level > 0 && o.coarse_rows > 0) return o.coarse_rows;
     (void)f32;
+    // measured on MI355X for the m = 8 BVP: 8 blocks at level 0 and 3 on the
+    // reduced levels (latency-bound there: the chain length per level trades
+    // against the number of levels)
     if (level == 0) return M <= 4 ? 16 : (M <= 8 ? 8 : 4);
-    return 4;
+    return 3;
 }
 
 constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chain
@@ -93,7 +119,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
             int64_t p;
             if (lvl == 0 && o.partitions > 0) p = o.partitions;
             else {
-                const int L = target_rows(M, f32, lvl, o.block_rows);
+                const int L = target_rows(M, f32, lvl, o);
                 p = (cur - 1) / (L + 1);
                 p = std::max<int64_t>(p, 1);
                 p = std::min<int64_t>(p, (cur - 1) / 2);
@@ -110,7 +136,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
         if (lvl == 0 && o.partitions > 0) p = o.partitions;
         else if (cur <= kTail) p = 1;
         else {
-            const int L = target_rows(M, f32, lvl, o.block_rows);
+            const int L = target_rows(M, f32, lvl, o);
             p = (cur + 1) / (L + 1);
             p = std::max<int64_t>(p, 2);
             p = std::min<int64_t>(p, (cur + 1) / 2);
@@ -142,10 +168,22 @@ size_t plan_bytes(const std::vector<PlanLevel> &plan, int M, int m, const pf_opt
     return b + 256;
 }
 
+// Device memory of a handle: stream-ordered allocations of its own, or
+// 256-byte aligned slices of a batch's arena.  A counting arena only adds up
+// sizes (the pointers it hands out are never dereferenced: no launch happens
+// while counting).
 hipError_t dalloc(pf_factor_s *F, void **p, size_t bytes, std::vector<void *> &list)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 8;
+    if (F->arena) {
+        Arena &ar = *F->arena;
+        const size_t off = (ar.off + 255) & ~(size_t)255;
+        if (!ar.counting && off + bytes > ar.cap) return hipErrorOutOfMemory;
+        *p = ar.counting ? (void *)(uintptr_t)(4096 + off) : (void *)(ar.base + off);
+        ar.off = off + bytes;
+        return hipSuccess;
+    }
     hipError_t e = hipMallocAsync(p, bytes, F->stream);
     if (e != hipSuccess) { *p = nullptr; return e; }
     list.push_back(*p);
@@ -181,7 +219,7 @@ pf_opts resolve_opts(const pf_opts *o)
 int check_opts(const pf_matrix *A, const pf_opts &o)
 {
     if (o.prec != PF_FP64 && o.prec != PF_FP32_IR) return -2;
-    if (o.partitions < 0 || o.block_rows < 0) return -2;
+    if (o.partitions < 0 || o.block_rows < 0 || o.coarse_rows < 0) return -2;
     if (o.partitions > 0) {
         const int64_t pmax = (A->kind == PF_BTRI) ? (A->nb + 1) / 2 : (A->nb - 1) / 2;
         if (o.partitions > pmax && !(A->kind == PF_BABD && A->nb == 2)) return -2;
@@ -218,6 +256,63 @@ hipError_t prof_launch(pf_factor_s *F, bool factor, int phase, int level, hipStr
     return hipEventRecord(sl.b, s);
 }
 
+// Kernel arguments of the factorization of level l.
+LevelArgs level_args(const pf_factor_s *F, size_t l)
+{
+    const Level &L = F->lv[l];
+    LevelArgs a{};
+    a.nb = L.nb; a.p = L.p;
+    a.D = L.D; a.Dadd = L.Dadd; a.Lo = L.Lo; a.Up = L.Up; a.C = L.C;
+    a.E = L.E; a.R = L.R; a.Z = L.Z; a.X = L.X;
+    a.nD = L.nD; a.nDadd = L.nDadd; a.nLo = L.nLo; a.nUp = L.nUp; a.nC = L.nC;
+    a.status = F->d_status;
+    a.dump = F->d_dump;
+    a.zero = F->d_zero;
+    a.level = (int)l;
+    return a;
+}
+
+// Kernel arguments of every level of one solve: F0/Y0 are the (padded when
+// M != m) right-hand side and solution of level 0, the other levels use the
+// handle's workspace.
+std::vector<SolveArgs> solve_args(const pf_factor_s *F, int nrhs, const double *F0, int64_t ld0f,
+                                  double *Y0, int64_t ld0y)
+{
+    const int M = F->M;
+    const size_t L = F->lv.size();
+    std::vector<SolveArgs> args(L);
+    for (size_t l = 0; l < L; ++l) {
+        const Level &lv = F->lv[l];
+        SolveArgs &a = args[l];
+        a = SolveArgs{};
+        a.nb = lv.nb;
+        a.dump = (double *)F->d_dump;
+        a.zero = F->d_zero;
+        a.p = lv.p;
+        a.nrhs = nrhs;
+        a.Lo = lv.Lo;
+        a.E = lv.E; a.R = lv.R; a.Z = lv.Z; a.X = lv.X;
+        if (l == 0) {
+            a.F = F0; a.ldf = ld0f; a.Fadd = nullptr; a.Y = Y0; a.ldy = ld0y;
+        } else {
+            a.F = F->wsF[l];
+            a.Fadd = F->wsFadd[l];
+            a.ldf = lv.nb * M;
+            a.Y = F->wsY[l];
+            a.ldy = lv.nb * M;
+        }
+        if (l + 1 < L) {
+            a.nF = F->wsF[l + 1];
+            a.nFadd = F->wsFadd[l + 1];
+            a.ldn = F->lv[l + 1].nb * M;
+            a.Xsep = F->wsY[l + 1];
+        } else {
+            a.ldn = 1;
+        }
+    }
+    return args;
+}
+
 hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
 {
     F->prof_fac_n = 0;
@@ -234,14 +329,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
     }
     for (size_t l = 0; l < F->lv.size(); ++l) {
         const Level &L = F->lv[l];
-        LevelArgs a{};
-        a.nb = L.nb; a.p = L.p;
-        a.D = L.D; a.Dadd = L.Dadd; a.Lo = L.Lo; a.Up = L.Up; a.C = L.C;
-        a.E = L.E; a.R = L.R; a.Z = L.Z; a.X = L.X;
-        a.nD = L.nD; a.nDadd = L.nDadd; a.nLo = L.nLo; a.nUp = L.nUp; a.nC = L.nC;
-        a.status = F->d_status;
-        a.dump = F->d_dump;
-        a.level = (int)l;
+        const LevelArgs a = level_args(F, l);
         e = prof_launch(F, true, 0, (int)l, s, [&] {
             return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
                                        : launch_babd_factor(F->M, L.f32, a, s);
@@ -261,6 +349,15 @@ int ensure_workspace(pf_factor_s *F, int nrhs)
 {
     if (nrhs <= F->rhs_cap) return 0;
     free_list(F, F->ws_allocs);
+    // a handle carved from a batch arena grows its workspace in memory of
+    // its own (the arena is sized for the batch's right-hand sides only)
+    Arena *const ar = F->arena;
+    if (ar && !ar->counting && F->rhs_cap > 0) F->arena = nullptr;
+    struct Restore {
+        pf_factor_s *F;
+        Arena *ar;
+        ~Restore() { F->arena = ar; }
+    } restore{F, ar};
     const int cap = std::max(nrhs, 1);
     const size_t L = F->lv.size();
     F->wsF.assign(L, nullptr);
@@ -314,35 +411,7 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
         Y0 = F->wsPadX;
         ld0f = ld0y = ldp;
     }
-    std::vector<SolveArgs> args(L);
-    for (size_t l = 0; l < L; ++l) {
-        const Level &lv = F->lv[l];
-        SolveArgs &a = args[l];
-        a = SolveArgs{};
-        a.nb = lv.nb;
-        a.dump = (double *)F->d_dump;
-        a.p = lv.p;
-        a.nrhs = nrhs;
-        a.Lo = lv.Lo;
-        a.E = lv.E; a.R = lv.R; a.Z = lv.Z; a.X = lv.X;
-        if (l == 0) {
-            a.F = F0; a.ldf = ld0f; a.Fadd = nullptr; a.Y = Y0; a.ldy = ld0y;
-        } else {
-            a.F = F->wsF[l];
-            a.Fadd = F->wsFadd[l];
-            a.ldf = lv.nb * M;
-            a.Y = F->wsY[l];
-            a.ldy = lv.nb * M;
-        }
-        if (l + 1 < L) {
-            a.nF = F->wsF[l + 1];
-            a.nFadd = F->wsFadd[l + 1];
-            a.ldn = F->lv[l + 1].nb * M;
-            a.Xsep = F->wsY[l + 1];
-        } else {
-            a.ldn = 1;
-        }
-    }
+    const std::vector<SolveArgs> args = solve_args(F, nrhs, F0, ld0f, Y0, ld0y);
     F->prof_sol_n = 0;
     for (size_t l = 0; l < L; ++l) {
         const Level &lv = F->lv[l];
@@ -455,28 +524,30 @@ size_t pf_solve_bytes_per_rhs(const pf_matrix *A, const pf_opts *opts)
     return b;
 }
 
-int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t *out)
-{
-    if (!out) return -4;
-    *out = nullptr;
-    int rc = check_matrix(A);
-    if (rc) return rc;
-    const pf_opts o = resolve_opts(opts);
-    if ((rc = check_opts(A, o))) return rc;
+}  // extern "C"
 
+namespace {
+
+// Allocate and wire a handle for an already validated matrix: plan, factor
+// storage, reduced systems, status words.  No kernel runs here.  With an
+// arena the memory comes from it; with shared scratch (a batch) the handle
+// uses it for its dump and zero areas instead of its own.
+int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *arena,
+                 void *shared_scratch, pf_factor_s **out)
+{
     pf_factor_s *F = new pf_factor_s();
     F->A = *A;
     F->opts = o;
     F->m = A->m;
     F->M = padded_block(A->m);
     F->nb = A->nb;
-    F->stream = (hipStream_t)stream;
+    F->stream = s;
+    F->arena = arena;
     const int M = F->M;
     const size_t bd = (size_t)M * M * sizeof(double);
-    hipStream_t s = F->stream;
     auto fail = [&](int code) {
         free_list(F, F->allocs);
-        hipStreamSynchronize(s);
+        if (!arena) hipStreamSynchronize(s);
         delete F;
         return code;
     };
@@ -485,9 +556,10 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
         return fail(PF_ENOMEM);
     F->d_status = (unsigned long long *)p;
     F->d_norm = F->d_status + 1;
-    if (dalloc(F, &F->d_dump, kDumpBytes, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-    if (launch_fill_u64(F->d_status, 1, ~0ull, s) != hipSuccess) return fail(PF_EHIP);
-    if (launch_fill_u64(F->d_norm, 1, 0ull, s) != hipSuccess) return fail(PF_EHIP);
+    if (shared_scratch) F->d_dump = shared_scratch;
+    else if (dalloc(F, &F->d_dump, kDumpBytes + kZeroBytes, F->allocs) != hipSuccess)
+        return fail(PF_ENOMEM);
+    F->d_zero = (const double *)((char *)F->d_dump + kDumpBytes);
 
     // level-0 matrix (padded to an instantiated block size if needed; the
     // padding itself runs in launch_factor_levels so refactor redoes it)
@@ -558,7 +630,31 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
             L.nC = (double *)p;
         }
     }
-    if (launch_factor_levels(F, s) != hipSuccess) return fail(PF_EHIP);
+    *out = F;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t *out)
+{
+    if (!out) return -4;
+    *out = nullptr;
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    const pf_opts o = resolve_opts(opts);
+    if ((rc = check_opts(A, o))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    pf_factor_s *F = nullptr;
+    if ((rc = factor_setup(A, o, s, nullptr, nullptr, &F))) return rc;
+    hipError_t e = launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s);
+    if (e == hipSuccess) e = launch_factor_levels(F, s);
+    if (e != hipSuccess) {
+        pf_destroy(F);
+        return PF_EHIP;
+    }
     *out = F;
     return 0;
 }
@@ -679,6 +775,7 @@ void pf_destroy(pf_factor_t F)
             if (sl.a) hipEventDestroy(sl.a);
             if (sl.b) hipEventDestroy(sl.b);
         }
+    if (F->arena) arena_release(F->arena, F->stream);
     delete F;
 }
 
@@ -778,32 +875,476 @@ int pf_abd_to_btri(int32_t m, int64_t N, int32_t qa, const double *Ba, const dou
                    hipSuccess ? 0 : PF_EHIP;
 }
 
+}  // extern "C"
+
+// ===========================================================================
+// Batches: many independent systems, one launch per (level, phase, launch
+// key), the whole factor + solve sequence recorded into one HIP graph.
+namespace {
+
+struct BatchLaunch {
+    int phase;      // 0 factor, 1 forward sweep, 2 back substitution
+    int kind, M, KC;
+    bool f32, add;
+    size_t work;    // first work item of this launch
+    int nwg;
+};
+
+// Device tables of one batched solve configuration (right-hand sides in,
+// solutions out): kernel arguments per (system, level) and one work item
+// (table entry, partition block, right-hand-side block) per workgroup.
+struct SolveSet {
+    SolveArgs *d_tab = nullptr;
+    int4 *d_work = nullptr;
+    std::vector<BatchLaunch> launches;
+};
+
+}  // namespace
+
+struct pf_batch_s {
+    int nsys = 0;
+    pf_opts opts{};
+    hipStream_t user = nullptr;         // the caller's stream at creation
+    hipStream_t cap = nullptr;          // internal stream the graph is recorded on
+    hipEvent_t ev = nullptr;
+    Arena *arena = nullptr;
+    std::vector<pf_factor_s *> F;       // per system (null once handed out)
+    std::vector<pf_factor_s *> all;     // per system, for the recorded work
+    std::vector<int32_t> nrhs;
+    std::vector<const double *> f;
+    std::vector<double *> x;
+    std::vector<int64_t> ldf, ldx;
+    unsigned long long *d_words = nullptr;   // nsys status words, nsys norm words
+    LevelArgs *d_lev = nullptr;
+    int4 *d_lwork = nullptr;
+    std::vector<BatchLaunch> flaunch;
+    SolveSet sol, corr;                  // f -> x, and residual -> correction
+    std::vector<void *> own;             // table allocations
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+hipError_t launch_pad_matrix(pf_factor_s *F, hipStream_t s)
+{
+    const pf_matrix &A0 = F->A;
+    hipError_t e = launch_pad_blocks(A0.m, F->M, A0.nb, A0.D, F->padD, 1.0, s);
+    if (e == hipSuccess) e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Lo, F->padLo, 0.0, s);
+    if (e == hipSuccess && F->padUp)
+        e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Up, F->padUp, 0.0, s);
+    if (e == hipSuccess && F->padC) e = launch_pad_blocks(A0.m, F->M, 1, A0.C, F->padC, 0.0, s);
+    return e;
+}
+
+void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector<int4> &work)
+{
+    size_t maxL = 0;
+    for (auto *F : B->all) maxL = std::max(maxL, F->lv.size());
+    for (size_t l = 0; l < maxL; ++l) {
+        std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+        for (int i = 0; i < B->nsys; ++i) {
+            const pf_factor_s *F = B->all[i];
+            if (l >= F->lv.size()) continue;
+            const Level &L = F->lv[l];
+            groups[{L.kind, F->M, L.f32 ? 1 : 0, (L.kind == PF_BTRI && L.Dadd) ? 1 : 0}].push_back(i);
+        }
+        for (auto &kv : groups) {
+            BatchLaunch bl{0, std::get<0>(kv.first), std::get<1>(kv.first), 1,
+                           std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0, work.size(), 0};
+            const int gpw = groups_per_wg(bl.M);
+            for (int i : kv.second) {
+                const int entry = (int)tab.size();
+                tab.push_back(level_args(B->all[i], l));
+                const int64_t nblk = (B->all[i]->lv[l].p + gpw - 1) / gpw;
+                for (int64_t pb = 0; pb < nblk; ++pb) work.push_back(make_int4(entry, (int)pb, 0, 0));
+            }
+            bl.nwg = (int)(work.size() - bl.work);
+            B->flaunch.push_back(bl);
+        }
+    }
+}
+
+// rhs/sol: per-system level-0 right-hand sides and solutions (unpadded);
+// systems whose block size is padded run through their padded workspace.
+void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
+                        const std::vector<int64_t> &ldr, const std::vector<double *> &sol,
+                        const std::vector<int64_t> &lds, SolveSet &S, std::vector<SolveArgs> &tab,
+                        std::vector<int4> &work)
+{
+    std::vector<std::vector<SolveArgs>> args(B->nsys);
+    size_t maxL = 0;
+    for (int i = 0; i < B->nsys; ++i) {
+        pf_factor_s *F = B->all[i];
+        const bool pad = F->M != F->m;
+        const int64_t ldp = F->nb * F->M;
+        args[i] = solve_args(F, B->nrhs[i], pad ? F->wsPadF : rhs[i], pad ? ldp : ldr[i],
+                             pad ? F->wsPadX : sol[i], pad ? ldp : lds[i]);
+        maxL = std::max(maxL, F->lv.size());
+    }
+    auto emit = [&](int phase, size_t l) {
+        std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
+        for (int i = 0; i < B->nsys; ++i) {
+            const pf_factor_s *F = B->all[i];
+            if (l >= F->lv.size() || B->nrhs[i] == 0) continue;
+            const Level &L = F->lv[l];
+            const int add = (phase == 1 && L.kind == PF_BTRI && args[i][l].Fadd) ? 1 : 0;
+            groups[{L.kind, F->M, L.f32 ? 1 : 0, add, rhs_chunk(B->nrhs[i])}].push_back(i);
+        }
+        for (auto &kv : groups) {
+            BatchLaunch bl{phase, std::get<0>(kv.first), std::get<1>(kv.first),
+                           std::get<4>(kv.first), std::get<2>(kv.first) != 0,
+                           std::get<3>(kv.first) != 0, work.size(), 0};
+            const int gpw = groups_per_wg(bl.M);
+            for (int i : kv.second) {
+                const int entry = (int)tab.size();
+                tab.push_back(args[i][l]);
+                const int64_t nblk = (B->all[i]->lv[l].p + gpw - 1) / gpw;
+                const int ncb = (B->nrhs[i] + bl.KC - 1) / bl.KC;
+                for (int cb = 0; cb < ncb; ++cb)
+                    for (int64_t pb = 0; pb < nblk; ++pb)
+                        work.push_back(make_int4(entry, (int)pb, cb, 0));
+            }
+            bl.nwg = (int)(work.size() - bl.work);
+            S.launches.push_back(bl);
+        }
+    };
+    for (size_t l = 0; l < maxL; ++l) emit(1, l);
+    for (size_t l = maxL; l-- > 0;) emit(2, l);
+}
+
+hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(B->d_words, B->nsys, ~0ull, s);
+    if (e == hipSuccess) e = launch_fill_u64(B->d_words + B->nsys, B->nsys, 0ull, s);
+    for (auto *F : B->all)
+        if (e == hipSuccess && F->M != F->m) e = launch_pad_matrix(F, s);
+    for (const auto &bl : B->flaunch)
+        if (e == hipSuccess)
+            e = launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev, B->d_lwork + bl.work,
+                                    bl.nwg, s);
+    if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
+        for (auto *F : B->all) {
+            const pf_matrix &A = F->A;
+            if (e == hipSuccess)
+                e = launch_norminf(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, F->d_norm, s);
+        }
+    return e;
+}
+
+hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < B->nsys && e == hipSuccess; ++i) {
+        pf_factor_s *F = B->all[i];
+        if (F->M == F->m || B->nrhs[i] == 0) continue;
+        const int64_t n = F->nb * F->m;
+        e = launch_pad_rhs(F->m, F->M, F->nb, B->nrhs[i], corr ? F->wsR : B->f[i],
+                           corr ? n : B->ldf[i], F->wsPadF, F->nb * F->M, true, s);
+    }
+    for (const auto &bl : S.launches)
+        if (e == hipSuccess)
+            e = launch_solve_batch(bl.kind, bl.phase == 1, bl.M, bl.f32, bl.add, bl.KC, S.d_tab,
+                                   S.d_work + bl.work, bl.nwg, s);
+    for (int i = 0; i < B->nsys && e == hipSuccess; ++i) {
+        pf_factor_s *F = B->all[i];
+        if (F->M == F->m || B->nrhs[i] == 0) continue;
+        const int64_t n = F->nb * F->m;
+        e = launch_pad_rhs(F->m, F->M, F->nb, B->nrhs[i], F->wsPadX, F->nb * F->M,
+                           corr ? F->wsD : B->x[i], corr ? n : B->ldx[i], false, s);
+    }
+    return e;
+}
+
+template <class T>
+hipError_t upload(pf_batch_s *B, const std::vector<T> &v, T **d)
+{
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    B->own.push_back(p);
+    *d = (T *)p;
+    return v.empty() ? hipSuccess : hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void batch_free(pf_batch_s *B)
+{
+    if (B->cap) hipStreamSynchronize(B->cap);
+    if (B->exec) hipGraphExecDestroy(B->exec);
+    if (B->graph) hipGraphDestroy(B->graph);
+    for (auto *F : B->F)
+        if (F) pf_destroy(F);
+    for (void *p : B->own) hipFree(p);
+    if (B->arena) arena_release(B->arena, B->cap ? B->cap : B->user);
+    if (B->ev) hipEventDestroy(B->ev);
+    if (B->cap) hipStreamDestroy(B->cap);
+    delete B;
+}
+
+// FP64 refinement of every system of the batch (PF_FP32_IR): residuals and
+// norms for all systems, one synchronization, then one batched correction
+// solve for all systems, until every eta <= tol or a system stagnates.
+int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::vector<int> &iters,
+                 std::vector<int> &status)
+{
+    const int ns = B->nsys;
+    eta.assign(ns, INFINITY);
+    iters.assign(ns, 0);
+    status.assign(ns, PF_OK);
+    std::vector<double> prev(ns, INFINITY);
+    std::vector<int> slow(ns, 0), done(ns, 0);
+    // words: ns status, ns ||A||, then 3 * max(nrhs, 1) norms per system
+    size_t slots = 0;
+    for (int i = 0; i < ns; ++i) slots += 3 * (size_t)std::max(B->nrhs[i], 1);
+    std::vector<unsigned long long> h(2 * (size_t)ns + slots);
+    HIPCHK(launch_fill_u64(B->d_words + 2 * ns, (int64_t)slots, 0ull, s));
+    for (;;) {
+        for (int i = 0; i < ns; ++i) {
+            pf_factor_s *F = B->all[i];
+            const pf_matrix &A = F->A;
+            const int64_t n = A.nb * A.m;
+            if (done[i] || B->nrhs[i] == 0) continue;
+            HIPCHK(launch_fill_u64(F->d_norms, 3 * B->nrhs[i], 0ull, s));
+            HIPCHK(launch_residual(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, B->nrhs[i], B->f[i],
+                                   B->ldf[i], B->x[i], B->ldx[i], F->wsR, n, F->d_norms, s));
+        }
+        HIPCHK(hipMemcpyAsync(h.data(), B->d_words, h.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool all = true;
+        size_t off = 2 * (size_t)ns;
+        for (int i = 0; i < ns; ++i) {
+            const size_t base = off;
+            off += 3 * (size_t)std::max(B->nrhs[i], 1);
+            if (done[i]) continue;
+            const double na = bits_to_double(h[ns + i]);
+            double w = 0.0;
+            for (int c = 0; c < B->nrhs[i]; ++c) {
+                const double nr = bits_to_double(h[base + 3 * c]),
+                             nx = bits_to_double(h[base + 3 * c + 1]),
+                             nf = bits_to_double(h[base + 3 * c + 2]);
+                const double den = na * nx + nf;
+                double e = den > 0 ? nr / den : (nr > 0 ? INFINITY : 0.0);
+                if (std::isnan(e)) e = INFINITY;
+                w = std::max(w, e);
+            }
+            eta[i] = w;
+            if (w <= B->opts.tol) { done[i] = 1; continue; }
+            if (iters[i] >= B->opts.max_refine) { done[i] = 1; status[i] = PF_ENOCONV; continue; }
+            slow[i] = (w > 0.5 * prev[i]) ? slow[i] + 1 : 0;
+            if (slow[i] >= 2) { done[i] = 1; status[i] = PF_ENOCONV; continue; }
+            prev[i] = w;
+            all = false;
+        }
+        if (all) break;
+        HIPCHK(issue_solve(B, B->corr, true, s));
+        for (int i = 0; i < ns; ++i) {
+            if (done[i]) continue;
+            pf_factor_s *F = B->all[i];
+            const int64_t n = F->nb * F->m;
+            HIPCHK(launch_axpy(n, B->nrhs[i], F->wsD, n, B->x[i], B->ldx[i], s));
+            ++iters[i];
+        }
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const int32_t *nrhs,
+                    const double *const *f, const int64_t *ldf, double *const *x,
+                    const int64_t *ldx, void *stream, pf_batch_t *out)
+{
+    if (!out) return -10;
+    *out = nullptr;
+    if (nsys < 1) return -1;
+    if (!A) return -2;
+    const pf_opts o = resolve_opts(opts);
+    if (!nrhs || !f || !ldf || !x || !ldx) return -4;
+    for (int i = 0; i < nsys; ++i) {
+        int rc = check_matrix(&A[i]);
+        if (rc) return rc < 0 ? -2 : rc;
+        if ((rc = check_opts(&A[i], o))) return -3;
+        const int64_t n = A[i].nb * A[i].m;
+        if (nrhs[i] < 0 || (nrhs[i] > 0 && (!f[i] || !x[i])) || ldf[i] < n || ldx[i] < n) return -4;
+    }
+    hipStream_t us = (hipStream_t)stream;
+    pf_batch_s *B = new pf_batch_s();
+    B->nsys = nsys;
+    B->opts = o;
+    B->user = us;
+    B->nrhs.assign(nrhs, nrhs + nsys);
+    B->f.assign(f, f + nsys);
+    B->x.assign(x, x + nsys);
+    B->ldf.assign(ldf, ldf + nsys);
+    B->ldx.assign(ldx, ldx + nsys);
+    auto fail = [&](int code) {
+        batch_free(B);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess) return fail(PF_EHIP);
+    if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess) return fail(PF_EHIP);
+
+    // sizes: a counting pass through the same setup code
+    Arena count;
+    count.counting = true;
+    size_t total_rhs = 0;
+    for (int i = 0; i < nsys; ++i) total_rhs += (size_t)std::max(nrhs[i], 1);
+    const size_t words = (2 * (size_t)nsys + 3 * total_rhs) * sizeof(unsigned long long);
+    void *fake = (void *)(uintptr_t)4096;
+    for (int i = 0; i < nsys; ++i) {
+        pf_factor_s *F = nullptr;
+        if (factor_setup(&A[i], o, us, &count, fake, &F)) return fail(PF_ENOMEM);
+        ensure_workspace(F, std::max(nrhs[i], 1));
+        delete F;
+    }
+    B->arena = new Arena();
+    B->arena->refs = 1;
+    B->arena->cap = count.off + words + kDumpBytes + kZeroBytes + 4096;
+    if (hipMalloc((void **)&B->arena->base, B->arena->cap) != hipSuccess) return fail(PF_ENOMEM);
+    Arena &ar = *B->arena;
+    B->d_words = (unsigned long long *)ar.base;
+    ar.off = words;
+    void *scratch = ar.base + ((ar.off + 255) & ~(size_t)255);
+    ar.off = ((ar.off + 255) & ~(size_t)255) + kDumpBytes + kZeroBytes;
+    unsigned long long *norms = B->d_words + 2 * nsys;
+    B->F.assign(nsys, nullptr);
+    for (int i = 0; i < nsys; ++i) {
+        pf_factor_s *F = nullptr;
+        if (factor_setup(&A[i], o, us, B->arena, scratch, &F)) return fail(PF_ENOMEM);
+        ++ar.refs;
+        B->F[i] = F;
+        if (ensure_workspace(F, std::max(nrhs[i], 1))) return fail(PF_ENOMEM);
+        // status, ||A|| and per-column norm words of all systems are
+        // contiguous: one fill, one read-back per refinement sweep
+        F->d_status = B->d_words + i;
+        F->d_norm = B->d_words + nsys + i;
+        F->d_norms = norms;
+        norms += 3 * (size_t)std::max(nrhs[i], 1);
+    }
+    B->all = B->F;
+    if (launch_fill_u64((unsigned long long *)((char *)scratch + kDumpBytes), kZeroBytes / 8, 0ull,
+                        us) != hipSuccess)
+        return fail(PF_EHIP);
+
+    std::vector<LevelArgs> ltab;
+    std::vector<int4> lwork;
+    build_factor_tables(B, ltab, lwork);
+    std::vector<SolveArgs> stab, ctab;
+    std::vector<int4> swork, cwork;
+    build_solve_tables(B, B->f, B->ldf, B->x, B->ldx, B->sol, stab, swork);
+    if (o.prec == PF_FP32_IR) {
+        std::vector<const double *> r(nsys);
+        std::vector<double *> d(nsys);
+        std::vector<int64_t> ld(nsys);
+        for (int i = 0; i < nsys; ++i) {
+            r[i] = B->all[i]->wsR;
+            d[i] = B->all[i]->wsD;
+            ld[i] = B->all[i]->nb * B->all[i]->m;
+        }
+        build_solve_tables(B, r, ld, d, ld, B->corr, ctab, cwork);
+    }
+    if (upload(B, ltab, &B->d_lev) || upload(B, lwork, &B->d_lwork) ||
+        upload(B, stab, &B->sol.d_tab) || upload(B, swork, &B->sol.d_work))
+        return fail(PF_EHIP);
+    if (o.prec == PF_FP32_IR &&
+        (upload(B, ctab, &B->corr.d_tab) || upload(B, cwork, &B->corr.d_work)))
+        return fail(PF_EHIP);
+    if (hipStreamSynchronize(us) != hipSuccess) return fail(PF_EHIP);
+
+    // record factor + solve once; pf_batch_run replays it
+    if (hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(PF_EHIP);
+    hipError_t e = issue_factor(B, B->cap);
+    if (e == hipSuccess) e = issue_solve(B, B->sol, false, B->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+    B->graph = g;
+    if (e != hipSuccess || e2 != hipSuccess || !g) return fail(PF_EHIP);
+    if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(PF_EHIP);
+    *out = B;
+    return 0;
+}
+
+int pf_batch_run(pf_batch_t B, void *stream, pf_info *info)
+{
+    if (!B) return -1;
+    hipStream_t us = (hipStream_t)stream;
+    if (hipEventRecord(B->ev, us) != hipSuccess) return PF_EHIP;
+    if (hipStreamWaitEvent(B->cap, B->ev, 0) != hipSuccess) return PF_EHIP;
+    if (hipGraphLaunch(B->exec, B->cap) != hipSuccess) return PF_EHIP;
+    std::vector<double> eta;
+    std::vector<int> iters, st;
+    int worst = 0;
+    if (B->opts.prec == PF_FP32_IR) {
+        const int rc = batch_refine(B, B->cap, eta, iters, st);
+        if (rc) return rc;
+    }
+    if (hipEventRecord(B->ev, B->cap) != hipSuccess) return PF_EHIP;
+    if (hipStreamWaitEvent(us, B->ev, 0) != hipSuccess) return PF_EHIP;
+    if (info || B->opts.prec == PF_FP32_IR) {
+        if (hipStreamSynchronize(B->cap) != hipSuccess) return PF_EHIP;
+        std::vector<unsigned long long> w(B->nsys);
+        if (hipMemcpy(w.data(), B->d_words, B->nsys * sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return PF_EHIP;
+        for (int i = 0; i < B->nsys; ++i) {
+            pf_info inf{};
+            inf.eta = -1.0;
+            inf.bad_block = -1;
+            if (w[i] != ~0ull) {
+                inf.status = PF_ESINGULAR;
+                inf.bad_level = (int32_t)(w[i] >> 40);
+                inf.bad_block = (int64_t)(w[i] & ((1ull << 40) - 1));
+            }
+            if (!eta.empty()) {
+                inf.eta = eta[i];
+                inf.refine_iters = iters[i];
+                if (inf.status == PF_OK) inf.status = st[i];
+            }
+            if (inf.status && !worst) worst = inf.status;
+            if (info) info[i] = inf;
+        }
+    }
+    return worst;
+}
+
+int pf_batch_factor(pf_batch_t B, int32_t i, pf_factor_t *out)
+{
+    if (!B) return -1;
+    if (i < 0 || i >= B->nsys) return -2;
+    if (!out) return -3;
+    *out = B->F[i];
+    if (!B->F[i]) return -2;      // already handed out
+    B->F[i] = nullptr;            // the handle now owns its share of the arena
+    return 0;
+}
+
+void pf_batch_destroy(pf_batch_t B)
+{
+    if (B) batch_free(B);
+}
+
 int pf_solve_batch(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const int32_t *nrhs,
                    const double *const *f, const int64_t *ldf, double *const *x,
                    const int64_t *ldx, void *stream, pf_factor_t *factors, pf_info *info)
 {
     if (nsys < 0) return -1;
-    if (nsys > 0 && !A) return -2;
-    if (nsys > 0 && (!nrhs || !f || !ldf || !x || !ldx)) return -4;
-    int worst = 0;
-    for (int i = 0; i < nsys; ++i) {
-        pf_factor_t Fi = nullptr;
-        int rc = pf_factor(&A[i], opts, stream, &Fi);
-        if (rc) {
-            if (info) { std::memset(&info[i], 0, sizeof(pf_info)); info[i].status = rc; }
-            worst = worst ? worst : rc;
-            if (factors) factors[i] = nullptr;
-            continue;
-        }
-        pf_info inf{};
-        rc = pf_solve(Fi, nrhs[i], f[i], ldf[i], x[i], ldx[i], stream, info ? &inf : nullptr);
-        if (info) info[i] = inf;
-        if (rc && !worst) worst = rc;
-        if (factors) factors[i] = Fi;
-        else pf_destroy(Fi);
-    }
-    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PF_EHIP;
-    return worst;
+    if (nsys == 0) return 0;
+    pf_batch_t B = nullptr;
+    int rc = pf_batch_create(nsys, A, opts, nrhs, f, ldf, x, ldx, stream, &B);
+    if (rc) return rc;
+    std::vector<pf_info> tmp(nsys);
+    rc = pf_batch_run(B, stream, info ? info : tmp.data());
+    if (factors)
+        for (int i = 0; i < nsys; ++i) pf_batch_factor(B, i, &factors[i]);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && !rc) rc = PF_EHIP;
+    pf_batch_destroy(B);
+    return rc;
 }
 
 }  // extern "C"

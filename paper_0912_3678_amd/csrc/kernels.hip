@@ -12,25 +12,27 @@
 // eq. (redmatr) / (redmatr1).
 //
 // GPU mapping.  A workgroup is one wave64.  A partition is owned by a group
-// of M consecutive lanes (M = block size; 64/M partitions per wave).  In the
-// factor kernels lane j holds column j of every block it works on; in the
-// solve kernels lane i holds row i.  Left operands of block products go
-// through the group's own slice of LDS.  A group never leaves its wave, so
-// the only ordering needed between an LDS write and the reads of the other
-// lanes is the in-order LDS pipe of the wave plus a compiler fence
-// (wave_sync); no workgroup barrier is used.
+// of M consecutive lanes (M = block size; 64/M partitions per wave) and lane
+// i holds row i of every block the partition works on.  The pivot block is
+// inverted by a row-distributed Gauss-Jordan elimination whose pivot search
+// is a DPP reduction inside the group; operands that every lane needs in
+// full go through the group's own, bank-padded slice of LDS.  A group never
+// leaves its wave, so the only ordering needed between an LDS write and the
+// reads of the other lanes is the in-order LDS pipe of the wave plus a
+// compiler fence (wave_sync); no workgroup barrier is used.
 //
-// Memory discipline inside the chain loops: every load and store is issued
-// unconditionally (load indices are clamped to a valid block and the values
-// masked afterwards; stores of inactive iterations are redirected to a small
-// dump buffer) and the zero-pivot report is deferred to the end.  With no
-// memory operation under a branch, the compiler's wait counters stay exact:
-// a row waits for the loads it needs, never for the stores of earlier rows
-// (on this architecture stores and loads share one in-order counter).
+// Memory discipline inside the chain loops: no memory operation sits under
+// a branch (missing operands are read from a zero block, stores a lane must
+// not make go to a dump buffer, the zero-pivot report is deferred), and the
+// operands of the next block row are loaded before the current row's
+// stores.  The compiler's wait counters then stay exact and a row never waits
+// for the stores of the previous one (loads and stores share one in-order
+// counter on this architecture).
 //
-// Factor storage: per block row g, column-major M x M blocks E (inverse of
-// the eliminated pivot block D'), X = E A(g,g+1), Zh (left spike column) and
-// R (left spike row) -- exactly the quantities the solve needs.
+// Factor storage: per block row g, row-major M x M blocks E (inverse of the
+// eliminated pivot block D'), X = E A(g,g+1), Zh (left spike column) and R
+// (left spike row) -- exactly the quantities the solve needs, laid out so the
+// solve kernels load contiguous rows.
 //
 // Recurrences of one partition (global blocks g_1..g_n between the
 // separators sL = g_1 - 1 and sR = g_n + 1), block tridiagonal case:
@@ -147,12 +149,27 @@ __device__ __forceinline__ void st_fac(T *__restrict__ p, const T (&v)[M])
     }
 }
 
-// row i of a column-major M x M block of T
+// M contiguous T (factor storage) -> registers (16-byte loads where possible)
 template <int M, typename T>
-__device__ __forceinline__ void ld_row(T (&v)[M], const T *__restrict__ blk, int i)
+__device__ __forceinline__ void ld_fac(T (&v)[M], const T *__restrict__ p)
 {
+    if constexpr (sizeof(T) == 8 && M % 2 == 0) {
 #pragma unroll
-    for (int l = 0; l < M; ++l) v[l] = blk[i + l * M];
+        for (int r = 0; r < M; r += 2) {
+            const double2 w = *reinterpret_cast<const double2 *>(p + r);
+            v[r] = w.x;
+            v[r + 1] = w.y;
+        }
+    } else if constexpr (sizeof(T) == 4 && M % 4 == 0) {
+#pragma unroll
+        for (int r = 0; r < M; r += 4) {
+            const float4 w = *reinterpret_cast<const float4 *>(p + r);
+            v[r] = w.x; v[r + 1] = w.y; v[r + 2] = w.z; v[r + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = p[r];
+    }
 }
 
 template <int M, typename T>
@@ -215,145 +232,247 @@ __device__ __forceinline__ void lds_gemv(const T *S, const T (&v)[M], T (&o)[M])
     }
 }
 
-// ---- Gauss-Jordan inversion of the pivot block with row partial pivoting --
-// Lane j holds column j of D' in d; on return e holds column j of D'^{-1}
-// (d is consumed).  At step c every lane publishes its current column in the
-// group's LDS scratch SG and reads column c; the pivot is the first index of
-// the largest magnitude among rows c..M-1 of that column.  Every lane swaps
-// the same two rows of its own columns and eliminates column c above and
-// below the pivot.  Branch-free (selects only).  Returns true if a pivot was
-// exactly zero.
-template <int M, typename T>
-__device__ __forceinline__ bool gj_invert(T (&d)[M], T (&e)[M], int j, T *SG)
+// ---- LDS layout ---------------------------------------------------------------
+// Rows of the small matrices a group keeps in LDS are padded by 16 bytes and
+// the groups' regions start 16 bytes apart modulo 128, so the lanes of a group
+// (one row each) and the groups of a wave (one region each) fall into
+// different banks instead of all hitting the same one.
+template <typename T> constexpr int kPad = 16 / (int)sizeof(T);
+template <typename T> constexpr int kLine = 128 / (int)sizeof(T);
+template <typename T> constexpr int group_stride(int elems)
 {
-    bool sing = false;
+    return ((elems + kLine<T> - 1) / kLine<T>) * kLine<T> + kPad<T>;
+}
+
+// ---- group-wide argmax with DPP -------------------------------------------
+// The M lanes of a group are an aligned run inside a row of 16 (M <= 16) or a
+// half wave (M = 32), so these cross-lane moves never leave the group.
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp_x(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_x(float v)
+{
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+
+// keep the larger value; among equal values the smaller row index
+template <typename T>
+__device__ __forceinline__ void argmax_merge(T &v, int &idx, T ov, int oi)
+{
+    const bool take = (ov > v) || (ov == v && oi < idx);
+    v = take ? ov : v;
+    idx = take ? oi : idx;
+}
+
+template <int M, typename T>
+__device__ __forceinline__ int group_argmax(T v, int idx)
+{
+    if constexpr (M >= 2) argmax_merge(v, idx, dpp_x<0xB1>(v), dpp_i<0xB1>(idx));    // lane ^ 1
+    if constexpr (M >= 4) argmax_merge(v, idx, dpp_x<0x4E>(v), dpp_i<0x4E>(idx));    // lane ^ 2
+    if constexpr (M >= 8) argmax_merge(v, idx, dpp_x<0x141>(v), dpp_i<0x141>(idx));  // half-row mirror
+    if constexpr (M >= 16) argmax_merge(v, idx, dpp_x<0x140>(v), dpp_i<0x140>(idx)); // row mirror
+    if constexpr (M >= 32) argmax_merge(v, idx, (T)__shfl_xor(v, 16, 32), __shfl_xor(idx, 16, 32));
+    return idx;
+}
+
+// reciprocal: hardware estimate refined by Newton steps (two in FP64, one in FP32)
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// ---- Gauss-Jordan inversion of the pivot block with row partial pivoting --
+// Row-distributed and swap-free: lane i holds row i of D' in d (consumed) and
+// starts with row i of the identity in e.  At step c the pivot is the row
+// with the largest |D'(r,c)| among rows not yet used as pivots (first index
+// on ties), found by a DPP max-reduction; the pivot lane's row [d | e] is read
+// from the group's LDS, the pivot row is scaled by 1/pivot and column c is
+// eliminated from every other row.  Rows never move: the lane chosen at step
+// c ends with row c of D'^{-1} in e, and sigma (the return value) is c.
+// Only the columns > c of d are still needed after step c.
+template <int M, typename T>
+__device__ __forceinline__ int gj_rows(T (&d)[M], T (&e)[M], int i, T *SP, bool &sing)
+{
+    constexpr int PR = 2 * M + kPad<T>;   // padded row stride of SP
 #pragma unroll
-    for (int r = 0; r < M; ++r) e[r] = (r == j) ? T(1) : T(0);
+    for (int l = 0; l < M; ++l) e[l] = (l == i) ? T(1) : T(0);
+    bool used = false;
+    int sigma = 0;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-        lds_put_col<M, T>(SG, j, d);
+        const int pr = group_argmax<M, T>(used ? T(-1) : tabs(d[c]), i);
+        T *row = SP + i * PR;
+#pragma unroll
+        for (int l = c; l < M; ++l) row[l] = d[l];
+#pragma unroll
+        for (int l = 0; l < M; ++l) row[M + l] = e[l];
         wave_sync();
-        T col[M];
+        const T *prow = SP + pr * PR;
+        T pd[M], pe[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) col[r] = SG[r + c * M];
-        int pr = c;
-        T best = tabs(col[c]);
+        for (int l = c; l < M; ++l) pd[l] = prow[l];
 #pragma unroll
-        for (int r = c + 1; r < M; ++r) {
-            const T v = tabs(col[r]);
-            const bool gt = v > best;
-            best = gt ? v : best;
-            pr = gt ? r : pr;
-        }
-#pragma unroll
-        for (int r = c + 1; r < M; ++r) {
-            const bool sw = (r == pr);
-            T a0 = d[c], b0 = d[r];
-            d[c] = sw ? b0 : a0;
-            d[r] = sw ? a0 : b0;
-            a0 = e[c]; b0 = e[r];
-            e[c] = sw ? b0 : a0;
-            e[r] = sw ? a0 : b0;
-            a0 = col[c]; b0 = col[r];
-            col[c] = sw ? b0 : a0;
-            col[r] = sw ? a0 : b0;
-        }
-        const T pv = col[c];
+        for (int l = 0; l < M; ++l) pe[l] = prow[M + l];
+        const T pv = pd[c];
         sing = sing || (pv == T(0));
-        const T inv = T(1) / pv;
-        const T dc = d[c] * inv, ec = e[c] * inv;
+        const T inv = recip(pv);
+        const bool isp = (i == pr);
+        const T f = isp ? -inv : d[c] * inv;
+        const T s = isp ? T(0) : T(1);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            if (r == c) continue;
-            d[r] = fma(-col[r], dc, d[r]);
-            e[r] = fma(-col[r], ec, e[r]);
-        }
-        d[c] = dc;
-        e[c] = ec;
+        for (int l = c + 1; l < M; ++l) d[l] = fma(-f, pd[l], s * d[l]);
+#pragma unroll
+        for (int l = 0; l < M; ++l) e[l] = fma(-f, pe[l], s * e[l]);
+        used = used || isp;
+        sigma = isp ? c : sigma;
         wave_sync();
     }
-    return sing;
+    return sigma;
+}
+
+// store row i of an M x M column-major FP64 block
+template <int M, typename T>
+__device__ __forceinline__ void st_row_d(double *__restrict__ blk, int i, const T (&v)[M])
+{
+#pragma unroll
+    for (int l = 0; l < M; ++l) blk[i + l * M] = (double)v[l];
 }
 
 // ---------------------------------------------------------------------------
-// Block tridiagonal factor: one level.  ADD: the diagonal blocks are the sum
+// Block tridiagonal factor: one level.  Lane i of a group holds row i of the
+// running blocks D', Z', R and alpha_1.  ADD: the diagonal blocks are the sum
 // of two arrays (the two neighbours' contributions of the level above).
 template <int M, typename T, bool ADD>
-__global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
+__device__ __forceinline__ void btri_factor_body(const LevelArgs &a, int64_t pblock)
 {
     constexpr int GPW = WG / M;
     constexpr size_t MM = (size_t)M * M;
-    const int tid = threadIdx.x, grp = tid / M, j = tid % M;
-    __shared__ __align__(16) T sA[GPW][M * M];
-    __shared__ __align__(16) T sR[GPW][M * M];
-    __shared__ __align__(16) T sG[GPW][M * M];
-    T *SA = sA[grp], *SR = sR[grp], *SG = sG[grp];
+    const int tid = threadIdx.x, grp = tid / M, i = tid % M;
+    constexpr int RS = M + kPad<T>, PR = 2 * M + kPad<T>;
+    constexpr int GS = group_stride<T>(M * PR + 2 * M * RS);
+    __shared__ __align__(16) T lds[GPW * GS];
+    T *SP = lds + grp * GS;   // Gauss-Jordan pivot rows (M x PR)
+    T *SU = SP + M * PR;      // A(g,g+1)^T, then the rows of X (M x RS)
+    T *SZ = SU + M * RS;      // Z'^T, then the rows of Zh (M x RS)
 
     const int64_t nb = a.nb;
-    const int64_t part = (int64_t)blockIdx.x * GPW + grp;
+    const int64_t part = pblock * GPW + grp;
     const Geo G = geometry<0>(nb, a.p, part);
     T *E = (T *)a.E, *R = (T *)a.R, *Zs = (T *)a.Z, *Xs = (T *)a.X;
     T *dump = (T *)a.dump + tid * M;
 
-    T d[M], z[M], rc[M], a1[M];
-    zero<M, T>(d); zero<M, T>(z); zero<M, T>(rc); zero<M, T>(a1);
+    T d[M], z[M], rr[M], a1[M];
+    zero<M, T>(d); zero<M, T>(z); zero<M, T>(rr); zero<M, T>(a1);
     if (G.valid) {
-        ld_vec<M, T>(d, a.D + G.start * MM + j * M);
-        if constexpr (ADD) add_vec<M, T>(d, a.Dadd + G.start * MM + j * M);
+        ld_row_d<M, T>(d, a.D + G.start * MM, i);
+        if constexpr (ADD) {
+            T w[M];
+            ld_row_d<M, T>(w, a.Dadd + G.start * MM, i);
+#pragma unroll
+            for (int l = 0; l < M; ++l) d[l] += w[l];
+        }
     }
     if (G.hasL) {
-        ld_vec<M, T>(z, a.Lo + (G.start - 1) * MM + j * M);   // A(g_1, sL)
-        ld_vec<M, T>(rc, a.Up + (G.start - 1) * MM + j * M);  // A(sL, g_1)
+        ld_row_d<M, T>(z, a.Lo + (G.start - 1) * MM, i);   // A(g_1, sL)
+        ld_row_d<M, T>(rr, a.Up + (G.start - 1) * MM, i);  // A(sL, g_1)
     }
-    lds_put_col<M, T>(SR, j, rc);
-    wave_sync();
     unsigned long long bad = ~0ull;
 
-    for (int k = 0; k < G.kmax; ++k) {
-        const bool act = k < G.len;
-        const int64_t g = G.start + k;
-        const bool nxt = act && (g + 1 < nb);
-        const int64_t gl = nxt ? g : 0, gd = nxt ? g + 1 : 0;
-        T up[M], lo[M], dn[M];
-        ld_vec<M, T>(up, a.Up + gl * MM + j * M);
-        ld_vec<M, T>(lo, a.Lo + gl * MM + j * M);
-        ld_vec<M, T>(dn, a.D + gd * MM + j * M);
-        if constexpr (ADD) add_vec<M, T>(dn, a.Dadd + gd * MM + j * M);
-        mask<M, T>(up, nxt);
-        mask<M, T>(lo, nxt);
-        mask<M, T>(dn, nxt);
+    // Operands of block row g that do not depend on the chain: column i of
+    // A(g,g+1), row i of A(g+1,g) and of D[g+1].  They are loaded one row
+    // ahead (before the stores of the current row), and from the zero block
+    // when they do not exist.
+    auto load_next = [&](int64_t g, bool ok, T (&upc)[M], T (&lor)[M], T (&dn)[M]) {
+        ld_vec<M, T>(upc, (ok ? a.Up + g * MM : a.zero) + i * M);
+        ld_row_d<M, T>(lor, ok ? a.Lo + g * MM : a.zero, i);
+        ld_row_d<M, T>(dn, ok ? a.D + (g + 1) * MM : a.zero, i);
+        if constexpr (ADD) {
+            T w[M];
+            ld_row_d<M, T>(w, ok ? a.Dadd + (g + 1) * MM : a.zero, i);
+#pragma unroll
+            for (int l = 0; l < M; ++l) dn[l] += w[l];
+        }
+    };
+    T upc[M], lor[M], dn[M];
+    load_next(G.start, G.len > 0 && G.start + 1 < nb, upc, lor, dn);
 
-        T e[M], dw[M];
-#pragma unroll
-        for (int r = 0; r < M; ++r) dw[r] = d[r];
-        const bool sing = gj_invert<M, T>(dw, e, j, SG);
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        T upn[M], lon[M], dnn[M];
+        load_next(g + 1, k + 1 < G.len && g + 2 < nb, upn, lon, dnn);
+
+        T e[M];
+        bool sing = false;
+        const int sig = gj_rows<M, T>(d, e, i, SP, sing);
         const unsigned long long code = status_code(a.level, g);
-        bad = (act && sing && code < bad) ? code : bad;
-        st_fac<M, T>(act ? E + g * MM + j * M : dump, e);
-        lds_put_col<M, T>(SA, j, e);
-        wave_sync();
-        T x[M], zh[M];
-        lds_gemv2<M, T>(SA, up, z, x, zh);          // X_k, Zh_k
-        st_fac<M, T>(act ? Xs + g * MM + j * M : dump, x);
-        st_fac<M, T>(act ? Zs + g * MM + j * M : dump, zh);
-        T t1[M], rn[M];
-        lds_gemv2<M, T>(SR, zh, x, t1, rn);         // R_k Zh_k, R_k X_k
-        st_fac<M, T>((act && G.hasL) ? R + g * MM + j * M : dump, rc);
+        bad = (sing && code < bad) ? code : bad;
+        st_fac<M, T>(E + g * MM + sig * M, e);             // row sig of E_k
+        st_fac<M, T>(G.hasL ? R + g * MM + i * M : dump, rr);   // row i of R_k
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            a1[r] = act ? a1[r] - t1[r] : a1[r];
-            rc[r] = act ? -rn[r] : rc[r];
+        for (int l = 0; l < M; ++l) {
+            SU[i * RS + l] = upc[l];                       // row i of A(g,g+1)^T
+            SZ[l * RS + i] = z[l];                         // column i of Z'^T
         }
         wave_sync();
-        lds_put_col<M, T>(SR, j, rc);
-        lds_put_col<M, T>(SA, j, lo);
-        wave_sync();
-        T dl[M], zl[M];
-        lds_gemv2<M, T>(SA, x, zh, dl, zl);         // Lo X_k, Lo Zh_k
+        T x[M], zh[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            d[r] = act ? dn[r] - dl[r] : d[r];
-            z[r] = act ? -zl[r] : z[r];
+        for (int c = 0; c < M; ++c) {                      // row sig of X_k and Zh_k
+            T sx = T(0), sz = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                sx = fma(e[l], SU[c * RS + l], sx);
+                sz = fma(e[l], SZ[c * RS + l], sz);
+            }
+            x[c] = sx;
+            zh[c] = sz;
+        }
+        st_fac<M, T>(Xs + g * MM + sig * M, x);
+        st_fac<M, T>(Zs + g * MM + sig * M, zh);
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            SU[sig * RS + c] = x[c];
+            SZ[sig * RS + c] = zh[c];
+        }
+        wave_sync();
+        T rn[M], t1[M], dl[M], zl[M];
+        zero<M, T>(rn); zero<M, T>(t1); zero<M, T>(dl); zero<M, T>(zl);
+#pragma unroll
+        for (int l = 0; l < M; ++l) {                      // R_k X_k, R_k Zh_k, Lo X_k, Lo Zh_k
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const T xv = SU[l * RS + c], zv = SZ[l * RS + c];
+                rn[c] = fma(rr[l], xv, rn[c]);
+                t1[c] = fma(rr[l], zv, t1[c]);
+                dl[c] = fma(lor[l], xv, dl[c]);
+                zl[c] = fma(lor[l], zv, zl[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            a1[c] -= t1[c];
+            rr[c] = -rn[c];
+            d[c] = dn[c] - dl[c];
+            z[c] = -zl[c];
+            upc[c] = upn[c];
+            lor[c] = lon[c];
+            dn[c] = dnn[c];
         }
         wave_sync();
     }
@@ -361,24 +480,12 @@ __global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
     // contributions to the reduced matrix (eq. (redmatr)); separator j sits
     // between partitions j and j+1
     if (G.hasR) {
-        double *o = a.nD + part * MM + j * M;
-#pragma unroll
-        for (int r = 0; r < M; ++r) o[r] = (double)d[r];        // D[sR] + alpha_2
-        if (G.hasL) {
-            double *ob = a.nLo + (part - 1) * MM + j * M;
-#pragma unroll
-            for (int r = 0; r < M; ++r) ob[r] = (double)z[r];   // beta
-        }
+        st_row_d<M, T>(a.nD + part * MM, i, d);                    // D[sR] + alpha_2
+        if (G.hasL) st_row_d<M, T>(a.nLo + (part - 1) * MM, i, z); // beta
     }
     if (G.hasL) {
-        double *oa = a.nDadd + (part - 1) * MM + j * M;
-#pragma unroll
-        for (int r = 0; r < M; ++r) oa[r] = (double)a1[r];      // alpha_1
-        if (G.hasR) {
-            double *og = a.nUp + (part - 1) * MM + j * M;
-#pragma unroll
-            for (int r = 0; r < M; ++r) og[r] = (double)rc[r];  // gamma
-        }
+        st_row_d<M, T>(a.nDadd + (part - 1) * MM, i, a1);          // alpha_1
+        if (G.hasR) st_row_d<M, T>(a.nUp + (part - 1) * MM, i, rr); // gamma
     }
 }
 
@@ -388,68 +495,86 @@ __global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
 // reduced matrix (eq. (redmatr1) with gamma = 0) has the same form:
 // diagonal D[s_i], sub-diagonal beta, corner unchanged.
 template <int M, typename T>
-__global__ __launch_bounds__(WG) void k_babd_factor(LevelArgs a)
+__device__ __forceinline__ void babd_factor_body(const LevelArgs &a, int64_t pblock)
 {
     constexpr int GPW = WG / M;
     constexpr size_t MM = (size_t)M * M;
-    const int tid = threadIdx.x, grp = tid / M, j = tid % M;
-    __shared__ __align__(16) T sA[GPW][M * M];
-    __shared__ __align__(16) T sG[GPW][M * M];
-    T *SA = sA[grp], *SG = sG[grp];
+    const int tid = threadIdx.x, grp = tid / M, i = tid % M;
+    constexpr int RS = M + kPad<T>, PR = 2 * M + kPad<T>;
+    constexpr int GS = group_stride<T>(M * PR + M * RS);
+    __shared__ __align__(16) T lds[GPW * GS];
+    T *SP = lds + grp * GS;   // Gauss-Jordan pivot rows
+    T *SZ = SP + M * PR;      // Z'^T, then the rows of Zh
 
-    const int64_t part = (int64_t)blockIdx.x * GPW + grp;
+    const int64_t part = pblock * GPW + grp;
     const Geo G = geometry<1>(a.nb, a.p, part);
     T *E = (T *)a.E, *Zs = (T *)a.Z;
-    T *dump = (T *)a.dump + tid * M;
 
     T z[M];
     zero<M, T>(z);
-    if (G.valid) ld_vec<M, T>(z, a.Lo + (G.start - 1) * MM + j * M);   // A(g_1, sL)
+    if (G.valid) ld_row_d<M, T>(z, a.Lo + (G.start - 1) * MM, i);   // A(g_1, sL)
     unsigned long long bad = ~0ull;
 
-    for (int k = 0; k < G.kmax; ++k) {
-        const bool act = k < G.len;
+    // rows i of D[g] and A(g+1,g), loaded one block row ahead
+    T dc[M], lc[M];
+    ld_row_d<M, T>(dc, G.len > 0 ? a.D + G.start * MM : a.zero, i);
+    ld_row_d<M, T>(lc, G.len > 0 ? a.Lo + G.start * MM : a.zero, i);
+    for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
-        const int64_t gc = act ? g : 0;
-        T d[M], lo[M];
-        ld_vec<M, T>(d, a.D + gc * MM + j * M);
-        ld_vec<M, T>(lo, a.Lo + gc * MM + j * M);                      // A(g+1, g)
+        const bool more = k + 1 < G.len;
+        T d[M], lor[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            d[l] = dc[l];
+            lor[l] = lc[l];
+        }
+        ld_row_d<M, T>(dc, more ? a.D + (g + 1) * MM : a.zero, i);
+        ld_row_d<M, T>(lc, more ? a.Lo + (g + 1) * MM : a.zero, i);
         T e[M];
-        const bool sing = gj_invert<M, T>(d, e, j, SG);
+        bool sing = false;
+        const int sig = gj_rows<M, T>(d, e, i, SP, sing);
         const unsigned long long code = status_code(a.level, g);
-        bad = (act && sing && code < bad) ? code : bad;
-        st_fac<M, T>(act ? E + g * MM + j * M : dump, e);
-        lds_put_col<M, T>(SA, j, e);
+        bad = (sing && code < bad) ? code : bad;
+        st_fac<M, T>(E + g * MM + sig * M, e);
+#pragma unroll
+        for (int l = 0; l < M; ++l) SZ[l * RS + i] = z[l];   // column i of Z'^T
         wave_sync();
         T zh[M];
-        lds_gemv<M, T>(SA, z, zh);                  // Zh_k = E_k Z'_k
-        st_fac<M, T>(act ? Zs + g * MM + j * M : dump, zh);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            T s = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) s = fma(e[l], SZ[c * RS + l], s);
+            zh[c] = s;
+        }
+        st_fac<M, T>(Zs + g * MM + sig * M, zh);
         wave_sync();
-        lds_put_col<M, T>(SA, j, lo);
+#pragma unroll
+        for (int c = 0; c < M; ++c) SZ[sig * RS + c] = zh[c];
         wave_sync();
         T zl[M];
-        lds_gemv<M, T>(SA, zh, zl);                 // A(g+1,g) Zh_k
+        zero<M, T>(zl);
 #pragma unroll
-        for (int r = 0; r < M; ++r) z[r] = act ? -zl[r] : z[r];
+        for (int l = 0; l < M; ++l)
+#pragma unroll
+            for (int c = 0; c < M; ++c) zl[c] = fma(lor[l], SZ[l * RS + c], zl[c]);
+#pragma unroll
+        for (int c = 0; c < M; ++c) z[c] = -zl[c];
         wave_sync();
     }
     if (bad != ~0ull) atomicMin(a.status, bad);
     if (G.valid) {
         const int64_t sR = G.start + G.len;
-        double *ob = a.nLo + part * MM + j * M;
-#pragma unroll
-        for (int r = 0; r < M; ++r) ob[r] = (double)z[r];                // beta
-        const double *ds = a.D + sR * MM + j * M;
-        double *od = a.nD + (part + 1) * MM + j * M;
+        st_row_d<M, T>(a.nLo + part * MM, i, z);                     // beta
+        const double *ds = a.D + sR * MM + i * M;                    // copy column i
+        double *od = a.nD + (part + 1) * MM + i * M;
 #pragma unroll
         for (int r = 0; r < M; ++r) od[r] = ds[r];
         if (part == 0) {
-            double *o0 = a.nD + j * M;
-            double *oc = a.nC + j * M;
 #pragma unroll
             for (int r = 0; r < M; ++r) {
-                o0[r] = a.D[j * M + r];
-                oc[r] = a.C[j * M + r];
+                a.nD[i * M + r] = a.D[i * M + r];
+                a.nC[i * M + r] = a.C[i * M + r];
             }
         }
     }
@@ -460,16 +585,18 @@ __global__ __launch_bounds__(WG) void k_babd_factor(LevelArgs a)
 // Lane i owns row i of KC right-hand-side columns.  ADD: the right-hand side
 // is the sum of two arrays (reduced levels of block tridiagonal matrices).
 template <int KIND, int M, int KC, typename T, bool ADD>
-__global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
+__device__ __forceinline__ void fwd_body(const SolveArgs &a, int64_t pblock, int cblock)
 {
     constexpr int GPW = WG / M;
     constexpr size_t MM = (size_t)M * M;
     const int tid = threadIdx.x, grp = tid / M, i = tid % M;
-    __shared__ __align__(16) T sV[GPW][KC * M];
-    T *SV = sV[grp];
-    const int64_t part = (int64_t)blockIdx.x * GPW + grp;
+    constexpr int CS = M + kPad<T>;                   // padded column stride
+    constexpr int GS = group_stride<T>(KC * CS);
+    __shared__ __align__(16) T lds[GPW * GS];
+    T *SV = lds + grp * GS;                           // M x KC block vector, by columns
+    const int64_t part = pblock * GPW + grp;
     const Geo G = geometry<KIND>(a.nb, a.p, part);
-    const int c0 = blockIdx.y * KC;
+    const int c0 = cblock * KC;
     const int kc = (a.nrhs - c0) < KC ? (a.nrhs - c0) : KC;
     const T *E = (const T *)a.E, *R = (const T *)a.R;
     double *dump = a.dump + tid;
@@ -483,62 +610,74 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
     for (int c = 0; c < KC; ++c) {
         fp[c] = T(0);
         gl[c] = T(0);
-        if (G.valid && c < kc) {
+        if (G.valid) {
             double v = a.F[G.start * M + i + col[c] * a.ldf];
             if constexpr (ADD) v += a.Fadd[G.start * M + i + col[c] * a.ldf];
             fp[c] = (T)v;
         }
     }
-    for (int k = 0; k < G.kmax; ++k) {
-        const bool act = k < G.len;
-        const int64_t g = G.start + k;
-        const bool nxt = act && (g + 1 < a.nb);
-        const int64_t ge = act ? g : 0, gn = nxt ? g : 0;
-        T er[M], lr[M], rr[M], fn[KC];
-        ld_row<M, T>(er, E + ge * MM, i);
-        ld_row_d<M, T>(lr, a.Lo + gn * MM, i);
-        if constexpr (KIND == 0) {
-            ld_row<M, T>(rr, R + ((act && G.hasL) ? g : 0) * MM, i);
-            mask<M, T>(rr, act && G.hasL);
-        }
-        mask<M, T>(lr, nxt);
+    // Row i of E_g, R_g and A(g+1,g) and row i of the next right-hand side,
+    // loaded one block row ahead (before the current row's stores); missing
+    // operands come from the zero block.
+    const T *zt = (const T *)a.zero + i * M;
+    auto load_row = [&](int64_t g, bool ok, T (&er)[M], T (&rr)[M], T (&lr)[M], T (&fn)[KC]) {
+        const bool nx = ok && (g + 1 < a.nb);
+        ld_fac<M, T>(er, ok ? E + g * MM + i * M : zt);
+        if constexpr (KIND == 0) ld_fac<M, T>(rr, (ok && G.hasL) ? R + g * MM + i * M : zt);
+        ld_row_d<M, T>(lr, nx ? a.Lo + g * MM : a.zero, i);
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
-            double v = a.F[(gn + (nxt ? 1 : 0)) * M + i + col[c] * a.ldf];
-            if constexpr (ADD) v += a.Fadd[(gn + (nxt ? 1 : 0)) * M + i + col[c] * a.ldf];
-            fn[c] = nxt ? (T)v : T(0);
+            const int64_t o = (g + 1) * M + i + col[c] * a.ldf;
+            double v = *(nx ? a.F + o : a.zero);
+            if constexpr (ADD) v += *(nx ? a.Fadd + o : a.zero);
+            fn[c] = (T)v;
+        }
+    };
+    T ec[M], rc[M], lc[M], fc[KC];
+    load_row(G.start, G.len > 0, ec, rc, lc, fc);
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        T er[M], lr[M], rr[M], fn[KC];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            er[l] = ec[l];
+            lr[l] = lc[l];
+            if constexpr (KIND == 0) rr[l] = rc[l];
         }
 #pragma unroll
-        for (int c = 0; c < KC; ++c) SV[i + c * M] = fp[c];
+        for (int c = 0; c < KC; ++c) fn[c] = fc[c];
+        load_row(g + 1, k + 1 < G.len, ec, rc, lc, fc);
+#pragma unroll
+        for (int c = 0; c < KC; ++c) SV[i + c * CS] = fp[c];
         wave_sync();
         T t[KC];
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             T s = T(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) s = fma(er[l], SV[l + c * M], s);
+            for (int l = 0; l < M; ++l) s = fma(er[l], SV[l + c * CS], s);
             t[c] = s;
         }
         wave_sync();
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
-            double *dst = (act && c < kc) ? a.Y + g * M + i + col[c] * a.ldy : dump;
+            double *dst = (c < kc) ? a.Y + g * M + i + col[c] * a.ldy : dump;
             *dst = (double)t[c];
         }
 #pragma unroll
-        for (int c = 0; c < KC; ++c) SV[i + c * M] = t[c];
+        for (int c = 0; c < KC; ++c) SV[i + c * CS] = t[c];
         wave_sync();
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             T sl = T(0), sr = T(0);
 #pragma unroll
             for (int l = 0; l < M; ++l) {
-                const T tv = SV[l + c * M];
+                const T tv = SV[l + c * CS];
                 sl = fma(lr[l], tv, sl);
                 if constexpr (KIND == 0) sr = fma(rr[l], tv, sr);
             }
-            fp[c] = act ? fn[c] - sl : fp[c];
-            if constexpr (KIND == 0) gl[c] = act ? gl[c] - sr : gl[c];
+            fp[c] = fn[c] - sl;
+            if constexpr (KIND == 0) gl[c] -= sr;
         }
         wave_sync();
     }
@@ -559,17 +698,19 @@ __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
 // ---------------------------------------------------------------------------
 // Back substitution (the G solve / the parallel updates of eq. (pups)).
 template <int KIND, int M, int KC, typename T>
-__global__ __launch_bounds__(WG) void k_bwd(SolveArgs a)
+__device__ __forceinline__ void bwd_body(const SolveArgs &a, int64_t pblock, int cblock)
 {
     constexpr int GPW = WG / M;
     constexpr size_t MM = (size_t)M * M;
     const int tid = threadIdx.x, grp = tid / M, i = tid % M;
-    __shared__ __align__(16) T sV[GPW][KC * M];
-    __shared__ __align__(16) T sL[GPW][KC * M];
-    T *SV = sV[grp], *SL = sL[grp];
-    const int64_t part = (int64_t)blockIdx.x * GPW + grp;
+    constexpr int CS = M + kPad<T>;                   // padded column stride
+    constexpr int GS = group_stride<T>(2 * KC * CS);
+    __shared__ __align__(16) T lds[GPW * GS];
+    T *SV = lds + grp * GS;                           // x of the row below (M x KC)
+    T *SL = SV + KC * CS;                             // x at the left separator
+    const int64_t part = pblock * GPW + grp;
     const Geo G = geometry<KIND>(a.nb, a.p, part);
-    const int c0 = blockIdx.y * KC;
+    const int c0 = cblock * KC;
     const int kc = (a.nrhs - c0) < KC ? (a.nrhs - c0) : KC;
     const T *Zs = (const T *)a.Z, *Xs = (const T *)a.X;
     double *dump = a.dump + tid;
@@ -595,39 +736,89 @@ __global__ __launch_bounds__(WG) void k_bwd(SolveArgs a)
             }
             if (KIND == 1 && G.valid && part == 0) a.Y[i + col[c] * a.ldy] = a.Xsep[i + cn];
         }
-        SL[i + c * M] = xl;
-        SV[i + c * M] = xr;
+        SL[i + c * CS] = xl;
+        SV[i + c * CS] = xr;
     }
     wave_sync();
-    for (int k = G.kmax - 1; k >= 0; --k) {
-        const bool act = k < G.len;
+    for (int k = G.len - 1; k >= 0; --k) {
         const int64_t g = G.start + k;
-        const int64_t ge = act ? g : 0;
         T zr[M], xrw[M], t[KC];
-        ld_row<M, T>(zr, Zs + ge * MM, i);
-        if constexpr (KIND == 0) ld_row<M, T>(xrw, Xs + ge * MM, i);
+        ld_fac<M, T>(zr, Zs + g * MM + i * M);
+        if constexpr (KIND == 0) ld_fac<M, T>(xrw, Xs + g * MM + i * M);
 #pragma unroll
-        for (int c = 0; c < KC; ++c) t[c] = (T)a.Y[ge * M + i + col[c] * a.ldy];
+        for (int c = 0; c < KC; ++c) t[c] = (T)a.Y[g * M + i + col[c] * a.ldy];
         T xk[KC];
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             T s = t[c];
 #pragma unroll
             for (int l = 0; l < M; ++l) {
-                s = fma(-zr[l], SL[l + c * M], s);
-                if constexpr (KIND == 0) s = fma(-xrw[l], SV[l + c * M], s);
+                s = fma(-zr[l], SL[l + c * CS], s);
+                if constexpr (KIND == 0) s = fma(-xrw[l], SV[l + c * CS], s);
             }
             xk[c] = s;
         }
         if constexpr (KIND == 0) wave_sync();
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
-            double *dst = (act && c < kc) ? a.Y + g * M + i + col[c] * a.ldy : dump;
+            double *dst = (c < kc) ? a.Y + g * M + i + col[c] * a.ldy : dump;
             *dst = (double)xk[c];
-            if constexpr (KIND == 0) SV[i + c * M] = act ? xk[c] : SV[i + c * M];
+            if constexpr (KIND == 0) SV[i + c * CS] = xk[c];
         }
         if constexpr (KIND == 0) wave_sync();
     }
+}
+
+// ---- kernels: one system (the grid covers its partitions) and batched (a
+// table of per-system arguments and a work list whose entry w says: system
+// table[w.x], partition block w.y, right-hand-side block w.z) -----------------
+template <int M, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void k_btri_factor(LevelArgs a)
+{
+    btri_factor_body<M, T, ADD>(a, blockIdx.x);
+}
+template <int M, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void kb_btri_factor(const LevelArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    btri_factor_body<M, T, ADD>(a, w.y);
+}
+template <int M, typename T>
+__global__ __launch_bounds__(WG) void k_babd_factor(LevelArgs a)
+{
+    babd_factor_body<M, T>(a, blockIdx.x);
+}
+template <int M, typename T>
+__global__ __launch_bounds__(WG) void kb_babd_factor(const LevelArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    babd_factor_body<M, T>(a, w.y);
+}
+template <int KIND, int M, int KC, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
+{
+    fwd_body<KIND, M, KC, T, ADD>(a, blockIdx.x, blockIdx.y);
+}
+template <int KIND, int M, int KC, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void kb_fwd(const SolveArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const SolveArgs a = tab[w.x];
+    fwd_body<KIND, M, KC, T, ADD>(a, w.y, w.z);
+}
+template <int KIND, int M, int KC, typename T>
+__global__ __launch_bounds__(WG) void k_bwd(SolveArgs a)
+{
+    bwd_body<KIND, M, KC, T>(a, blockIdx.x, blockIdx.y);
+}
+template <int KIND, int M, int KC, typename T>
+__global__ __launch_bounds__(WG) void kb_bwd(const SolveArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const SolveArgs a = tab[w.x];
+    bwd_body<KIND, M, KC, T>(a, w.y, w.z);
 }
 
 template <typename F>
@@ -644,6 +835,12 @@ hipError_t dispatch_M(int M, F &&f)
     }
 }
 
+template <typename F>
+hipError_t dispatch_KC(int KC, F &&f)
+{
+    return KC == 1 ? f(std::integral_constant<int, 1>{}) : f(std::integral_constant<int, 4>{});
+}
+
 inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)
 {
     const int64_t gpw = WG / M;
@@ -651,6 +848,9 @@ inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)
 }
 
 }  // namespace
+
+int groups_per_wg(int M) { return WG / M; }
+int rhs_chunk(int nrhs) { return nrhs == 1 ? 1 : 4; }
 
 hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s)
 {
@@ -679,13 +879,25 @@ hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
     });
 }
 
-template <int KIND, int M, int KC, typename T>
-static void launch_fwd_kernel(const SolveArgs &a, dim3 grid, hipStream_t s)
+hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, const LevelArgs *tab,
+                               const int4 *work, int nwg, hipStream_t s)
 {
-    if (KIND == 0 && a.Fadd)
-        hipLaunchKernelGGL((k_fwd<KIND, M, KC, T, true>), grid, dim3(WG), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_fwd<KIND, M, KC, T, false>), grid, dim3(WG), 0, s, a);
+    if (nwg <= 0) return hipSuccess;
+    return dispatch_M(M, [&](auto mc) {
+        constexpr int MV = decltype(mc)::value;
+        const dim3 grid(nwg);
+        if (kind == 1) {
+            if (f32) hipLaunchKernelGGL((kb_babd_factor<MV, float>), grid, dim3(WG), 0, s, tab, work);
+            else hipLaunchKernelGGL((kb_babd_factor<MV, double>), grid, dim3(WG), 0, s, tab, work);
+        } else if (add) {
+            if (f32) hipLaunchKernelGGL((kb_btri_factor<MV, float, true>), grid, dim3(WG), 0, s, tab, work);
+            else hipLaunchKernelGGL((kb_btri_factor<MV, double, true>), grid, dim3(WG), 0, s, tab, work);
+        } else {
+            if (f32) hipLaunchKernelGGL((kb_btri_factor<MV, float, false>), grid, dim3(WG), 0, s, tab, work);
+            else hipLaunchKernelGGL((kb_btri_factor<MV, double, false>), grid, dim3(WG), 0, s, tab, work);
+        }
+        return hipGetLastError();
+    });
 }
 
 template <int KIND, bool FWD>
@@ -693,26 +905,24 @@ static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t 
 {
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
-        if (a.nrhs == 1) {
-            const dim3 grid = grid_for(MV, a.p, a.nrhs, 1);
+        return dispatch_KC(rhs_chunk(a.nrhs), [&](auto kcc) {
+            constexpr int KC = decltype(kcc)::value;
+            const dim3 grid = grid_for(MV, a.p, a.nrhs, KC);
+            const bool add = KIND == 0 && a.Fadd;
             if (FWD) {
-                if (f32) launch_fwd_kernel<KIND, MV, 1, float>(a, grid, s);
-                else launch_fwd_kernel<KIND, MV, 1, double>(a, grid, s);
+                if (add) {
+                    if (f32) hipLaunchKernelGGL((k_fwd<KIND, MV, KC, float, true>), grid, dim3(WG), 0, s, a);
+                    else hipLaunchKernelGGL((k_fwd<KIND, MV, KC, double, true>), grid, dim3(WG), 0, s, a);
+                } else {
+                    if (f32) hipLaunchKernelGGL((k_fwd<KIND, MV, KC, float, false>), grid, dim3(WG), 0, s, a);
+                    else hipLaunchKernelGGL((k_fwd<KIND, MV, KC, double, false>), grid, dim3(WG), 0, s, a);
+                }
             } else {
-                if (f32) hipLaunchKernelGGL((k_bwd<KIND, MV, 1, float>), grid, dim3(WG), 0, s, a);
-                else hipLaunchKernelGGL((k_bwd<KIND, MV, 1, double>), grid, dim3(WG), 0, s, a);
+                if (f32) hipLaunchKernelGGL((k_bwd<KIND, MV, KC, float>), grid, dim3(WG), 0, s, a);
+                else hipLaunchKernelGGL((k_bwd<KIND, MV, KC, double>), grid, dim3(WG), 0, s, a);
             }
-        } else {
-            const dim3 grid = grid_for(MV, a.p, a.nrhs, 4);
-            if (FWD) {
-                if (f32) launch_fwd_kernel<KIND, MV, 4, float>(a, grid, s);
-                else launch_fwd_kernel<KIND, MV, 4, double>(a, grid, s);
-            } else {
-                if (f32) hipLaunchKernelGGL((k_bwd<KIND, MV, 4, float>), grid, dim3(WG), 0, s, a);
-                else hipLaunchKernelGGL((k_bwd<KIND, MV, 4, double>), grid, dim3(WG), 0, s, a);
-            }
-        }
-        return hipGetLastError();
+            return hipGetLastError();
+        });
     });
 }
 
@@ -731,6 +941,41 @@ hipError_t launch_babd_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s)
 hipError_t launch_babd_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s)
 {
     return launch_solve<1, false>(M, f32, a, s);
+}
+
+template <int KIND>
+static hipError_t launch_solve_batch_k(bool fwd, int M, bool f32, bool add, int KC,
+                                       const SolveArgs *tab, const int4 *work, int nwg,
+                                       hipStream_t s)
+{
+    return dispatch_M(M, [&](auto mc) {
+        constexpr int MV = decltype(mc)::value;
+        return dispatch_KC(KC, [&](auto kcc) {
+            constexpr int K = decltype(kcc)::value;
+            const dim3 grid(nwg);
+            if (fwd) {
+                if (KIND == 0 && add) {
+                    if (f32) hipLaunchKernelGGL((kb_fwd<KIND, MV, K, float, true>), grid, dim3(WG), 0, s, tab, work);
+                    else hipLaunchKernelGGL((kb_fwd<KIND, MV, K, double, true>), grid, dim3(WG), 0, s, tab, work);
+                } else {
+                    if (f32) hipLaunchKernelGGL((kb_fwd<KIND, MV, K, float, false>), grid, dim3(WG), 0, s, tab, work);
+                    else hipLaunchKernelGGL((kb_fwd<KIND, MV, K, double, false>), grid, dim3(WG), 0, s, tab, work);
+                }
+            } else {
+                if (f32) hipLaunchKernelGGL((kb_bwd<KIND, MV, K, float>), grid, dim3(WG), 0, s, tab, work);
+                else hipLaunchKernelGGL((kb_bwd<KIND, MV, K, double>), grid, dim3(WG), 0, s, tab, work);
+            }
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_solve_batch(int kind, bool fwd, int M, bool f32, bool add, int KC,
+                              const SolveArgs *tab, const int4 *work, int nwg, hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    return kind == 0 ? launch_solve_batch_k<0>(fwd, M, f32, add, KC, tab, work, nwg, s)
+                     : launch_solve_batch_k<1>(fwd, M, f32, add, KC, tab, work, nwg, s);
 }
 
 }  // namespace pf

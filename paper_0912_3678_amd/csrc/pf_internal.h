@@ -29,12 +29,16 @@ struct LevelArgs {
     double *nC;            // next level: corner (BABD)
     unsigned long long *status;  // packed (level << 40 | block); atomicMin
     void *dump;            // kDumpBytes of scratch that masked stores write into
+    const double *zero;    // kZeroBytes of zeros: the target of out-of-range loads
     int level;
 };
 
-// Device scratch that receives the stores of inactive loop iterations (the
-// kernels keep every memory operation of a chain loop unconditional).
+// Device scratch that receives the stores a lane must not make, and a block
+// of zeros that out-of-range loads read instead of real data: the chain
+// loops keep every memory operation unconditional and select nothing after a
+// load, so their wait counters stay exact.
 constexpr size_t kDumpBytes = 64 * 1024;
+constexpr size_t kZeroBytes = 16 * 1024;   // >= one 32 x 32 FP64 block
 
 // One level of a solve.
 struct SolveArgs {
@@ -52,6 +56,7 @@ struct SolveArgs {
     int64_t ldn;
     const double *Xsep;    // backward: next level's solution (ld ldn)
     double *dump;          // kDumpBytes of scratch for masked stores
+    const double *zero;    // kZeroBytes of zeros
 };
 
 // Launchers (kernels.hip).  M must be 1, 2, 4, 8, 16 or 32.
@@ -61,6 +66,18 @@ hipError_t launch_btri_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s);
 hipError_t launch_babd_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_babd_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
+
+// Batched launches: one launch serves every entry of a device table; work[w]
+// = (table entry, partition block, right-hand-side block, unused) for
+// workgroup w.  A partition block is groups_per_wg(M) partitions; a
+// right-hand-side block is rhs_chunk(nrhs) columns.  Entries of one launch
+// share kind, M, precision, the ADD variant and (solves) the chunk size.
+int groups_per_wg(int M);
+int rhs_chunk(int nrhs);
+hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, const LevelArgs *tab,
+                               const int4 *work, int nwg, hipStream_t s);
+hipError_t launch_solve_batch(int kind, bool fwd, int M, bool f32, bool add, int KC,
+                              const SolveArgs *tab, const int4 *work, int nwg, hipStream_t s);
 
 // Utility kernels (kernels_util.hip).
 // Copy m x m blocks into M x M blocks (M >= m); the extra diagonal entries

@@ -23,6 +23,7 @@ EXPORTED = [
     "pf_sync_status", "pf_destroy", "pf_strerror", "pf_factor_levels", "pf_factor_level",
     "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
     "pf_plan", "pf_refactor", "pf_profile_enable", "pf_profile_read",
+    "pf_batch_create", "pf_batch_run", "pf_batch_factor", "pf_batch_destroy",
 ]
 
 
@@ -35,7 +36,7 @@ class pf_matrix(ctypes.Structure):
 class pf_opts(ctypes.Structure):
     _fields_ = [("partitions", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("block_rows", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("coarse_rows", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
 
 
@@ -81,6 +82,11 @@ def load(path: str = LIB_PATH):
         "pf_factor_export_reduced": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "pf_band_to_btri": (ctypes.c_int, [i64, i32, i32, vp, i64, vp, vp, vp, vp]),
         "pf_abd_to_btri": (ctypes.c_int, [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "pf_batch_create": (ctypes.c_int, [i32, P(pf_matrix), P(pf_opts), P(i32), P(vp), P(i64),
+                                           P(vp), P(i64), vp, P(vp)]),
+        "pf_batch_run": (ctypes.c_int, [vp, vp, P(pf_info)]),
+        "pf_batch_factor": (ctypes.c_int, [vp, i32, P(vp)]),
+        "pf_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -120,8 +126,9 @@ def make_matrix(kind, m, nb, D, Lo, Up=None, C=None) -> pf_matrix:
                      _ptr(C).value if C is not None else None)
 
 
-def make_opts(partitions=0, prec=PF_FP64, max_refine=0, block_rows=0, flags=0, tol=0.0):
-    return pf_opts(partitions, prec, max_refine, block_rows, flags, 0, tol)
+def make_opts(partitions=0, prec=PF_FP64, max_refine=0, block_rows=0, flags=0, tol=0.0,
+              coarse_rows=0):
+    return pf_opts(partitions, prec, max_refine, block_rows, flags, coarse_rows, tol)
 
 
 def pf_factor(A: pf_matrix, opts: pf_opts | None = None, stream=None):
@@ -255,12 +262,7 @@ def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False):
     """mats: list of pf_matrix; fs/xs: lists of device tensors (nrhs_i, n_i)."""
     lib = load()
     ns = len(mats)
-    A = (pf_matrix * ns)(*mats)
-    nr = (ctypes.c_int32 * ns)(*nrhs)
-    fp = (ctypes.c_void_p * ns)(*[f.data_ptr() for f in fs])
-    xp = (ctypes.c_void_p * ns)(*[x.data_ptr() for x in xs])
-    lf = (ctypes.c_int64 * ns)(*[f.shape[-1] for f in fs])
-    lx = (ctypes.c_int64 * ns)(*[x.shape[-1] for x in xs])
+    A, nr, fp, lf, xp, lx = _batch_arrays(mats, nrhs, fs, xs)
     fac = (ctypes.c_void_p * ns)() if keep_factors else None
     infos = (pf_info * ns)()
     rc = lib.pf_solve_batch(ns, A, ctypes.byref(opts) if opts is not None else None, nr, fp, lf,
@@ -268,3 +270,53 @@ def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False):
     if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
         raise PFError(rc, "pf_solve_batch")
     return list(infos), (list(fac) if keep_factors else None)
+
+
+def _batch_arrays(mats, nrhs, fs, xs):
+    ns = len(mats)
+    A = (pf_matrix * ns)(*mats)
+    nr = (ctypes.c_int32 * ns)(*nrhs)
+    fp = (ctypes.c_void_p * ns)(*[f.data_ptr() for f in fs])
+    xp = (ctypes.c_void_p * ns)(*[x.data_ptr() for x in xs])
+    lf = (ctypes.c_int64 * ns)(*[f.shape[-1] for f in fs])
+    lx = (ctypes.c_int64 * ns)(*[x.shape[-1] for x in xs])
+    return A, nr, fp, lf, xp, lx
+
+
+class Batch:
+    """pf_batch_create / pf_batch_run / pf_batch_factor / pf_batch_destroy.
+
+    mats: list of pf_matrix; fs/xs: device tensors (nrhs_i, n_i) per system
+    (the batch keeps their pointers: keep the tensors alive)."""
+
+    def __init__(self, mats, opts, nrhs, fs, xs, stream=None):
+        lib = load()
+        self.n = len(mats)
+        self._keep = (mats, fs, xs)
+        self._arrays = _batch_arrays(mats, nrhs, fs, xs)
+        h = ctypes.c_void_p()
+        rc = lib.pf_batch_create(self.n, *self._arrays[:1],
+                                 ctypes.byref(opts) if opts is not None else None,
+                                 *self._arrays[1:], _stream(stream), ctypes.byref(h))
+        if rc != 0:
+            raise PFError(rc, "pf_batch_create")
+        self.h = h
+
+    def run(self, stream=None, want_info=True):
+        infos = (pf_info * self.n)() if want_info else None
+        rc = load().pf_batch_run(self.h, _stream(stream), infos)
+        if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
+            raise PFError(rc, "pf_batch_run")
+        return list(infos) if want_info else None
+
+    def factor(self, i):
+        out = ctypes.c_void_p()
+        rc = load().pf_batch_factor(self.h, i, ctypes.byref(out))
+        if rc != 0:
+            raise PFError(rc, "pf_batch_factor")
+        return out
+
+    def destroy(self):
+        if self.h:
+            load().pf_batch_destroy(self.h)
+            self.h = None

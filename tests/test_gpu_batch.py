@@ -1,0 +1,219 @@
+"""GPU parity of batched solves: many independent systems in one set of
+launches, recorded into a HIP graph and replayed.
+
+Every system of a batch runs the same per-partition work as when it is
+solved alone (same plan, same kernels' arithmetic), so batch results must
+equal the single-system results bit for bit; each is also held to the
+oracle's acceptance bounds."""
+import numpy as np
+import pytest
+
+from paper_0912_3678_amd import pf
+from paper_0912_3678_amd import workloads as wl
+
+from . import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _systems(specs):
+    """specs: (kind, m, nb, nrhs, seed) -> list of (System, f (nrhs, n))."""
+    out = []
+    for kind, m, nb, k, seed in specs:
+        s = wl.random_btri(nb, m, seed=seed) if kind == "btri" else wl.random_babd(nb, m, seed=seed)
+        rng = np.random.default_rng(seed + 1)
+        f = rng.standard_normal((k, nb * m)) if k else np.zeros((0, nb * m))
+        out.append((s, f))
+    return out
+
+
+def _device(systems):
+    import torch
+    mats, keep, fs, xs = [], [], [], []
+    for s, f in systems:
+        A, kp = G.to_device(s)
+        mats.append(A)
+        keep.append(kp)
+        fd = torch.tensor(np.ascontiguousarray(f), dtype=torch.float64, device=G.device())
+        if fd.shape[0] == 0:
+            fd = torch.zeros((0, s.nb * s.m), dtype=torch.float64, device=G.device())
+        fs.append(fd)
+        xs.append(torch.full_like(fd, np.nan))
+    return mats, keep, fs, xs
+
+
+def _alone(A, fd, opts):
+    import torch
+    x = torch.full_like(fd, np.nan)
+    F = pf.pf_factor(A, opts)
+    try:
+        if fd.shape[0]:
+            pf.pf_solve(F, fd, x)
+        torch.cuda.synchronize()
+    finally:
+        pf.pf_destroy(F)
+    return x
+
+
+MIXED = [("btri", 8, 1000, 1, 11), ("btri", 4, 77, 3, 12), ("babd", 8, 300, 1, 13),
+         ("btri", 16, 50, 5, 14), ("btri", 3, 41, 2, 15), ("babd", 4, 9, 1, 16),
+         ("btri", 1, 4099, 1, 17), ("btri", 8, 2, 1, 18), ("babd", 6, 33, 4, 19),
+         ("btri", 8, 513, 0, 20), ("btri", 32, 20, 2, 21), ("babd", 2, 3, 1, 22)]
+
+
+def _check_against_alone_and_oracle(systems, mats, fs, xs, opts, tag):
+    for i, ((s, f), A, fd, xd) in enumerate(zip(systems, mats, fs, xs)):
+        if f.shape[0] == 0:
+            assert bool(xd.isnan().all()), f"{tag} sys {i}: nrhs=0 output touched"
+            continue
+        xa = _alone(A, fd, opts)
+        xb = xd.cpu().numpy()
+        assert np.array_equal(xb, xa.cpu().numpy()), f"{tag} sys {i}: batch != alone"
+        G.check(s, xb.T, f=f.T, tag=f"{tag} sys {i} {s.kind} m={s.m} nb={s.nb}")
+
+
+def test_batch_mixed_equals_alone():
+    import torch
+    systems = _systems(MIXED)
+    mats, keep, fs, xs = _device(systems)
+    _say("batch mixed", [(s.kind, s.m, s.nb, f.shape[0]) for s, f in systems])
+    infos, _ = pf.pf_solve_batch(mats, None, [f.shape[0] for _, f in systems], fs, xs)
+    torch.cuda.synchronize()
+    assert [i.status for i in infos] == [0] * len(systems)
+    _check_against_alone_and_oracle(systems, mats, fs, xs, None, "mixed")
+    del keep
+
+
+def test_batch_graph_replays_with_eager_work_between():
+    """The recorded graph is replayed three times; between replays the
+    program changes the matrices and right-hand sides with eager torch work
+    and synchronizes; every replay must match single solves of the values
+    it saw."""
+    import torch
+    specs = [("btri", 8, 700, 1, 31), ("babd", 4, 120, 2, 32), ("btri", 5, 64, 3, 33),
+             ("btri", 16, 100, 1, 34)]
+    systems = _systems(specs)
+    mats, keep, fs, xs = _device(systems)
+    B = pf.Batch(mats, None, [f.shape[0] for _, f in systems], fs, xs)
+    try:
+        for rep in range(3):
+            _say("replay", rep)
+            if rep:
+                for j, ((s, f), kp, fd) in enumerate(zip(systems, keep, fs)):
+                    D = kp[0]
+                    scale = 1.0 + 0.25 * rep
+                    D.mul_(scale)                   # A's diagonal blocks, in place
+                    fd.mul_(-0.5).add_(float(rep))  # new right-hand sides
+                    torch.cuda.synchronize()
+                    s.D = s.D * scale
+                    systems[j] = (s, fd.cpu().numpy())
+            for x in xs:
+                x.fill_(np.nan)
+            infos = B.run()
+            torch.cuda.synchronize()
+            assert [i.status for i in infos] == [0] * len(systems)
+            _check_against_alone_and_oracle(systems, mats, fs, xs, None, f"replay {rep}")
+    finally:
+        B.destroy()
+    del keep
+
+
+def test_batch_async_run_then_stream_order():
+    """pf_batch_run without info returns at once; work queued after it on the
+    same stream sees the solutions."""
+    import torch
+    systems = _systems([("btri", 8, 4000, 1, 41), ("btri", 8, 3000, 2, 42)])
+    mats, keep, fs, xs = _device(systems)
+    B = pf.Batch(mats, None, [1, 2], fs, xs)
+    try:
+        for x in xs:
+            x.zero_()
+        B.run(want_info=False)
+        sums = [x.sum() for x in xs]                 # queued behind the graph
+        torch.cuda.synchronize()
+        for (s, f), x, sm in zip(systems, xs, sums):
+            xr = G.oracle_solve(s, f.T).T
+            assert abs(float(sm) - float(np.sum(xr))) <= 1e-9 * max(1.0, np.abs(xr).sum())
+    finally:
+        B.destroy()
+    del keep
+
+
+def test_batch_handed_out_factor_outlives_batch():
+    import torch
+    systems = _systems([("btri", 8, 500, 1, 51), ("babd", 8, 200, 1, 52)])
+    mats, keep, fs, xs = _device(systems)
+    B = pf.Batch(mats, None, [1, 1], fs, xs)
+    B.run()
+    F1 = B.factor(1)
+    with pytest.raises(pf.PFError):
+        B.factor(1)
+    B.destroy()
+    s, _ = systems[1]
+    rng = np.random.default_rng(7)
+    f2 = rng.standard_normal((7, s.nb * s.m))        # more columns than the batch had
+    fd = torch.tensor(f2, dtype=torch.float64, device=G.device())
+    x = torch.empty_like(fd)
+    try:
+        info = pf.pf_solve(F1, fd, x)
+        assert info.status == 0
+        G.check(s, x.cpu().numpy().T, f=f2.T, tag="handed-out")
+        pf.pf_refactor(F1)
+        info = pf.pf_solve(F1, fd, x)
+        G.check(s, x.cpu().numpy().T, f=f2.T, tag="handed-out refactor")
+    finally:
+        pf.pf_destroy(F1)
+    torch.cuda.synchronize()
+    del keep
+
+
+def test_batch_fp32_ir():
+    import torch
+    specs = [("btri", 8, 900, 1, 61), ("babd", 8, 300, 2, 62), ("btri", 6, 50, 1, 63)]
+    systems = _systems(specs)
+    mats, keep, fs, xs = _device(systems)
+    opts = pf.make_opts(prec=pf.PF_FP32_IR)
+    infos, _ = pf.pf_solve_batch(mats, opts, [f.shape[0] for _, f in systems], fs, xs)
+    torch.cuda.synchronize()
+    for i, ((s, f), x, inf) in enumerate(zip(systems, xs, infos)):
+        _say("fp32-ir sys", i, inf.as_dict())
+        assert inf.status == 0 and inf.eta <= G.ETA_TOL and inf.refine_iters >= 1
+        G.check(s, x.cpu().numpy().T, f=f.T, tag=f"fp32-ir sys {i}")
+    del keep
+
+
+def test_batch_singular_member_reported_alone():
+    import torch
+    systems = _systems([("btri", 4, 200, 1, 71), ("btri", 4, 200, 1, 72), ("babd", 4, 50, 1, 73)])
+    s1 = systems[1][0]
+    s1.D[0] = 0.0                        # first block row all zero: an exact zero pivot
+    s1.Up[0] = 0.0
+    mats, keep, fs, xs = _device(systems)
+    infos, _ = pf.pf_solve_batch(mats, None, [1, 1, 1], fs, xs)
+    torch.cuda.synchronize()
+    assert infos[0].status == 0 and infos[2].status == 0
+    assert infos[1].status == pf.PF_ESINGULAR
+    for i in (0, 2):
+        s, f = systems[i]
+        G.check(s, xs[i].cpu().numpy().T, f=f.T, tag=f"neighbour {i}")
+    del keep
+
+
+def test_batch_mixed_block_sizes_workload_subset():
+    """A subset of the batched workload's shapes (block sizes 4..32, block
+    counts log-uniform, 1..64 right-hand sides), scaled down so the oracle
+    checks every system."""
+    import torch
+    specs = wl.batch_specs(count=12, n_hi=2 ** 11, max_rhs=8)
+    systems = _systems([("btri", m, nb, k, seed) for m, nb, k, seed in specs])
+    mats, keep, fs, xs = _device(systems)
+    _say("workload subset", [(m, nb, k) for m, nb, k, _ in specs])
+    infos, _ = pf.pf_solve_batch(mats, None, [k for _, _, k, _ in specs], fs, xs)
+    torch.cuda.synchronize()
+    assert all(i.status == 0 for i in infos)
+    _check_against_alone_and_oracle(systems, mats, fs, xs, None, "subset")
+    del keep

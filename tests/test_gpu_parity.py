@@ -55,6 +55,16 @@ def test_btri_random(m, nb):
     G.check(s, x, tag=f"m={m} nb={nb} levels={levels}")
 
 
+@pytest.mark.parametrize("kind,nb", [("btri", 2), ("btri", 3), ("btri", 50), ("btri", 513),
+                                     ("babd", 3), ("babd", 40)])
+def test_block_size_32(kind, nb):
+    s = wl.random_btri(nb, 32, seed=900 + nb) if kind == "btri" else wl.random_babd(nb, 32, seed=900 + nb)
+    _say(kind, "m 32 nb", nb)
+    x, info, levels = G.gpu_solve(s)
+    assert info.status == 0
+    G.check(s, x, tag=f"{kind} m=32 nb={nb} levels={levels}")
+
+
 @pytest.mark.parametrize("m", [4, 8])
 @pytest.mark.parametrize("nrhs", [2, 5, 9])
 def test_btri_multi_rhs(m, nrhs):
