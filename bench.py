@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--partitions", type=int, default=0, help="finest-level p (0 = planner)")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--coarse-rows", type=int, default=0)
+    ap.add_argument("--map", choices=["auto", "rows", "tiles"], default="auto",
+                    help="factor lane mapping: planner default, or rows / tiles on every level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=10)
@@ -108,8 +110,9 @@ def main():
     f = wl.to_device_rhs(s.f, dev)
     x = torch.empty_like(f)
     A = pf.make_matrix(pf.PF_BTRI, m, nb, D, Lo, Up)
+    flags = {"auto": 0, "rows": pf.PF_FLAG_MAP_ROWS, "tiles": pf.PF_FLAG_MAP_TILES}[args.map]
     opts = pf.make_opts(partitions=args.partitions, block_rows=args.block_rows,
-                        coarse_rows=args.coarse_rows)
+                        coarse_rows=args.coarse_rows, flags=flags)
     F = pf.pf_factor(A, opts)
     levels = pf.pf_factor_levels(F)
     torch.cuda.synchronize()
@@ -166,7 +169,8 @@ def main():
         kernels.append({"phase": ph, "level": lvl, "nb": lnb, "p": lp, "avg_us": round(avg * 1e3, 2),
                         "alg_MB": round(b / 1e6, 3), "GBps": round(b / (avg * 1e-3) / 1e9, 1)})
     dom = max(kernels, key=lambda k: k["avg_us"])
-    names = {"factor": f"k_btri_factor<{m}, double, false>",
+    tile0 = args.map != "rows" and m in (2, 3, 4, 5, 6, 7, 8)
+    names = {"factor": f"k_btri_factor{'_tile' if tile0 else ''}<{m}, double, false>",
              "forward": f"k_fwd<0, {m}, 1, double, false>", "backward": f"k_bwd<0, {m}, 1, double>"}
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6
@@ -190,6 +194,7 @@ def main():
         "config": {"workload": "trapezoid_bvp_btri", "N": args.N, "m": m, "nb": nb,
                    "unknowns": n, "nrhs": 1,
                    "partitions": args.partitions or "planner",
+                   "lane_mapping": args.map,
                    "levels": [[k, a, b] for k, a, b in levels],
                    "step": "pf_refactor + pf_solve"},
         "eta": eta,

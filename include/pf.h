@@ -67,7 +67,15 @@ enum {
     PF_EUNSUPPORTED = 5 /* block size beyond what the library instantiates   */
 };
 
-enum { PF_FLAG_ETA = 1 }; /* pf_solve in FP64 also computes eta (one residual pass) */
+enum {
+    PF_FLAG_ETA = 1,       /* pf_solve in FP64 also computes eta (one residual pass)  */
+    PF_FLAG_MAP_ROWS = 2,  /* factor every level with the row lane mapping (M lanes per
+                              partition, lane i holds row i of each block)            */
+    PF_FLAG_MAP_TILES = 4  /* factor every level with the tile lane mapping (M*M lanes
+                              per partition, one block entry per lane; m <= 8).
+                              Default: tiles wherever m <= 8, else rows.
+                              The mappings differ only in rounding.                  */
+};
 
 typedef struct {
     int32_t kind;       /* pf_kind                                            */

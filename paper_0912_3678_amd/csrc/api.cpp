@@ -21,6 +21,7 @@ struct Level {
     int kind = PF_BTRI;
     int64_t nb = 0, p = 1;
     bool f32 = false;
+    bool tile = false;   // factor with the tile lane mapping
     const double *D = nullptr, *Dadd = nullptr, *Lo = nullptr, *Up = nullptr, *C = nullptr;
     void *E = nullptr, *R = nullptr, *Z = nullptr, *X = nullptr;
     double *nD = nullptr, *nDadd = nullptr, *nLo = nullptr, *nUp = nullptr, *nC = nullptr;
@@ -107,6 +108,18 @@ int target_rows(int M, bool f32, int level, const pf_opts &o)
 }
 
 constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chain
+
+// Lane mapping of a level's factor kernel.  Tiles (one block entry per lane)
+// cut the latency of a chain row several times over, which is what bounds
+// the reduced levels; on the m = 8 benchmark they also match or beat rows at
+// level 0 (60.7 vs 62.3 us).  Rows remain for block sizes without a tile
+// kernel (1, 16, 32) and on request.
+bool use_tiles(int M, int level, const pf_opts &o)
+{
+    (void)level;
+    if (!tile_mapping_ok(M) || (o.flags & PF_FLAG_MAP_ROWS)) return false;
+    return true;
+}
 
 std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
 {
@@ -331,8 +344,8 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         const Level &L = F->lv[l];
         const LevelArgs a = level_args(F, l);
         e = prof_launch(F, true, 0, (int)l, s, [&] {
-            return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
-                                       : launch_babd_factor(F->M, L.f32, a, s);
+            return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, L.tile, a, s)
+                                       : launch_babd_factor(F->M, L.f32, L.tile, a, s);
         });
         if (e != hipSuccess) return e;
     }
@@ -590,6 +603,7 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         L.nb = plan[l].nb;
         L.p = plan[l].p;
         L.f32 = (l == 0 && o.prec == PF_FP32_IR);
+        L.tile = use_tiles(M, (int)l, o);
         if (l == 0) {
             L.D = D0; L.Lo = Lo0;
             if (A->kind == PF_BTRI) L.Up = Up0;
@@ -885,7 +899,7 @@ namespace {
 struct BatchLaunch {
     int phase;      // 0 factor, 1 forward sweep, 2 back substitution
     int kind, M, KC;
-    bool f32, add;
+    bool f32, add, tile;
     size_t work;    // first work item of this launch
     int nwg;
 };
@@ -942,17 +956,19 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
     size_t maxL = 0;
     for (auto *F : B->all) maxL = std::max(maxL, F->lv.size());
     for (size_t l = 0; l < maxL; ++l) {
-        std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+        std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
         for (int i = 0; i < B->nsys; ++i) {
             const pf_factor_s *F = B->all[i];
             if (l >= F->lv.size()) continue;
             const Level &L = F->lv[l];
-            groups[{L.kind, F->M, L.f32 ? 1 : 0, (L.kind == PF_BTRI && L.Dadd) ? 1 : 0}].push_back(i);
+            groups[{L.kind, F->M, L.f32 ? 1 : 0, (L.kind == PF_BTRI && L.Dadd) ? 1 : 0,
+                    L.tile ? 1 : 0}].push_back(i);
         }
         for (auto &kv : groups) {
             BatchLaunch bl{0, std::get<0>(kv.first), std::get<1>(kv.first), 1,
-                           std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0, work.size(), 0};
-            const int gpw = groups_per_wg(bl.M);
+                           std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0,
+                           std::get<4>(kv.first) != 0, work.size(), 0};
+            const int gpw = partitions_per_wg(bl.M, bl.tile);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(level_args(B->all[i], l));
@@ -994,7 +1010,7 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
         for (auto &kv : groups) {
             BatchLaunch bl{phase, std::get<0>(kv.first), std::get<1>(kv.first),
                            std::get<4>(kv.first), std::get<2>(kv.first) != 0,
-                           std::get<3>(kv.first) != 0, work.size(), 0};
+                           std::get<3>(kv.first) != 0, false, work.size(), 0};
             const int gpw = groups_per_wg(bl.M);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
@@ -1021,8 +1037,8 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
         if (e == hipSuccess && F->M != F->m) e = launch_pad_matrix(F, s);
     for (const auto &bl : B->flaunch)
         if (e == hipSuccess)
-            e = launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev, B->d_lwork + bl.work,
-                                    bl.nwg, s);
+            e = launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, bl.tile, B->d_lev,
+                                    B->d_lwork + bl.work, bl.nwg, s);
     if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
         for (auto *F : B->all) {
             const pf_matrix &A = F->A;

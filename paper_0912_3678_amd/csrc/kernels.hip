@@ -66,7 +66,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T> __device__ __forceinline__ T tabs(T v) { return v < T(0) ? -v : v; }
 
 __device__ __forceinline__ unsigned long long status_code(int level, int64_t block)
 {
@@ -244,42 +243,39 @@ template <typename T> constexpr int group_stride(int elems)
     return ((elems + kLine<T> - 1) / kLine<T>) * kLine<T> + kPad<T>;
 }
 
-// ---- group-wide argmax with DPP -------------------------------------------
-// The M lanes of a group are an aligned run inside a row of 16 (M <= 16) or a
-// half wave (M = 32), so these cross-lane moves never leave the group.
+// ---- pivot search: group-wide max of a packed key with DPP ----------------
+// A candidate's key is the high 32 bits of |v| (sign cleared) with the low 5
+// bits replaced by 31 - row: an unsigned max over the group then picks the
+// largest magnitude, compared to 15 (FP64) or 18 (FP32) mantissa bits, and
+// among equal keys the first row.  Rows already used as pivots have key 0,
+// below every candidate.  Each reduction stage is one max with a DPP operand.
 template <int CTRL> __device__ __forceinline__ int dpp_i(int v)
 {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
-template <int CTRL> __device__ __forceinline__ double dpp_x(double v)
+
+__device__ __forceinline__ unsigned pivot_key(double v, int row, bool used)
 {
-    const long long b = __double_as_longlong(v);
-    const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
+    return used ? 0u : ((hi & ~31u) | (unsigned)(31 - row));
 }
-template <int CTRL> __device__ __forceinline__ float dpp_x(float v)
+__device__ __forceinline__ unsigned pivot_key(float v, int row, bool used)
 {
-    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+    const unsigned b = (unsigned)__float_as_int(v) & 0x7fffffffu;
+    return used ? 0u : ((b & ~31u) | (unsigned)(31 - row));
 }
 
-// keep the larger value; among equal values the smaller row index
-template <typename T>
-__device__ __forceinline__ void argmax_merge(T &v, int &idx, T ov, int oi)
+// The M lanes of a group are an aligned run inside a row of 16 (M <= 16) or a
+// half wave (M = 32), so these cross-lane moves never leave the group.
+template <int M>
+__device__ __forceinline__ int group_pivot(unsigned k)
 {
-    const bool take = (ov > v) || (ov == v && oi < idx);
-    v = take ? ov : v;
-    idx = take ? oi : idx;
-}
-
-template <int M, typename T>
-__device__ __forceinline__ int group_argmax(T v, int idx)
-{
-    if constexpr (M >= 2) argmax_merge(v, idx, dpp_x<0xB1>(v), dpp_i<0xB1>(idx));    // lane ^ 1
-    if constexpr (M >= 4) argmax_merge(v, idx, dpp_x<0x4E>(v), dpp_i<0x4E>(idx));    // lane ^ 2
-    if constexpr (M >= 8) argmax_merge(v, idx, dpp_x<0x141>(v), dpp_i<0x141>(idx));  // half-row mirror
-    if constexpr (M >= 16) argmax_merge(v, idx, dpp_x<0x140>(v), dpp_i<0x140>(idx)); // row mirror
-    if constexpr (M >= 32) argmax_merge(v, idx, (T)__shfl_xor(v, 16, 32), __shfl_xor(idx, 16, 32));
-    return idx;
+    if constexpr (M >= 2) k = max(k, (unsigned)dpp_i<0xB1>((int)k));    // lane ^ 1
+    if constexpr (M >= 4) k = max(k, (unsigned)dpp_i<0x4E>((int)k));    // lane ^ 2
+    if constexpr (M >= 8) k = max(k, (unsigned)dpp_i<0x141>((int)k));   // half-row mirror
+    if constexpr (M >= 16) k = max(k, (unsigned)dpp_i<0x140>((int)k));  // row mirror
+    if constexpr (M >= 32) k = max(k, (unsigned)__shfl_xor((int)k, 16, 32));
+    return 31 - (int)(k & 31u);
 }
 
 // reciprocal: hardware estimate refined by Newton steps (two in FP64, one in FP32)
@@ -300,8 +296,8 @@ __device__ __forceinline__ float recip(float x)
 // ---- Gauss-Jordan inversion of the pivot block with row partial pivoting --
 // Row-distributed and swap-free: lane i holds row i of D' in d (consumed) and
 // starts with row i of the identity in e.  At step c the pivot is the row
-// with the largest |D'(r,c)| among rows not yet used as pivots (first index
-// on ties), found by a DPP max-reduction; the pivot lane's row [d | e] is read
+// with the largest |D'(r,c)| among rows not yet used as pivots (ranked by
+// pivot_key), found by a DPP max-reduction; the pivot lane's row [d | e] is read
 // from the group's LDS, the pivot row is scaled by 1/pivot and column c is
 // eliminated from every other row.  Rows never move: the lane chosen at step
 // c ends with row c of D'^{-1} in e, and sigma (the return value) is c.
@@ -316,7 +312,7 @@ __device__ __forceinline__ int gj_rows(T (&d)[M], T (&e)[M], int i, T *SP, bool 
     int sigma = 0;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-        const int pr = group_argmax<M, T>(used ? T(-1) : tabs(d[c]), i);
+        const int pr = group_pivot<M>(pivot_key(d[c], i, used));
         T *row = SP + i * PR;
 #pragma unroll
         for (int l = c; l < M; ++l) row[l] = d[l];
@@ -581,6 +577,274 @@ __device__ __forceinline__ void babd_factor_body(const LevelArgs &a, int64_t pbl
 }
 
 // ---------------------------------------------------------------------------
+// Tile mapping: one partition per M*M lanes (M = 2, 4, 8; 64/(M*M)
+// partitions per wave).  Lane (r, c) of a partition holds entry (r, c) of
+// every block of its chain, column c occupying M consecutive lanes.  The
+// per-row work is spread over M times more lanes than in the row mapping,
+// which cuts the latency of a chain row several times over: this mapping is
+// for levels with few partitions (the reduced levels), where latency, not
+// bandwidth, bounds a level.
+//
+// The pivot block is inverted in place by Gauss-Jordan exchange steps: step
+// j exchanges unknown j with the equation of pivot row p_j (the largest
+// |entry| of column j among the rows not yet used, as ranked by pivot_key).
+// With b the running tableau and v = b(p_j, j):
+//   b(p_j, j) <- 1/v,  b(p_j, l) <- b(p_j, l)/v,  b(i, j) <- -b(i, j)/v,
+//   b(i, l) <- b(i, l) - b(i, j) b(p_j, l)/v          (i != p_j, l != j).
+// After the M steps b(r, c) is entry (sigma(r), p_c) of the inverse, sigma(r)
+// being the step at which row r was the pivot.  The pivot search of step
+// j+1 is a DPP reduction inside column group j+1 right after step j's
+// update, so each step costs one LDS round trip.
+
+// pivot row of column j: reduce over column group j, then broadcast it to
+// the partition's lanes
+template <int M, typename T>
+__device__ __forceinline__ int tile_pivot(T b, bool used, int r, int j)
+{
+    constexpr int LP = M * M;
+    const int idx = group_pivot<M>(pivot_key(b, r, used));
+    if constexpr (LP == WG) return __builtin_amdgcn_readlane(idx, j * M);
+    else return __shfl(idx, (int)((threadIdx.x / LP) * LP) + j * M, WG);
+}
+
+// In-place Gauss-Jordan of the tableau b = D'(r, c); returns sigma(r) and
+// p_c through the references.
+template <int M, typename T>
+__device__ __forceinline__ void tile_invert(T &b, int r, int c, T *S, int &sigma, int &pc,
+                                            bool &sing)
+{
+    constexpr int RS = M + kPad<T>;
+    bool used = false;
+    int pr = tile_pivot<M, T>(b, used, r, 0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        S[r * RS + c] = b;
+        wave_sync();
+        const T prow = S[pr * RS + c], mcol = S[r * RS + j], pv = S[pr * RS + j];
+        sing = sing || (pv == T(0));
+        const T inv = recip(pv);
+        const bool isr = (r == pr), isc = (c == j);
+        const T upd = fma(-(mcol * inv), prow, b);
+        b = isr ? (isc ? inv : prow * inv) : (isc ? -mcol * inv : upd);
+        used = used || isr;
+        sigma = isr ? j : sigma;
+        pc = isc ? pr : pc;
+        wave_sync();
+        if (j + 1 < M) pr = tile_pivot<M, T>(b, used, r, j + 1);
+    }
+}
+
+// M entries of an LDS row (16-byte reads; rows are 16-byte aligned)
+template <int M, typename T>
+__device__ __forceinline__ void lds_row(T (&v)[M], const T *p)
+{
+    if constexpr (sizeof(T) == 8 && M % 2 == 0) {
+#pragma unroll
+        for (int l = 0; l < M; l += 2) {
+            const double2 w = *reinterpret_cast<const double2 *>(p + l);
+            v[l] = w.x;
+            v[l + 1] = w.y;
+        }
+    } else if constexpr (sizeof(T) == 4 && M % 4 == 0) {
+#pragma unroll
+        for (int l = 0; l < M; l += 4) {
+            const float4 w = *reinterpret_cast<const float4 *>(p + l);
+            v[l] = w.x; v[l + 1] = w.y; v[l + 2] = w.z; v[l + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) v[l] = p[l];
+    }
+}
+
+template <int M, typename T>
+__device__ __forceinline__ T dot(const T (&u)[M], const T (&v)[M])
+{
+    T s = T(0);
+#pragma unroll
+    for (int l = 0; l < M; ++l) s = fma(u[l], v[l], s);
+    return s;
+}
+
+// Block tridiagonal factor, tile mapping (same recurrences, storage and
+// outputs as btri_factor_body).
+template <int M, typename T, bool ADD>
+__device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_t pblock)
+{
+    constexpr int LP = M * M, PPW = WG / LP;
+    constexpr size_t MM = (size_t)M * M;
+    const int tid = threadIdx.x, grp = tid / LP, t = tid % LP;
+    const int r = t % M, c = t / M;
+    constexpr int RS = M + kPad<T>;
+    constexpr int GS = group_stride<T>(4 * M * RS);
+    __shared__ __align__(16) T lds[PPW * GS];
+    T *S0 = lds + grp * GS;   // tableau; then E by rows; then R by rows
+    T *S1 = S0 + M * RS;      // Z' by columns; then X by columns
+    T *S2 = S1 + M * RS;      // A(g+1,g) by rows
+    T *S3 = S2 + M * RS;      // Zh by columns
+
+    const int64_t nb = a.nb;
+    const int64_t part = pblock * PPW + grp;
+    const Geo G = geometry<0>(nb, a.p, part);
+    T *E = (T *)a.E, *R = (T *)a.R, *Zs = (T *)a.Z, *Xs = (T *)a.X;
+    T *dump = (T *)a.dump + tid;
+    const int cm = r + c * M;   // column-major offset of (r, c)
+    const int rm = r * M + c;   // row-major offset
+
+    T d = T(0), z = T(0), rr = T(0), a1 = T(0);
+    if (G.valid) {
+        double v = a.D[G.start * MM + cm];
+        if constexpr (ADD) v += a.Dadd[G.start * MM + cm];
+        d = (T)v;
+    }
+    if (G.hasL) {
+        z = (T)a.Lo[(G.start - 1) * MM + cm];    // A(g_1, sL)
+        rr = (T)a.Up[(G.start - 1) * MM + cm];   // A(sL, g_1)
+    }
+    unsigned long long bad = ~0ull;
+
+    // column c of A(g,g+1), entry (r,c) of A(g+1,g) and of D[g+1], one block
+    // row ahead, from the zero block when they do not exist
+    // (the two addends of D[g+1] are summed only where the row uses them)
+    auto load_next = [&](int64_t g, bool ok, T (&upc)[M], T &lo, double &dn, double &da) {
+        ld_vec<M, T>(upc, (ok ? a.Up + g * MM : a.zero) + c * M);
+        lo = (T)*((ok ? a.Lo + g * MM : a.zero) + cm);
+        dn = *((ok ? a.D + (g + 1) * MM : a.zero) + cm);
+        if constexpr (ADD) da = *((ok ? a.Dadd + (g + 1) * MM : a.zero) + cm);
+    };
+    T upc[M], lo;
+    double dn, da = 0.0;
+    load_next(G.start, G.len > 0 && G.start + 1 < nb, upc, lo, dn, da);
+
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        T upn[M], lon;
+        double dnn, dan = 0.0;
+        load_next(g + 1, k + 1 < G.len && g + 2 < nb, upn, lon, dnn, dan);
+
+        T b = d;
+        int sigma = 0, pc = 0;
+        bool sing = false;
+        tile_invert<M, T>(b, r, c, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, g);
+        bad = (sing && code < bad) ? code : bad;
+
+        S0[sigma * RS + pc] = b;   // E_k by (logical) rows
+        S1[c * RS + r] = z;        // Z'_k by columns
+        S2[r * RS + c] = lo;       // A(g+1,g) by rows
+        wave_sync();
+        T er[M], zc[M], lr[M];
+        lds_row<M, T>(er, S0 + r * RS);
+        lds_row<M, T>(zc, S1 + c * RS);
+        lds_row<M, T>(lr, S2 + r * RS);
+        const T x = dot<M, T>(er, upc), zh = dot<M, T>(er, zc);
+        E[g * MM + sigma * M + pc] = b;
+        *(G.hasL ? R + g * MM + rm : dump) = rr;
+        Xs[g * MM + rm] = x;
+        Zs[g * MM + rm] = zh;
+        wave_sync();
+        S0[r * RS + c] = rr;       // R_k by rows
+        S1[c * RS + r] = x;        // X_k by columns
+        S3[c * RS + r] = zh;       // Zh_k by columns
+        wave_sync();
+        T rw[M], xc[M], hc[M];
+        lds_row<M, T>(rw, S0 + r * RS);
+        lds_row<M, T>(xc, S1 + c * RS);
+        lds_row<M, T>(hc, S3 + c * RS);
+        a1 -= dot<M, T>(rw, hc);
+        rr = -dot<M, T>(rw, xc);
+        d = (T)(ADD ? dn + da : dn) - dot<M, T>(lr, xc);
+        z = -dot<M, T>(lr, hc);
+#pragma unroll
+        for (int l = 0; l < M; ++l) upc[l] = upn[l];
+        lo = lon;
+        dn = dnn;
+        da = dan;
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+    if (G.hasR) {
+        a.nD[part * MM + cm] = (double)d;                       // D[sR] + alpha_2
+        if (G.hasL) a.nLo[(part - 1) * MM + cm] = (double)z;    // beta
+    }
+    if (G.hasL) {
+        a.nDadd[(part - 1) * MM + cm] = (double)a1;             // alpha_1
+        if (G.hasR) a.nUp[(part - 1) * MM + cm] = (double)rr;   // gamma
+    }
+}
+
+// Bidiagonal-plus-corner factor, tile mapping (same outputs as
+// babd_factor_body).  D' = D here, so the inversion of the next block row
+// does not wait for the chain.
+template <int M, typename T>
+__device__ __forceinline__ void babd_factor_tile_body(const LevelArgs &a, int64_t pblock)
+{
+    constexpr int LP = M * M, PPW = WG / LP;
+    constexpr size_t MM = (size_t)M * M;
+    const int tid = threadIdx.x, grp = tid / LP, t = tid % LP;
+    const int r = t % M, c = t / M;
+    constexpr int RS = M + kPad<T>;
+    constexpr int GS = group_stride<T>(4 * M * RS);
+    __shared__ __align__(16) T lds[PPW * GS];
+    T *S0 = lds + grp * GS;   // tableau; then E by rows
+    T *S1 = S0 + M * RS;      // Z' by columns
+    T *S2 = S1 + M * RS;      // A(g+1,g) by rows
+    T *S3 = S2 + M * RS;      // Zh by columns
+
+    const int64_t part = pblock * PPW + grp;
+    const Geo G = geometry<1>(a.nb, a.p, part);
+    T *E = (T *)a.E, *Zs = (T *)a.Z;
+    const int cm = r + c * M, rm = r * M + c;
+
+    T z = G.valid ? (T)a.Lo[(G.start - 1) * MM + cm] : T(0);   // A(g_1, sL)
+    unsigned long long bad = ~0ull;
+    T dc = (T)*((G.len > 0 ? a.D + G.start * MM : a.zero) + cm);
+    T lc = (T)*((G.len > 0 ? a.Lo + G.start * MM : a.zero) + cm);
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        const bool more = k + 1 < G.len;
+        T b = dc;
+        const T lo = lc;
+        dc = (T)*((more ? a.D + (g + 1) * MM : a.zero) + cm);
+        lc = (T)*((more ? a.Lo + (g + 1) * MM : a.zero) + cm);
+
+        int sigma = 0, pc = 0;
+        bool sing = false;
+        tile_invert<M, T>(b, r, c, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, g);
+        bad = (sing && code < bad) ? code : bad;
+
+        S0[sigma * RS + pc] = b;
+        S1[c * RS + r] = z;
+        S2[r * RS + c] = lo;
+        wave_sync();
+        T er[M], zc[M], lr[M];
+        lds_row<M, T>(er, S0 + r * RS);
+        lds_row<M, T>(zc, S1 + c * RS);
+        lds_row<M, T>(lr, S2 + r * RS);
+        const T zh = dot<M, T>(er, zc);
+        E[g * MM + sigma * M + pc] = b;
+        Zs[g * MM + rm] = zh;
+        S3[c * RS + r] = zh;
+        wave_sync();
+        T hc[M];
+        lds_row<M, T>(hc, S3 + c * RS);
+        z = -dot<M, T>(lr, hc);
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+    if (G.valid) {
+        const int64_t sR = G.start + G.len;
+        a.nLo[part * MM + cm] = (double)z;                         // beta
+        a.nD[(part + 1) * MM + cm] = a.D[sR * MM + cm];
+        if (part == 0) {
+            a.nD[cm] = a.D[cm];
+            a.nC[cm] = a.C[cm];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Forward sweep of a solve (the F solve): t_k and the reduced right-hand side.
 // Lane i owns row i of KC right-hand-side columns.  ADD: the right-hand side
 // is the sum of two arrays (reduced levels of block tridiagonal matrices).
@@ -620,7 +884,11 @@ __device__ __forceinline__ void fwd_body(const SolveArgs &a, int64_t pblock, int
     // loaded one block row ahead (before the current row's stores); missing
     // operands come from the zero block.
     const T *zt = (const T *)a.zero + i * M;
-    auto load_row = [&](int64_t g, bool ok, T (&er)[M], T (&rr)[M], T (&lr)[M], T (&fn)[KC]) {
+    // (the right-hand side stays in FP64 and its two addends apart until the
+    // row that uses them: converting or summing early would wait for this
+    // row's own prefetch)
+    auto load_row = [&](int64_t g, bool ok, T (&er)[M], T (&rr)[M], T (&lr)[M],
+                        double (&fn)[KC], double (&fa)[KC]) {
         const bool nx = ok && (g + 1 < a.nb);
         ld_fac<M, T>(er, ok ? E + g * MM + i * M : zt);
         if constexpr (KIND == 0) ld_fac<M, T>(rr, (ok && G.hasL) ? R + g * MM + i * M : zt);
@@ -628,16 +896,19 @@ __device__ __forceinline__ void fwd_body(const SolveArgs &a, int64_t pblock, int
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             const int64_t o = (g + 1) * M + i + col[c] * a.ldf;
-            double v = *(nx ? a.F + o : a.zero);
-            if constexpr (ADD) v += *(nx ? a.Fadd + o : a.zero);
-            fn[c] = (T)v;
+            fn[c] = *(nx ? a.F + o : a.zero);
+            if constexpr (ADD) fa[c] = *(nx ? a.Fadd + o : a.zero);
         }
     };
-    T ec[M], rc[M], lc[M], fc[KC];
-    load_row(G.start, G.len > 0, ec, rc, lc, fc);
+    T ec[M], rc[M], lc[M];
+    double fc[KC], fca[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) fca[c] = 0.0;
+    load_row(G.start, G.len > 0, ec, rc, lc, fc, fca);
     for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
-        T er[M], lr[M], rr[M], fn[KC];
+        T er[M], lr[M], rr[M];
+        double fn[KC], fna[KC];
 #pragma unroll
         for (int l = 0; l < M; ++l) {
             er[l] = ec[l];
@@ -645,8 +916,11 @@ __device__ __forceinline__ void fwd_body(const SolveArgs &a, int64_t pblock, int
             if constexpr (KIND == 0) rr[l] = rc[l];
         }
 #pragma unroll
-        for (int c = 0; c < KC; ++c) fn[c] = fc[c];
-        load_row(g + 1, k + 1 < G.len, ec, rc, lc, fc);
+        for (int c = 0; c < KC; ++c) {
+            fn[c] = fc[c];
+            fna[c] = fca[c];
+        }
+        load_row(g + 1, k + 1 < G.len, ec, rc, lc, fc, fca);
 #pragma unroll
         for (int c = 0; c < KC; ++c) SV[i + c * CS] = fp[c];
         wave_sync();
@@ -676,7 +950,7 @@ __device__ __forceinline__ void fwd_body(const SolveArgs &a, int64_t pblock, int
                 sl = fma(lr[l], tv, sl);
                 if constexpr (KIND == 0) sr = fma(rr[l], tv, sr);
             }
-            fp[c] = fn[c] - sl;
+            fp[c] = (T)(ADD ? fn[c] + fna[c] : fn[c]) - sl;
             if constexpr (KIND == 0) gl[c] -= sr;
         }
         wave_sync();
@@ -796,6 +1070,30 @@ __global__ __launch_bounds__(WG) void kb_babd_factor(const LevelArgs *tab, const
     const LevelArgs a = tab[w.x];
     babd_factor_body<M, T>(a, w.y);
 }
+template <int M, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void k_btri_factor_tile(LevelArgs a)
+{
+    btri_factor_tile_body<M, T, ADD>(a, blockIdx.x);
+}
+template <int M, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void kb_btri_factor_tile(const LevelArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    btri_factor_tile_body<M, T, ADD>(a, w.y);
+}
+template <int M, typename T>
+__global__ __launch_bounds__(WG) void k_babd_factor_tile(LevelArgs a)
+{
+    babd_factor_tile_body<M, T>(a, blockIdx.x);
+}
+template <int M, typename T>
+__global__ __launch_bounds__(WG) void kb_babd_factor_tile(const LevelArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    babd_factor_tile_body<M, T>(a, w.y);
+}
 template <int KIND, int M, int KC, typename T, bool ADD>
 __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
 {
@@ -850,14 +1148,42 @@ inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)
 }  // namespace
 
 int groups_per_wg(int M) { return WG / M; }
+bool tile_mapping_ok(int M) { return M == 2 || M == 4 || M == 8; }
+int partitions_per_wg(int M, bool tile) { return tile ? WG / (M * M) : WG / M; }
 int rhs_chunk(int nrhs) { return nrhs == 1 ? 1 : 4; }
 
-hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s)
+template <typename F>
+hipError_t dispatch_Mtile(int M, F &&f)
 {
+    switch (M) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_btri_factor(int M, bool f32, bool tile, const LevelArgs &a, hipStream_t s)
+{
+    const bool add = a.Dadd != nullptr;
+    if (tile)
+        return dispatch_Mtile(M, [&](auto mc) {
+            constexpr int MV = decltype(mc)::value;
+            const dim3 grid((unsigned)((a.p + partitions_per_wg(MV, true) - 1) /
+                                       partitions_per_wg(MV, true)));
+            if (add) {
+                if (f32) hipLaunchKernelGGL((k_btri_factor_tile<MV, float, true>), grid, dim3(WG), 0, s, a);
+                else hipLaunchKernelGGL((k_btri_factor_tile<MV, double, true>), grid, dim3(WG), 0, s, a);
+            } else {
+                if (f32) hipLaunchKernelGGL((k_btri_factor_tile<MV, float, false>), grid, dim3(WG), 0, s, a);
+                else hipLaunchKernelGGL((k_btri_factor_tile<MV, double, false>), grid, dim3(WG), 0, s, a);
+            }
+            return hipGetLastError();
+        });
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
         const dim3 grid = grid_for(MV, a.p, 1, 1);
-        if (a.Dadd) {
+        if (add) {
             if (f32) hipLaunchKernelGGL((k_btri_factor<MV, float, true>), grid, dim3(WG), 0, s, a);
             else hipLaunchKernelGGL((k_btri_factor<MV, double, true>), grid, dim3(WG), 0, s, a);
         } else {
@@ -868,8 +1194,17 @@ hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
     });
 }
 
-hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s)
+hipError_t launch_babd_factor(int M, bool f32, bool tile, const LevelArgs &a, hipStream_t s)
 {
+    if (tile)
+        return dispatch_Mtile(M, [&](auto mc) {
+            constexpr int MV = decltype(mc)::value;
+            const dim3 grid((unsigned)((a.p + partitions_per_wg(MV, true) - 1) /
+                                       partitions_per_wg(MV, true)));
+            if (f32) hipLaunchKernelGGL((k_babd_factor_tile<MV, float>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_babd_factor_tile<MV, double>), grid, dim3(WG), 0, s, a);
+            return hipGetLastError();
+        });
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
         const dim3 grid = grid_for(MV, a.p, 1, 1);
@@ -879,13 +1214,28 @@ hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
     });
 }
 
-hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, const LevelArgs *tab,
+hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, bool tile, const LevelArgs *tab,
                                const int4 *work, int nwg, hipStream_t s)
 {
     if (nwg <= 0) return hipSuccess;
+    const dim3 grid(nwg);
+    if (tile)
+        return dispatch_Mtile(M, [&](auto mc) {
+            constexpr int MV = decltype(mc)::value;
+            if (kind == 1) {
+                if (f32) hipLaunchKernelGGL((kb_babd_factor_tile<MV, float>), grid, dim3(WG), 0, s, tab, work);
+                else hipLaunchKernelGGL((kb_babd_factor_tile<MV, double>), grid, dim3(WG), 0, s, tab, work);
+            } else if (add) {
+                if (f32) hipLaunchKernelGGL((kb_btri_factor_tile<MV, float, true>), grid, dim3(WG), 0, s, tab, work);
+                else hipLaunchKernelGGL((kb_btri_factor_tile<MV, double, true>), grid, dim3(WG), 0, s, tab, work);
+            } else {
+                if (f32) hipLaunchKernelGGL((kb_btri_factor_tile<MV, float, false>), grid, dim3(WG), 0, s, tab, work);
+                else hipLaunchKernelGGL((kb_btri_factor_tile<MV, double, false>), grid, dim3(WG), 0, s, tab, work);
+            }
+            return hipGetLastError();
+        });
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
-        const dim3 grid(nwg);
         if (kind == 1) {
             if (f32) hipLaunchKernelGGL((kb_babd_factor<MV, float>), grid, dim3(WG), 0, s, tab, work);
             else hipLaunchKernelGGL((kb_babd_factor<MV, double>), grid, dim3(WG), 0, s, tab, work);

@@ -65,6 +65,21 @@ def test_block_size_32(kind, nb):
     G.check(s, x, tag=f"{kind} m=32 nb={nb} levels={levels}")
 
 
+@pytest.mark.parametrize("flag", ["rows", "tiles"])
+@pytest.mark.parametrize("kind,m,nb", [("btri", 2, 301), ("btri", 4, 1001), ("btri", 8, 4099),
+                                       ("btri", 3, 77), ("btri", 8, 7), ("babd", 2, 40),
+                                       ("babd", 4, 300), ("babd", 8, 1001), ("babd", 6, 31)])
+def test_lane_mappings(kind, m, nb, flag):
+    """Both factor lane mappings on every level give the oracle's solution."""
+    seed = 500 + m * 13 + nb
+    s = wl.random_btri(nb, m, seed=seed) if kind == "btri" else wl.random_babd(nb, m, seed=seed)
+    f = pf.PF_FLAG_MAP_ROWS if flag == "rows" else pf.PF_FLAG_MAP_TILES
+    _say(kind, "m", m, "nb", nb, flag)
+    x, info, levels = G.gpu_solve(s, pf.make_opts(flags=f))
+    assert info.status == 0
+    G.check(s, x, tag=f"{kind} m={m} nb={nb} {flag} levels={levels}")
+
+
 @pytest.mark.parametrize("m", [4, 8])
 @pytest.mark.parametrize("nrhs", [2, 5, 9])
 def test_btri_multi_rhs(m, nrhs):
@@ -159,10 +174,11 @@ def test_fp32_ir_btri():
 
 # --------------------------------------------------------------------------
 # error path: an exactly singular pivot block
-def test_singular_pivot_reported():
+@pytest.mark.parametrize("flags", [0, pf.PF_FLAG_MAP_TILES])
+def test_singular_pivot_reported(flags):
     s = wl.random_btri(64, 4, seed=5)
     s.D[0] = 0.0
     s.Up[0] = 0.0
-    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=4))
+    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=4, flags=flags))
     assert info.status == pf.PF_ESINGULAR
     assert info.bad_level == 0 and info.bad_block == 0
