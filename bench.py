@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--partitions", type=int, default=0, help="finest-level p (0 = planner)")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--coarse-rows", type=int, default=0)
+    ap.add_argument("--split", action="store_true",
+                    help="time pf_refactor + pf_solve instead of the fused pf_factor_solve")
     ap.add_argument("--map", choices=["auto", "rows", "tiles"], default="auto",
                     help="factor lane mapping: planner default, or rows / tiles on every level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -53,6 +55,8 @@ def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
     factors / vectors it must write (8-byte words; 4 for FP32 factors)."""
     w = 4 if f32 else 8
     mm = m * m
+    if phase == "factor+forward":   # the factor's blocks plus f read and t written
+        return kernel_bytes(kind, "factor", level_nb, m, nrhs, f32) + level_nb * 2 * m * 8 * nrhs
     if kind == 0:  # block tridiagonal
         if phase == "factor":   # read D, Lo, Up; write E, R, Z, X
             return level_nb * (3 * mm * 8 + 4 * mm * w)
@@ -117,25 +121,32 @@ def main():
     levels = pf.pf_factor_levels(F)
     torch.cuda.synchronize()
 
-    def step():
+    def step_fused():
+        pf.pf_factor_solve(F, f, x, want_info=False)
+
+    def step_split():
         pf.pf_refactor(F)
         pf.pf_solve(F, f, x, want_info=False)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b in evs:
-        a.record()
-        step()
-        b.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per = np.array([a.elapsed_time(b) for a, b in evs])      # ms
-    ms_per_step = wall * 1e3 / args.steps
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record()
+            step()
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall * 1e3 / args.steps, np.array([a.elapsed_time(b) for a, b in evs])
+
+    split_ms, _ = timed(step_split)
+    step = step_split if args.split else step_fused
+    ms_per_step, per = timed(step)
 
     # acceptance of the result: FP64 residual with torch block products
     # (independent of the library's kernels)
@@ -171,6 +182,7 @@ def main():
     dom = max(kernels, key=lambda k: k["avg_us"])
     tile0 = args.map != "rows" and m in (2, 3, 4, 5, 6, 7, 8)
     names = {"factor": f"k_btri_factor{'_tile' if tile0 else ''}<{m}, double, false>",
+             "factor+forward": f"k_btri_factor_solve<{m}, double, false>",
              "forward": f"k_fwd<0, {m}, 1, double, false>", "backward": f"k_bwd<0, {m}, 1, double>"}
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6
@@ -196,10 +208,12 @@ def main():
                    "partitions": args.partitions or "planner",
                    "lane_mapping": args.map,
                    "levels": [[k, a, b] for k, a, b in levels],
-                   "step": "pf_refactor + pf_solve"},
+                   "step": "pf_refactor + pf_solve" if args.split else
+                           "pf_factor_solve (refactor + solve, forward sweep fused per level)"},
         "eta": eta,
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                        "mean_events": float(per.mean())},
+        "split_ms_per_step": split_ms,
         "step_alg_GBps": round(total_alg / (per.mean() * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": dom_name, "level": dom["level"],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

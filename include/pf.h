@@ -132,8 +132,9 @@ int pf_refactor(pf_factor_t F, void *stream);
  * handle's factor and solve calls (on the stream they run on).  Off by
  * default.  pf_profile_read synchronizes and returns the number of entries
  * of the most recent factor/refactor and solve calls (up to max are copied):
- * phase 0 = factor, 1 = forward sweep, 2 = back substitution; level = the
- * recursion level; ms = the launch's duration. */
+ * phase 0 = factor, 1 = forward sweep, 2 = back substitution, 3 = factor
+ * with the forward sweep fused (pf_factor_solve); level = the recursion
+ * level; ms = the launch's duration. */
 int pf_profile_enable(pf_factor_t F, int enable);
 int pf_profile_read(pf_factor_t F, int32_t max, int32_t *phase, int32_t *level, float *ms);
 
@@ -145,6 +146,17 @@ int pf_profile_read(pf_factor_t F, int32_t max, int32_t *phase, int32_t *level, 
  * synchronizes once per refinement step to test eta. */
 int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
              int64_t ldx, void *stream, pf_info *info);
+
+/* Factor-and-solve: factor A again in the handle's memory (as pf_refactor:
+ * same pointers, new values) and solve A x = f, as pf_refactor followed by
+ * pf_solve.  Where every level runs on the tile mapping and 1 <= nrhs <= m
+ * (padded block size), each level is factored and its right-hand sides are
+ * swept forward in one pass (the F solve of Sec. 2 alongside the
+ * factorization), which saves one pass over the factors per level.  The
+ * factors stay in the handle for later pf_solve calls.  nrhs = 0 only
+ * refactors.  Arguments, errors and synchronization as for pf_solve. */
+int pf_factor_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
+                    int64_t ldx, void *stream, pf_info *info);
 
 /* ---- batches of independent systems ---------------------------------------
  * The partitions of many systems run side by side: every system's

@@ -326,20 +326,35 @@ std::vector<SolveArgs> solve_args(const pf_factor_s *F, int nrhs, const double *
     return args;
 }
 
+// Level-0 matrix copied into the instantiated block size (M != m).
+hipError_t pad_matrix(pf_factor_s *F, hipStream_t s)
+{
+    const pf_matrix &A0 = F->A;
+    hipError_t e = launch_pad_blocks(A0.m, F->M, A0.nb, A0.D, F->padD, 1.0, s);
+    if (e == hipSuccess) e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Lo, F->padLo, 0.0, s);
+    if (e == hipSuccess && F->padUp)
+        e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Up, F->padUp, 0.0, s);
+    if (e == hipSuccess && F->padC) e = launch_pad_blocks(A0.m, F->M, 1, A0.C, F->padC, 0.0, s);
+    return e;
+}
+
+// ||A||_inf for the refinement loop and eta, when the options ask for them.
+hipError_t launch_norm(pf_factor_s *F, hipStream_t s)
+{
+    if (F->opts.prec != PF_FP32_IR && !(F->opts.flags & PF_FLAG_ETA)) return hipSuccess;
+    const pf_matrix *A = &F->A;
+    hipError_t e = launch_fill_u64(F->d_norm, 1, 0ull, s);
+    if (e == hipSuccess)
+        e = launch_norminf(A->kind, A->m, A->nb, A->D, A->Lo, A->Up, A->C, F->d_norm, s);
+    return e;
+}
+
 hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
 {
     F->prof_fac_n = 0;
     hipError_t e = launch_fill_u64(F->d_status, 1, ~0ull, s);
     if (e != hipSuccess) return e;
-    if (F->M != F->m) {
-        const pf_matrix &A0 = F->A;
-        e = launch_pad_blocks(A0.m, F->M, A0.nb, A0.D, F->padD, 1.0, s);
-        if (e == hipSuccess) e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Lo, F->padLo, 0.0, s);
-        if (e == hipSuccess && F->padUp)
-            e = launch_pad_blocks(A0.m, F->M, A0.nb - 1, A0.Up, F->padUp, 0.0, s);
-        if (e == hipSuccess && F->padC) e = launch_pad_blocks(A0.m, F->M, 1, A0.C, F->padC, 0.0, s);
-        if (e != hipSuccess) return e;
-    }
+    if (F->M != F->m && (e = pad_matrix(F, s)) != hipSuccess) return e;
     for (size_t l = 0; l < F->lv.size(); ++l) {
         const Level &L = F->lv[l];
         const LevelArgs a = level_args(F, l);
@@ -349,13 +364,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         });
         if (e != hipSuccess) return e;
     }
-    const pf_matrix *A = &F->A;
-    if (F->opts.prec == PF_FP32_IR || (F->opts.flags & PF_FLAG_ETA)) {
-        e = launch_fill_u64(F->d_norm, 1, 0ull, s);
-        if (e != hipSuccess) return e;
-        e = launch_norminf(A->kind, A->m, A->nb, A->D, A->Lo, A->Up, A->C, F->d_norm, s);
-    }
-    return e;
+    return launch_norm(F, s);
 }
 
 int ensure_workspace(pf_factor_s *F, int nrhs)
@@ -433,6 +442,58 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
                                       : launch_babd_fwd(M, lv.f32, args[l], s);
         }));
     }
+    for (size_t l = L; l-- > 0;) {
+        const Level &lv = F->lv[l];
+        HIPCHK(prof_launch(F, false, 2, (int)l, s, [&] {
+            return lv.kind == PF_BTRI ? launch_btri_bwd(M, lv.f32, args[l], s)
+                                      : launch_babd_bwd(M, lv.f32, args[l], s);
+        }));
+    }
+    if (M != F->m)
+        HIPCHK(launch_pad_rhs(F->m, M, F->nb, nrhs, F->wsPadX, (int64_t)F->nb * M, x, ldx, false,
+                              s));
+    return 0;
+}
+
+// Factor-and-solve in one pass per level (every level on the tile mapping,
+// 1 <= nrhs <= M): the factor kernels also sweep the right-hand sides
+// forward, then the back substitution runs up the levels as in run_solve.
+bool fused_ok(const pf_factor_s *F, int nrhs)
+{
+    if (nrhs < 1 || nrhs > F->M) return false;
+    for (const Level &L : F->lv)
+        if (!L.tile) return false;
+    return true;
+}
+
+int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
+                     int64_t ldx, hipStream_t s)
+{
+    const int M = F->M;
+    const size_t L = F->lv.size();
+    F->prof_fac_n = 0;
+    F->prof_sol_n = 0;
+    HIPCHK(launch_fill_u64(F->d_status, 1, ~0ull, s));
+    const double *F0 = f;
+    int64_t ld0f = ldf, ld0y = ldx;
+    double *Y0 = x;
+    if (M != F->m) {
+        HIPCHK(pad_matrix(F, s));
+        const int64_t ldp = (int64_t)F->nb * M;
+        HIPCHK(launch_pad_rhs(F->m, M, F->nb, nrhs, f, ldf, F->wsPadF, ldp, true, s));
+        F0 = F->wsPadF;
+        Y0 = F->wsPadX;
+        ld0f = ld0y = ldp;
+    }
+    const std::vector<SolveArgs> args = solve_args(F, nrhs, F0, ld0f, Y0, ld0y);
+    for (size_t l = 0; l < L; ++l) {
+        const Level &lv = F->lv[l];
+        const LevelArgs a = level_args(F, l);
+        HIPCHK(prof_launch(F, true, 3, (int)l, s, [&] {
+            return launch_factor_solve(lv.kind, M, lv.f32, a, args[l], s);
+        }));
+    }
+    HIPCHK(launch_norm(F, s));
     for (size_t l = L; l-- > 0;) {
         const Level &lv = F->lv[l];
         HIPCHK(prof_launch(F, false, 2, (int)l, s, [&] {
@@ -718,8 +779,16 @@ int pf_sync_status(pf_factor_t F, pf_info *info)
     return info->status;
 }
 
-int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x, int64_t ldx,
-             void *stream, pf_info *info)
+}  // extern "C"
+
+namespace {
+
+// A solve call: x = A^{-1} f by `first` (a pass of the method over the
+// right-hand sides: run_solve, or run_factor_solve that also refactors),
+// then, for PF_FP32_IR, FP64 refinement with correction solves.
+template <class First>
+int solve_call(pf_factor_s *F, int32_t nrhs, const double *f, int64_t ldf, double *x, int64_t ldx,
+               void *stream, pf_info *info, First first)
 {
     if (!F) return -1;
     if (nrhs < 0) return -2;
@@ -737,8 +806,8 @@ int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *
     if (nrhs == 0) return 0;
     int rc = ensure_workspace(F, nrhs);
     if (rc) return rc;
+    if ((rc = first(s))) return rc;
     if (F->opts.prec == PF_FP64) {
-        if ((rc = run_solve(F, nrhs, f, ldf, x, ldx, s))) return rc;
         if (info) {
             if (F->opts.flags & PF_FLAG_ETA) {
                 double eta;
@@ -752,7 +821,6 @@ int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *
         return 0;
     }
     // FP32 bulk + FP64 refinement: x0 = solve32(f); r = f - A x; d = solve32(r); x += d
-    if ((rc = run_solve(F, nrhs, f, ldf, x, ldx, s))) return rc;
     double eta = INFINITY, prev = INFINITY;
     int iters = 0, slow = 0, status = PF_OK;
     for (;;) {
@@ -776,6 +844,35 @@ int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *
         info->eta = eta;
     }
     return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x, int64_t ldx,
+             void *stream, pf_info *info)
+{
+    return solve_call(F, nrhs, f, ldf, x, ldx, stream, info,
+                      [&](hipStream_t s) { return run_solve(F, nrhs, f, ldf, x, ldx, s); });
+}
+
+int pf_factor_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
+                    int64_t ldx, void *stream, pf_info *info)
+{
+    if (F && nrhs == 0) {
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            info->eta = -1.0;
+            info->bad_block = -1;
+        }
+        return pf_refactor(F, stream);
+    }
+    return solve_call(F, nrhs, f, ldf, x, ldx, stream, info, [&](hipStream_t s) {
+        if (fused_ok(F, nrhs)) return run_factor_solve(F, nrhs, f, ldf, x, ldx, s);
+        if (launch_factor_levels(F, s) != hipSuccess) return (int)PF_EHIP;
+        return run_solve(F, nrhs, f, ldf, x, ldx, s);
+    });
 }
 
 void pf_destroy(pf_factor_t F)

@@ -667,21 +667,28 @@ __device__ __forceinline__ T dot(const T (&u)[M], const T (&v)[M])
 }
 
 // Block tridiagonal factor, tile mapping (same recurrences, storage and
-// outputs as btri_factor_body).
-template <int M, typename T, bool ADD>
-__device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_t pblock)
+// outputs as btri_factor_body).  RHS: the forward sweep of a solve runs in
+// the same pass (factor-and-solve, the F solve of Sec. 2 next to the
+// factorization): lane (r, c) also carries entry r of right-hand-side column
+// c (c < nrhs <= M) of f' and t, and the level's t and reduced right-hand
+// side are written as by fwd_body.
+template <int M, typename T, bool ADD, bool RHS>
+__device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, const SolveArgs &sv,
+                                                      int64_t pblock)
 {
     constexpr int LP = M * M, PPW = WG / LP;
     constexpr size_t MM = (size_t)M * M;
     const int tid = threadIdx.x, grp = tid / LP, t = tid % LP;
     const int r = t % M, c = t / M;
     constexpr int RS = M + kPad<T>;
-    constexpr int GS = group_stride<T>(4 * M * RS);
+    constexpr int NS = RHS ? 5 : 4;
+    constexpr int GS = group_stride<T>(NS * M * RS);
     __shared__ __align__(16) T lds[PPW * GS];
     T *S0 = lds + grp * GS;   // tableau; then E by rows; then R by rows
     T *S1 = S0 + M * RS;      // Z' by columns; then X by columns
     T *S2 = S1 + M * RS;      // A(g+1,g) by rows
     T *S3 = S2 + M * RS;      // Zh by columns
+    T *S4 = S3 + M * RS;      // (RHS) f' by columns; then t by columns
 
     const int64_t nb = a.nb;
     const int64_t part = pblock * PPW + grp;
@@ -690,12 +697,22 @@ __device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_
     T *dump = (T *)a.dump + tid;
     const int cm = r + c * M;   // column-major offset of (r, c)
     const int rm = r * M + c;   // row-major offset
+    // right-hand-side column of this lane (RHS), clamped to an existing one
+    const bool act = RHS && c < sv.nrhs;
+    const int64_t fo = (int64_t)r + (int64_t)(act ? c : 0) * sv.ldf;
+    const int64_t yo = (int64_t)r + (int64_t)(act ? c : 0) * sv.ldy;
+    double *ydump = (double *)a.dump + WG + tid;
 
-    T d = T(0), z = T(0), rr = T(0), a1 = T(0);
+    T d = T(0), z = T(0), rr = T(0), a1 = T(0), fp = T(0), gl = T(0);
     if (G.valid) {
         double v = a.D[G.start * MM + cm];
         if constexpr (ADD) v += a.Dadd[G.start * MM + cm];
         d = (T)v;
+        if constexpr (RHS) {
+            double w = act ? sv.F[G.start * M + fo] : 0.0;
+            if constexpr (ADD) w += act ? sv.Fadd[G.start * M + fo] : 0.0;
+            fp = (T)w;
+        }
     }
     if (G.hasL) {
         z = (T)a.Lo[(G.start - 1) * MM + cm];    // A(g_1, sL)
@@ -703,24 +720,29 @@ __device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_
     }
     unsigned long long bad = ~0ull;
 
-    // column c of A(g,g+1), entry (r,c) of A(g+1,g) and of D[g+1], one block
-    // row ahead, from the zero block when they do not exist
-    // (the two addends of D[g+1] are summed only where the row uses them)
-    auto load_next = [&](int64_t g, bool ok, T (&upc)[M], T &lo, double &dn, double &da) {
+    // column c of A(g,g+1), entry (r,c) of A(g+1,g), of D[g+1] and (RHS) of
+    // f[g+1], one block row ahead, from the zero block when they do not
+    // exist; the two addends of a sum stay apart until the row that uses them
+    auto load_next = [&](int64_t g, bool ok, T (&upc)[M], T &lo, double &dn, double &da,
+                         double &fn, double &fa) {
         ld_vec<M, T>(upc, (ok ? a.Up + g * MM : a.zero) + c * M);
         lo = (T)*((ok ? a.Lo + g * MM : a.zero) + cm);
         dn = *((ok ? a.D + (g + 1) * MM : a.zero) + cm);
         if constexpr (ADD) da = *((ok ? a.Dadd + (g + 1) * MM : a.zero) + cm);
+        if constexpr (RHS) {
+            fn = *((ok && act) ? sv.F + (g + 1) * M + fo : a.zero);
+            if constexpr (ADD) fa = *((ok && act) ? sv.Fadd + (g + 1) * M + fo : a.zero);
+        }
     };
     T upc[M], lo;
-    double dn, da = 0.0;
-    load_next(G.start, G.len > 0 && G.start + 1 < nb, upc, lo, dn, da);
+    double dn, da = 0.0, fn = 0.0, fa = 0.0;
+    load_next(G.start, G.len > 0 && G.start + 1 < nb, upc, lo, dn, da, fn, fa);
 
     for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
         T upn[M], lon;
-        double dnn, dan = 0.0;
-        load_next(g + 1, k + 1 < G.len && g + 2 < nb, upn, lon, dnn, dan);
+        double dnn, dan = 0.0, fnn = 0.0, fan = 0.0;
+        load_next(g + 1, k + 1 < G.len && g + 2 < nb, upn, lon, dnn, dan, fnn, fan);
 
         T b = d;
         int sigma = 0, pc = 0;
@@ -732,12 +754,20 @@ __device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_
         S0[sigma * RS + pc] = b;   // E_k by (logical) rows
         S1[c * RS + r] = z;        // Z'_k by columns
         S2[r * RS + c] = lo;       // A(g+1,g) by rows
+        if constexpr (RHS) S4[c * RS + r] = fp;   // f'_k by columns
         wave_sync();
         T er[M], zc[M], lr[M];
         lds_row<M, T>(er, S0 + r * RS);
         lds_row<M, T>(zc, S1 + c * RS);
         lds_row<M, T>(lr, S2 + r * RS);
         const T x = dot<M, T>(er, upc), zh = dot<M, T>(er, zc);
+        T tk = T(0);
+        if constexpr (RHS) {
+            T fc[M];
+            lds_row<M, T>(fc, S4 + c * RS);
+            tk = dot<M, T>(er, fc);                              // t_k = E_k f'_k
+            *(act ? sv.Y + g * M + yo : ydump) = (double)tk;
+        }
         E[g * MM + sigma * M + pc] = b;
         *(G.hasL ? R + g * MM + rm : dump) = rr;
         Xs[g * MM + rm] = x;
@@ -746,6 +776,7 @@ __device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_
         S0[r * RS + c] = rr;       // R_k by rows
         S1[c * RS + r] = x;        // X_k by columns
         S3[c * RS + r] = zh;       // Zh_k by columns
+        if constexpr (RHS) S4[c * RS + r] = tk;   // t_k by columns
         wave_sync();
         T rw[M], xc[M], hc[M];
         lds_row<M, T>(rw, S0 + r * RS);
@@ -755,11 +786,19 @@ __device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_
         rr = -dot<M, T>(rw, xc);
         d = (T)(ADD ? dn + da : dn) - dot<M, T>(lr, xc);
         z = -dot<M, T>(lr, hc);
+        if constexpr (RHS) {
+            T tc[M];
+            lds_row<M, T>(tc, S4 + c * RS);
+            gl -= dot<M, T>(rw, tc);                             // g_sL -= R_k t_k
+            fp = (T)(ADD ? fn + fa : fn) - dot<M, T>(lr, tc);    // f'_{k+1}
+        }
 #pragma unroll
         for (int l = 0; l < M; ++l) upc[l] = upn[l];
         lo = lon;
         dn = dnn;
         da = dan;
+        fn = fnn;
+        fa = fan;
         wave_sync();
     }
     if (bad != ~0ull) atomicMin(a.status, bad);
@@ -771,42 +810,62 @@ __device__ __forceinline__ void btri_factor_tile_body(const LevelArgs &a, int64_
         a.nDadd[(part - 1) * MM + cm] = (double)a1;             // alpha_1
         if (G.hasR) a.nUp[(part - 1) * MM + cm] = (double)rr;   // gamma
     }
+    if constexpr (RHS) {
+        if (act) {
+            const int64_t no = (int64_t)r + (int64_t)c * sv.ldn;
+            if (G.hasR) sv.nF[part * M + no] = (double)fp;          // f[sR] - A(sR,g_n) t_n
+            if (G.hasL) sv.nFadd[(part - 1) * M + no] = (double)gl; // - sum R_k t_k
+        }
+    }
 }
 
 // Bidiagonal-plus-corner factor, tile mapping (same outputs as
 // babd_factor_body).  D' = D here, so the inversion of the next block row
-// does not wait for the chain.
-template <int M, typename T>
-__device__ __forceinline__ void babd_factor_tile_body(const LevelArgs &a, int64_t pblock)
+// does not wait for the chain.  RHS as in btri_factor_tile_body.
+template <int M, typename T, bool RHS>
+__device__ __forceinline__ void babd_factor_tile_body(const LevelArgs &a, const SolveArgs &sv,
+                                                      int64_t pblock)
 {
     constexpr int LP = M * M, PPW = WG / LP;
     constexpr size_t MM = (size_t)M * M;
     const int tid = threadIdx.x, grp = tid / LP, t = tid % LP;
     const int r = t % M, c = t / M;
     constexpr int RS = M + kPad<T>;
-    constexpr int GS = group_stride<T>(4 * M * RS);
+    constexpr int NS = RHS ? 5 : 4;
+    constexpr int GS = group_stride<T>(NS * M * RS);
     __shared__ __align__(16) T lds[PPW * GS];
     T *S0 = lds + grp * GS;   // tableau; then E by rows
     T *S1 = S0 + M * RS;      // Z' by columns
     T *S2 = S1 + M * RS;      // A(g+1,g) by rows
     T *S3 = S2 + M * RS;      // Zh by columns
+    T *S4 = S3 + M * RS;      // (RHS) f' by columns; then t by columns
 
     const int64_t part = pblock * PPW + grp;
     const Geo G = geometry<1>(a.nb, a.p, part);
     T *E = (T *)a.E, *Zs = (T *)a.Z;
     const int cm = r + c * M, rm = r * M + c;
+    const bool act = RHS && c < sv.nrhs;
+    const int64_t fo = (int64_t)r + (int64_t)(act ? c : 0) * sv.ldf;
+    const int64_t yo = (int64_t)r + (int64_t)(act ? c : 0) * sv.ldy;
+    double *ydump = (double *)a.dump + WG + tid;
 
     T z = G.valid ? (T)a.Lo[(G.start - 1) * MM + cm] : T(0);   // A(g_1, sL)
+    T fp = T(0);
+    if constexpr (RHS) fp = (G.valid && act) ? (T)sv.F[G.start * M + fo] : T(0);
     unsigned long long bad = ~0ull;
     T dc = (T)*((G.len > 0 ? a.D + G.start * MM : a.zero) + cm);
     T lc = (T)*((G.len > 0 ? a.Lo + G.start * MM : a.zero) + cm);
+    double fc = 0.0;
+    if constexpr (RHS) fc = *((G.len > 0 && act) ? sv.F + (G.start + 1) * M + fo : a.zero);
     for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
         const bool more = k + 1 < G.len;
         T b = dc;
         const T lo = lc;
+        const double fn = fc;
         dc = (T)*((more ? a.D + (g + 1) * MM : a.zero) + cm);
         lc = (T)*((more ? a.Lo + (g + 1) * MM : a.zero) + cm);
+        if constexpr (RHS) fc = *((more && act) ? sv.F + (g + 2) * M + fo : a.zero);
 
         int sigma = 0, pc = 0;
         bool sing = false;
@@ -817,19 +876,33 @@ __device__ __forceinline__ void babd_factor_tile_body(const LevelArgs &a, int64_
         S0[sigma * RS + pc] = b;
         S1[c * RS + r] = z;
         S2[r * RS + c] = lo;
+        if constexpr (RHS) S4[c * RS + r] = fp;
         wave_sync();
         T er[M], zc[M], lr[M];
         lds_row<M, T>(er, S0 + r * RS);
         lds_row<M, T>(zc, S1 + c * RS);
         lds_row<M, T>(lr, S2 + r * RS);
         const T zh = dot<M, T>(er, zc);
+        T tk = T(0);
+        if constexpr (RHS) {
+            T fv[M];
+            lds_row<M, T>(fv, S4 + c * RS);
+            tk = dot<M, T>(er, fv);
+            *(act ? sv.Y + g * M + yo : ydump) = (double)tk;
+        }
         E[g * MM + sigma * M + pc] = b;
         Zs[g * MM + rm] = zh;
         S3[c * RS + r] = zh;
+        if constexpr (RHS) S4[c * RS + r] = tk;
         wave_sync();
         T hc[M];
         lds_row<M, T>(hc, S3 + c * RS);
         z = -dot<M, T>(lr, hc);
+        if constexpr (RHS) {
+            T tc[M];
+            lds_row<M, T>(tc, S4 + c * RS);
+            fp = (T)fn - dot<M, T>(lr, tc);
+        }
         wave_sync();
     }
     if (bad != ~0ull) atomicMin(a.status, bad);
@@ -840,6 +913,13 @@ __device__ __forceinline__ void babd_factor_tile_body(const LevelArgs &a, int64_
         if (part == 0) {
             a.nD[cm] = a.D[cm];
             a.nC[cm] = a.C[cm];
+        }
+        if constexpr (RHS) {
+            if (act) {
+                const int64_t no = (int64_t)r + (int64_t)c * sv.ldn;
+                sv.nF[(part + 1) * M + no] = (double)fp;
+                if (part == 0) sv.nF[no] = sv.F[fo];
+            }
         }
     }
 }
@@ -1073,26 +1153,37 @@ __global__ __launch_bounds__(WG) void kb_babd_factor(const LevelArgs *tab, const
 template <int M, typename T, bool ADD>
 __global__ __launch_bounds__(WG) void k_btri_factor_tile(LevelArgs a)
 {
-    btri_factor_tile_body<M, T, ADD>(a, blockIdx.x);
+    btri_factor_tile_body<M, T, ADD, false>(a, SolveArgs{}, blockIdx.x);
 }
 template <int M, typename T, bool ADD>
 __global__ __launch_bounds__(WG) void kb_btri_factor_tile(const LevelArgs *tab, const int4 *work)
 {
     const int4 w = work[blockIdx.x];
     const LevelArgs a = tab[w.x];
-    btri_factor_tile_body<M, T, ADD>(a, w.y);
+    btri_factor_tile_body<M, T, ADD, false>(a, SolveArgs{}, w.y);
 }
 template <int M, typename T>
 __global__ __launch_bounds__(WG) void k_babd_factor_tile(LevelArgs a)
 {
-    babd_factor_tile_body<M, T>(a, blockIdx.x);
+    babd_factor_tile_body<M, T, false>(a, SolveArgs{}, blockIdx.x);
 }
 template <int M, typename T>
 __global__ __launch_bounds__(WG) void kb_babd_factor_tile(const LevelArgs *tab, const int4 *work)
 {
     const int4 w = work[blockIdx.x];
     const LevelArgs a = tab[w.x];
-    babd_factor_tile_body<M, T>(a, w.y);
+    babd_factor_tile_body<M, T, false>(a, SolveArgs{}, w.y);
+}
+// factor-and-solve: factor a level and sweep its right-hand sides forward
+template <int M, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void k_btri_factor_solve(LevelArgs a, SolveArgs sv)
+{
+    btri_factor_tile_body<M, T, ADD, true>(a, sv, blockIdx.x);
+}
+template <int M, typename T>
+__global__ __launch_bounds__(WG) void k_babd_factor_solve(LevelArgs a, SolveArgs sv)
+{
+    babd_factor_tile_body<M, T, true>(a, sv, blockIdx.x);
 }
 template <int KIND, int M, int KC, typename T, bool ADD>
 __global__ __launch_bounds__(WG) void k_fwd(SolveArgs a)
@@ -1210,6 +1301,28 @@ hipError_t launch_babd_factor(int M, bool f32, bool tile, const LevelArgs &a, hi
         const dim3 grid = grid_for(MV, a.p, 1, 1);
         if (f32) hipLaunchKernelGGL((k_babd_factor<MV, float>), grid, dim3(WG), 0, s, a);
         else hipLaunchKernelGGL((k_babd_factor<MV, double>), grid, dim3(WG), 0, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_factor_solve(int kind, int M, bool f32, const LevelArgs &a, const SolveArgs &sv,
+                               hipStream_t s)
+{
+    if (sv.nrhs < 1 || sv.nrhs > M) return hipErrorInvalidValue;
+    return dispatch_Mtile(M, [&](auto mc) {
+        constexpr int MV = decltype(mc)::value;
+        const dim3 grid((unsigned)((a.p + partitions_per_wg(MV, true) - 1) /
+                                   partitions_per_wg(MV, true)));
+        if (kind == 1) {
+            if (f32) hipLaunchKernelGGL((k_babd_factor_solve<MV, float>), grid, dim3(WG), 0, s, a, sv);
+            else hipLaunchKernelGGL((k_babd_factor_solve<MV, double>), grid, dim3(WG), 0, s, a, sv);
+        } else if (a.Dadd) {
+            if (f32) hipLaunchKernelGGL((k_btri_factor_solve<MV, float, true>), grid, dim3(WG), 0, s, a, sv);
+            else hipLaunchKernelGGL((k_btri_factor_solve<MV, double, true>), grid, dim3(WG), 0, s, a, sv);
+        } else {
+            if (f32) hipLaunchKernelGGL((k_btri_factor_solve<MV, float, false>), grid, dim3(WG), 0, s, a, sv);
+            else hipLaunchKernelGGL((k_btri_factor_solve<MV, double, false>), grid, dim3(WG), 0, s, a, sv);
+        }
         return hipGetLastError();
     });
 }

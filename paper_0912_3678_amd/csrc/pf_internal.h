@@ -69,6 +69,10 @@ hipError_t launch_btri_factor(int M, bool f32, bool tile, const LevelArgs &a, hi
 hipError_t launch_btri_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_btri_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_babd_factor(int M, bool f32, bool tile, const LevelArgs &a, hipStream_t s);
+// Factor-and-solve of one level (tile mapping only, 1 <= sv.nrhs <= M): the
+// factor of launch_*_factor plus the forward sweep of launch_*_fwd in one pass.
+hipError_t launch_factor_solve(int kind, int M, bool f32, const LevelArgs &a, const SolveArgs &sv,
+                               hipStream_t s);
 hipError_t launch_babd_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_babd_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 

@@ -24,7 +24,7 @@ EXPORTED = [
     "pf_sync_status", "pf_destroy", "pf_strerror", "pf_factor_levels", "pf_factor_level",
     "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
     "pf_plan", "pf_refactor", "pf_profile_enable", "pf_profile_read",
-    "pf_batch_create", "pf_batch_run", "pf_batch_factor", "pf_batch_destroy",
+    "pf_batch_create", "pf_batch_run", "pf_batch_factor", "pf_batch_destroy", "pf_factor_solve",
 ]
 
 
@@ -66,6 +66,7 @@ def load(path: str = LIB_PATH):
     sigs = {
         "pf_factor": (ctypes.c_int, [P(pf_matrix), P(pf_opts), vp, P(vp)]),
         "pf_solve": (ctypes.c_int, [vp, i32, vp, i64, vp, i64, vp, P(pf_info)]),
+        "pf_factor_solve": (ctypes.c_int, [vp, i32, vp, i64, vp, i64, vp, P(pf_info)]),
         "pf_solve_batch": (ctypes.c_int, [i32, P(pf_matrix), P(pf_opts), P(i32), P(vp), P(i64),
                                           P(vp), P(i64), vp, P(vp), P(pf_info)]),
         "pf_factor_bytes": (ctypes.c_size_t, [P(pf_matrix), P(pf_opts)]),
@@ -141,20 +142,31 @@ def pf_factor(A: pf_matrix, opts: pf_opts | None = None, stream=None):
     return h
 
 
-def pf_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_info=True):
-    """f, x: device FP64 tensors holding n x nrhs column-major data (shape
-    (nrhs, n) or (n,)).  Returns a pf_info (synchronizing) or None."""
+def _solve(fn, name, F, f, x, nrhs, ldf, ldx, stream, want_info):
     if nrhs is None:
         nrhs = 1 if f.dim() == 1 else f.shape[0]
     n = f.shape[-1]
     ldf = n if ldf is None else ldf
     ldx = n if ldx is None else ldx
     info = pf_info() if want_info else None
-    rc = load().pf_solve(F, nrhs, _ptr(f), ldf, _ptr(x), ldx, _stream(stream),
-                         ctypes.byref(info) if info is not None else None)
+    rc = fn(F, nrhs, _ptr(f), ldf, _ptr(x), ldx, _stream(stream),
+            ctypes.byref(info) if info is not None else None)
     if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
-        raise PFError(rc, "pf_solve")
+        raise PFError(rc, name)
     return info
+
+
+def pf_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_info=True):
+    """f, x: device FP64 tensors holding n x nrhs column-major data (shape
+    (nrhs, n) or (n,)).  Returns a pf_info (synchronizing) or None."""
+    return _solve(load().pf_solve, "pf_solve", F, f, x, nrhs, ldf, ldx, stream, want_info)
+
+
+def pf_factor_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_info=True):
+    """Refactor (the values behind the handle's matrix pointers) and solve in
+    one call; arguments as pf_solve."""
+    return _solve(load().pf_factor_solve, "pf_factor_solve", F, f, x, nrhs, ldf, ldx, stream,
+                  want_info)
 
 
 def pf_refactor(F, stream=None):
@@ -167,7 +179,7 @@ def pf_profile_enable(F, on=True):
     load().pf_profile_enable(F, 1 if on else 0)
 
 
-PHASES = {0: "factor", 1: "forward", 2: "backward"}
+PHASES = {0: "factor", 1: "forward", 2: "backward", 3: "factor+forward"}
 
 
 def pf_profile_read(F):

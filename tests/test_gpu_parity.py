@@ -80,6 +80,48 @@ def test_lane_mappings(kind, m, nb, flag):
     G.check(s, x, tag=f"{kind} m={m} nb={nb} {flag} levels={levels}")
 
 
+@pytest.mark.parametrize("kind,m,nb,nrhs,prec", [
+    ("btri", 8, 4099, 1, "fp64"), ("btri", 8, 1001, 3, "fp64"), ("btri", 8, 300, 8, "fp64"),
+    ("btri", 8, 300, 9, "fp64"), ("btri", 4, 2049, 1, "fp64"), ("btri", 3, 700, 2, "fp64"),
+    ("btri", 2, 513, 2, "fp64"), ("btri", 16, 200, 1, "fp64"), ("btri", 1, 4096, 1, "fp64"),
+    ("babd", 8, 1001, 1, "fp64"), ("babd", 4, 300, 4, "fp64"), ("babd", 6, 77, 1, "fp64"),
+    ("btri", 8, 2049, 1, "fp32ir"), ("babd", 8, 1001, 2, "fp32ir")])
+def test_factor_solve(kind, m, nb, nrhs, prec):
+    """pf_factor_solve (refactor + solve, fused per level where it applies)
+    gives the oracle's solution, leaves factors that pf_solve can reuse, and
+    agrees with pf_refactor + pf_solve."""
+    import torch
+    seed = 700 + m * 11 + nb + nrhs
+    s = wl.random_btri(nb, m, seed=seed) if kind == "btri" else wl.random_babd(nb, m, seed=seed)
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((nb * m, nrhs))
+    A, keep = G.to_device(s)
+    opts = pf.make_opts(prec=pf.PF_FP32_IR if prec == "fp32ir" else pf.PF_FP64)
+    F = pf.pf_factor(A, opts)
+    try:
+        fd = G.rhs_to_device(f)
+        x1 = torch.full_like(fd, np.nan)
+        x2 = torch.full_like(fd, np.nan)
+        _say(kind, m, nb, nrhs, prec)
+        info = pf.pf_factor_solve(F, fd, x1)
+        assert info.status == 0
+        G.check(s, x1.cpu().numpy().T, f=f, tag=f"factor_solve {kind} m={m} nb={nb} k={nrhs}")
+        pf.pf_refactor(F)
+        info = pf.pf_solve(F, fd, x2)
+        assert info.status == 0
+        a, b = x1.cpu().numpy(), x2.cpu().numpy()
+        assert np.abs(a - b).max() <= (1e-13 if prec == "fp64" else 1e-10) * np.abs(b).max()
+        f3 = rng.standard_normal((nb * m, 1))       # the stored factors serve a new solve
+        f3d = G.rhs_to_device(f3)
+        x3 = torch.empty_like(f3d)
+        pf.pf_factor_solve(F, f3d, x3, nrhs=0)      # nrhs = 0: refactor only
+        info = pf.pf_solve(F, f3d, x3)
+        G.check(s, x3.cpu().numpy().T, f=f3, tag="after factor_solve")
+    finally:
+        pf.pf_destroy(F)
+    del keep
+
+
 @pytest.mark.parametrize("m", [4, 8])
 @pytest.mark.parametrize("nrhs", [2, 5, 9])
 def test_btri_multi_rhs(m, nrhs):
