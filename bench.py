@@ -40,8 +40,10 @@ def parse():
     ap.add_argument("--coarse-rows", type=int, default=0)
     ap.add_argument("--split", action="store_true",
                     help="time pf_refactor + pf_solve instead of the fused pf_factor_solve")
-    ap.add_argument("--map", choices=["auto", "rows", "tiles"], default="auto",
-                    help="factor lane mapping: planner default, or rows / tiles on every level")
+    ap.add_argument("--map", choices=["auto", "rows"], default="auto",
+                    help="factor lane mapping: planner default (segments), or rows on every level")
+    ap.add_argument("--lane-entries", type=int, default=0,
+                    help="segment mapping at level 0: block entries per lane (0 = planner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=10)
@@ -70,10 +72,15 @@ def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
     return level_nb * (mm * w + 2 * m * 8 * nrhs)           # read Z, t; write x
 
 
+KERNEL_SOURCES = ("kernels_common.h", "kernels_seg.hip", "kernels_rows.hip", "kernels_solve.hip")
+
+
 def source_hash():
+    """Hash of the kernel sources the recorded counters belong to."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_0912_3678_amd", "csrc", "kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0912_3678_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -114,9 +121,9 @@ def main():
     f = wl.to_device_rhs(s.f, dev)
     x = torch.empty_like(f)
     A = pf.make_matrix(pf.PF_BTRI, m, nb, D, Lo, Up)
-    flags = {"auto": 0, "rows": pf.PF_FLAG_MAP_ROWS, "tiles": pf.PF_FLAG_MAP_TILES}[args.map]
+    flags = {"auto": 0, "rows": pf.PF_FLAG_MAP_ROWS}[args.map]
     opts = pf.make_opts(partitions=args.partitions, block_rows=args.block_rows,
-                        coarse_rows=args.coarse_rows, flags=flags)
+                        coarse_rows=args.coarse_rows, flags=flags, lane_entries=args.lane_entries)
     F = pf.pf_factor(A, opts)
     levels = pf.pf_factor_levels(F)
     torch.cuda.synchronize()
@@ -180,10 +187,12 @@ def main():
         kernels.append({"phase": ph, "level": lvl, "nb": lnb, "p": lp, "avg_us": round(avg * 1e3, 2),
                         "alg_MB": round(b / 1e6, 3), "GBps": round(b / (avg * 1e-3) / 1e9, 1)})
     dom = max(kernels, key=lambda k: k["avg_us"])
-    tile0 = args.map != "rows" and m in (2, 3, 4, 5, 6, 7, 8)
-    names = {"factor": f"k_btri_factor{'_tile' if tile0 else ''}<{m}, double, false>",
-             "factor+forward": f"k_btri_factor_solve<{m}, double, false>",
-             "forward": f"k_fwd<0, {m}, 1, double, false>", "backward": f"k_bwd<0, {m}, 1, double>"}
+    M = 1 << (m - 1).bit_length()
+    E = 0 if args.map == "rows" else (args.lane_entries or {8: 2, 16: 4, 32: 0}.get(M, 1))
+    names = {"factor": (f"k_btri_seg<{M}, {E}, double, false, false>" if E else
+                        f"k_btri_factor<{M}, double, false>"),
+             "factor+forward": f"k_btri_seg<{M}, {E}, double, false, true>",
+             "forward": f"k_fwd<0, {M}, 1, double, false>", "backward": f"k_bwd<0, {M}, 1, double>"}
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6
     achieved = dom_bytes / (dom["avg_us"] * 1e-6) / 1e9
@@ -206,7 +215,7 @@ def main():
         "config": {"workload": "trapezoid_bvp_btri", "N": args.N, "m": m, "nb": nb,
                    "unknowns": n, "nrhs": 1,
                    "partitions": args.partitions or "planner",
-                   "lane_mapping": args.map,
+                   "lane_mapping": "rows" if args.map == "rows" else f"segments of {E}",
                    "levels": [[k, a, b] for k, a, b in levels],
                    "step": "pf_refactor + pf_solve" if args.split else
                            "pf_factor_solve (refactor + solve, forward sweep fused per level)"},

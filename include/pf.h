@@ -70,11 +70,13 @@ enum {
 enum {
     PF_FLAG_ETA = 1,       /* pf_solve in FP64 also computes eta (one residual pass)  */
     PF_FLAG_MAP_ROWS = 2,  /* factor every level with the row lane mapping (M lanes per
-                              partition, lane i holds row i of each block)            */
-    PF_FLAG_MAP_TILES = 4  /* factor every level with the tile lane mapping (M*M lanes
-                              per partition, one block entry per lane; m <= 8).
-                              Default: tiles wherever m <= 8, else rows.
-                              The mappings differ only in rounding.                  */
+                              partition, lane i holds row i of each block) instead of
+                              the default segment mapping (M*M/E lanes per partition,
+                              E block entries per lane: E = 1 for m <= 8 (2 at the
+                              finest level for m = 8), 4 for m = 16; m = 32 always
+                              uses rows).  The mappings differ
+                              only in rounding.                                      */
+    PF_FLAG_MAP_TILES = 4  /* reserved (the segment mapping is the default)         */
 };
 
 typedef struct {
@@ -97,6 +99,8 @@ typedef struct {
                            partitions == 0; 0 = autotuned table               */
     int32_t flags;      /* PF_FLAG_*                                          */
     int32_t coarse_rows;/* blocks per partition on the reduced levels; 0 = table */
+    int32_t lane_entries;/* finest level, segment lane mapping: block entries per
+                           lane (1: one entry; 2: m = 8; 4: m = 16); 0 = planner */
     double tol;         /* PF_FP32_IR target eta; <= 0 means 1e-12            */
 } pf_opts;
 

@@ -21,7 +21,7 @@ struct Level {
     int kind = PF_BTRI;
     int64_t nb = 0, p = 1;
     bool f32 = false;
-    bool tile = false;   // factor with the tile lane mapping
+    int seg = 0;          // factor lane mapping: E entries per lane (segments), 0 = rows
     const double *D = nullptr, *Dadd = nullptr, *Lo = nullptr, *Up = nullptr, *C = nullptr;
     void *E = nullptr, *R = nullptr, *Z = nullptr, *X = nullptr;
     double *nD = nullptr, *nDadd = nullptr, *nLo = nullptr, *nUp = nullptr, *nC = nullptr;
@@ -100,25 +100,30 @@ int target_rows(int M, bool f32, int level, const pf_opts &o)
     if (level == 0 && o.block_rows > 0) return o.block_rows;
     if (level > 0 && o.coarse_rows > 0) return o.coarse_rows;
     (void)f32;
-    // measured on MI355X for the m = 8 BVP: 8 blocks at level 0 and 3 on the
-    // reduced levels (latency-bound there: the chain length per level trades
-    // against the number of levels)
-    if (level == 0) return M <= 4 ? 16 : (M <= 8 ? 8 : 4);
+    // measured on MI355X for the m = 8 BVP (segment mapping, two entries per
+    // lane at level 0): 16 blocks at level 0, where 3855 partitions fill the
+    // resident wave slots about once, and 3 on the reduced levels (latency-
+    // bound: the chain length per level trades against the number of levels)
+    if (level == 0) return M <= 8 ? 16 : 4;
     return 3;
 }
 
 constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chain
 
-// Lane mapping of a level's factor kernel.  Tiles (one block entry per lane)
-// cut the latency of a chain row several times over, which is what bounds
-// the reduced levels; on the m = 8 benchmark they also match or beat rows at
-// level 0 (60.7 vs 62.3 us).  Rows remain for block sizes without a tile
-// kernel (1, 16, 32) and on request.
-bool use_tiles(int M, int level, const pf_opts &o)
+// Lane mapping of a level's factor kernel: segments of E entries per lane,
+// or rows (0).  One entry per lane (E = 1) spreads a chain row over M*M
+// lanes and gives the lowest latency per row, which bounds the reduced
+// levels; at level 0 (many partitions) fewer, wider lanes spend fewer
+// instructions per partition.  m = 16 uses four entries per lane (one wave
+// per partition), m = 32 the row mapping.
+int seg_width(int M, int level, const pf_opts &o)
 {
-    (void)level;
-    if (!tile_mapping_ok(M) || (o.flags & PF_FLAG_MAP_ROWS)) return false;
-    return true;
+    if (o.flags & PF_FLAG_MAP_ROWS) return 0;
+    if (level == 0 && o.lane_entries > 0) return seg_ok(M, o.lane_entries) ? o.lane_entries : 0;
+    if (level == 0 && M == 8) return 2;   // 0.153 vs 0.156 ms per step with one entry
+    for (int E = 1; E <= M; E <<= 1)
+        if (seg_ok(M, E)) return E;
+    return 0;
 }
 
 std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
@@ -232,7 +237,10 @@ pf_opts resolve_opts(const pf_opts *o)
 int check_opts(const pf_matrix *A, const pf_opts &o)
 {
     if (o.prec != PF_FP64 && o.prec != PF_FP32_IR) return -2;
-    if (o.partitions < 0 || o.block_rows < 0 || o.coarse_rows < 0) return -2;
+    if (o.partitions < 0 || o.block_rows < 0 || o.coarse_rows < 0 || o.lane_entries < 0) return -2;
+    if (o.lane_entries > 0 && !(o.flags & PF_FLAG_MAP_ROWS) &&
+        !seg_ok(padded_block(A->m), o.lane_entries))
+        return -2;
     if (o.partitions > 0) {
         const int64_t pmax = (A->kind == PF_BTRI) ? (A->nb + 1) / 2 : (A->nb - 1) / 2;
         if (o.partitions > pmax && !(A->kind == PF_BABD && A->nb == 2)) return -2;
@@ -359,8 +367,9 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         const Level &L = F->lv[l];
         const LevelArgs a = level_args(F, l);
         e = prof_launch(F, true, 0, (int)l, s, [&] {
-            return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, L.tile, a, s)
-                                       : launch_babd_factor(F->M, L.f32, L.tile, a, s);
+            if (L.seg) return launch_seg_factor(L.kind, F->M, L.seg, L.f32, a, nullptr, s);
+            return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
+                                       : launch_babd_factor(F->M, L.f32, a, s);
         });
         if (e != hipSuccess) return e;
     }
@@ -455,14 +464,14 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
     return 0;
 }
 
-// Factor-and-solve in one pass per level (every level on the tile mapping,
+// Factor-and-solve in one pass per level (every level on the segment mapping,
 // 1 <= nrhs <= M): the factor kernels also sweep the right-hand sides
 // forward, then the back substitution runs up the levels as in run_solve.
 bool fused_ok(const pf_factor_s *F, int nrhs)
 {
     if (nrhs < 1 || nrhs > F->M) return false;
     for (const Level &L : F->lv)
-        if (!L.tile) return false;
+        if (!L.seg) return false;
     return true;
 }
 
@@ -490,7 +499,7 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
         const Level &lv = F->lv[l];
         const LevelArgs a = level_args(F, l);
         HIPCHK(prof_launch(F, true, 3, (int)l, s, [&] {
-            return launch_factor_solve(lv.kind, M, lv.f32, a, args[l], s);
+            return launch_seg_factor(lv.kind, M, lv.seg, lv.f32, a, &args[l], s);
         }));
     }
     HIPCHK(launch_norm(F, s));
@@ -664,7 +673,7 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         L.nb = plan[l].nb;
         L.p = plan[l].p;
         L.f32 = (l == 0 && o.prec == PF_FP32_IR);
-        L.tile = use_tiles(M, (int)l, o);
+        L.seg = seg_width(M, (int)l, o);
         if (l == 0) {
             L.D = D0; L.Lo = Lo0;
             if (A->kind == PF_BTRI) L.Up = Up0;
@@ -996,7 +1005,8 @@ namespace {
 struct BatchLaunch {
     int phase;      // 0 factor, 1 forward sweep, 2 back substitution
     int kind, M, KC;
-    bool f32, add, tile;
+    bool f32, add;
+    int seg;        // factor launches: segment width (0 = rows)
     size_t work;    // first work item of this launch
     int nwg;
 };
@@ -1059,13 +1069,13 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
             if (l >= F->lv.size()) continue;
             const Level &L = F->lv[l];
             groups[{L.kind, F->M, L.f32 ? 1 : 0, (L.kind == PF_BTRI && L.Dadd) ? 1 : 0,
-                    L.tile ? 1 : 0}].push_back(i);
+                    L.seg}].push_back(i);
         }
         for (auto &kv : groups) {
             BatchLaunch bl{0, std::get<0>(kv.first), std::get<1>(kv.first), 1,
                            std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0,
-                           std::get<4>(kv.first) != 0, work.size(), 0};
-            const int gpw = partitions_per_wg(bl.M, bl.tile);
+                           std::get<4>(kv.first), work.size(), 0};
+            const int gpw = bl.seg ? seg_partitions_per_wg(bl.M, bl.seg) : groups_per_wg(bl.M);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(level_args(B->all[i], l));
@@ -1107,7 +1117,7 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
         for (auto &kv : groups) {
             BatchLaunch bl{phase, std::get<0>(kv.first), std::get<1>(kv.first),
                            std::get<4>(kv.first), std::get<2>(kv.first) != 0,
-                           std::get<3>(kv.first) != 0, false, work.size(), 0};
+                           std::get<3>(kv.first) != 0, 0, work.size(), 0};
             const int gpw = groups_per_wg(bl.M);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
@@ -1134,8 +1144,10 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
         if (e == hipSuccess && F->M != F->m) e = launch_pad_matrix(F, s);
     for (const auto &bl : B->flaunch)
         if (e == hipSuccess)
-            e = launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, bl.tile, B->d_lev,
-                                    B->d_lwork + bl.work, bl.nwg, s);
+            e = bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
+                                                 B->d_lwork + bl.work, bl.nwg, s)
+                       : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
+                                             B->d_lwork + bl.work, bl.nwg, s);
     if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
         for (auto *F : B->all) {
             const pf_matrix &A = F->A;

@@ -1,0 +1,263 @@
+// Helpers shared by the partition-method kernels (gfx950, wave64).
+//
+// A workgroup is one wave64 and a partition never leaves its wave, so the
+// only ordering needed between an LDS write and the reads of other lanes is
+// the in-order LDS pipe of the wave plus a compiler fence (wave_sync); no
+// workgroup barrier is used.
+//
+// Memory discipline inside the chain loops: no memory operation sits under
+// a branch (missing operands are read from a zero block, stores a lane must
+// not make go to a dump buffer, the zero-pivot report is deferred), and the
+// operands of the next block row are loaded before the current row's
+// stores.  The compiler's wait counters then stay exact and a row never waits
+// for the stores of the previous one (loads and stores share one in-order
+// counter on this architecture).
+#pragma once
+#include "pf_internal.h"
+
+#include <type_traits>
+
+namespace pf {
+namespace {
+
+constexpr int WG = 64;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
+__device__ __forceinline__ unsigned long long status_code(int level, int64_t block)
+{
+    return ((unsigned long long)level << 40) | (unsigned long long)block;
+}
+
+// ---- partition geometry ---------------------------------------------------
+// Balanced rule: the non-separator blocks are spread as evenly as possible,
+// the first (count mod p) partitions getting one block more.
+struct Geo {
+    int64_t start;   // first block of the partition
+    int len;         // blocks in the partition
+    int kmax;        // longest partition (uniform loop bound)
+    bool valid, hasL, hasR;
+};
+
+template <int KIND>
+__device__ __forceinline__ Geo geometry(int64_t nb, int64_t p, int64_t part)
+{
+    Geo g;
+    const int64_t nint = (KIND == 0) ? nb - (p - 1) : nb - (p + 1);
+    const int64_t q = nint / p, rem = nint % p;
+    g.valid = part < p;
+    const int64_t mn = part < rem ? part : rem;
+    g.start = (KIND == 0 ? 0 : 1) + part * (q + 1) + mn;
+    g.len = g.valid ? (int)(q + (part < rem ? 1 : 0)) : 0;
+    g.kmax = (int)(q + (rem > 0 ? 1 : 0));
+    if (KIND == 0) {
+        g.hasL = g.valid && part > 0;
+        g.hasR = g.valid && part < p - 1;
+    } else {
+        g.hasL = g.valid;
+        g.hasR = g.valid;
+    }
+    return g;
+}
+
+// ---- register <-> memory helpers ------------------------------------------
+// M contiguous doubles -> registers of type T
+template <int M, typename T>
+__device__ __forceinline__ void ld_vec(T (&v)[M], const double *__restrict__ p)
+{
+    if constexpr (M % 2 == 0) {
+#pragma unroll
+        for (int r = 0; r < M; r += 2) {
+            const double2 w = *reinterpret_cast<const double2 *>(p + r);
+            v[r] = (T)w.x;
+            v[r + 1] = (T)w.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = (T)p[r];
+    }
+}
+
+// registers -> M contiguous T (16-byte stores where the size allows)
+template <int M, typename T>
+__device__ __forceinline__ void st_fac(T *__restrict__ p, const T (&v)[M])
+{
+    if constexpr (sizeof(T) == 8 && M % 2 == 0) {
+#pragma unroll
+        for (int r = 0; r < M; r += 2)
+            *reinterpret_cast<double2 *>(p + r) = make_double2(v[r], v[r + 1]);
+    } else if constexpr (sizeof(T) == 4 && M % 4 == 0) {
+#pragma unroll
+        for (int r = 0; r < M; r += 4)
+            *reinterpret_cast<float4 *>(p + r) = make_float4(v[r], v[r + 1], v[r + 2], v[r + 3]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < M; ++r) p[r] = v[r];
+    }
+}
+
+// M contiguous T (factor storage) -> registers (16-byte loads where possible)
+template <int M, typename T>
+__device__ __forceinline__ void ld_fac(T (&v)[M], const T *__restrict__ p)
+{
+    if constexpr (sizeof(T) == 8 && M % 2 == 0) {
+#pragma unroll
+        for (int r = 0; r < M; r += 2) {
+            const double2 w = *reinterpret_cast<const double2 *>(p + r);
+            v[r] = w.x;
+            v[r + 1] = w.y;
+        }
+    } else if constexpr (sizeof(T) == 4 && M % 4 == 0) {
+#pragma unroll
+        for (int r = 0; r < M; r += 4) {
+            const float4 w = *reinterpret_cast<const float4 *>(p + r);
+            v[r] = w.x; v[r + 1] = w.y; v[r + 2] = w.z; v[r + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = p[r];
+    }
+}
+
+template <int M, typename T>
+__device__ __forceinline__ void ld_row_d(T (&v)[M], const double *__restrict__ blk, int i)
+{
+#pragma unroll
+    for (int l = 0; l < M; ++l) v[l] = (T)blk[i + l * M];
+}
+
+template <int M, typename T>
+__device__ __forceinline__ void zero(T (&v)[M])
+{
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = T(0);
+}
+
+// ---- LDS layout ---------------------------------------------------------------
+// Rows of the small matrices a group keeps in LDS are padded by 16 bytes and
+// the groups' regions start 16 bytes apart modulo 128, so the lanes of a group
+// (one row each) and the groups of a wave (one region each) fall into
+// different banks instead of all hitting the same one.
+template <typename T> constexpr int kPad = 16 / (int)sizeof(T);
+template <typename T> constexpr int kLine = 128 / (int)sizeof(T);
+template <typename T> constexpr int group_stride(int elems)
+{
+    return ((elems + kLine<T> - 1) / kLine<T>) * kLine<T> + kPad<T>;
+}
+
+// ---- pivot search: group-wide max of a packed key with DPP ----------------
+// A candidate's key is the high 32 bits of |v| (sign cleared) with the low 5
+// bits replaced by 31 - row: an unsigned max over the group then picks the
+// largest magnitude, compared to 15 (FP64) or 18 (FP32) mantissa bits, and
+// among equal keys the first row.  Rows already used as pivots have key 0,
+// below every candidate.  Each reduction stage is one max with a DPP operand.
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ unsigned pivot_key(double v, int row, bool used)
+{
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(v) >> 32) & 0x7fffffffu;
+    return used ? 0u : ((hi & ~31u) | (unsigned)(31 - row));
+}
+__device__ __forceinline__ unsigned pivot_key(float v, int row, bool used)
+{
+    const unsigned b = (unsigned)__float_as_int(v) & 0x7fffffffu;
+    return used ? 0u : ((b & ~31u) | (unsigned)(31 - row));
+}
+
+// The M lanes of a group are an aligned run inside a row of 16 (M <= 16) or a
+// half wave (M = 32), so these cross-lane moves never leave the group.
+template <int M>
+__device__ __forceinline__ int group_pivot(unsigned k)
+{
+    if constexpr (M >= 2) k = max(k, (unsigned)dpp_i<0xB1>((int)k));    // lane ^ 1
+    if constexpr (M >= 4) k = max(k, (unsigned)dpp_i<0x4E>((int)k));    // lane ^ 2
+    if constexpr (M >= 8) k = max(k, (unsigned)dpp_i<0x141>((int)k));   // half-row mirror
+    if constexpr (M >= 16) k = max(k, (unsigned)dpp_i<0x140>((int)k));  // row mirror
+    if constexpr (M >= 32) k = max(k, (unsigned)__shfl_xor((int)k, 16, 32));
+    return 31 - (int)(k & 31u);
+}
+
+// reciprocal: hardware estimate refined by Newton steps (two in FP64, one in FP32)
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// M entries of an LDS row (16-byte reads; rows are 16-byte aligned)
+template <int M, typename T>
+__device__ __forceinline__ void lds_row(T (&v)[M], const T *p)
+{
+    if constexpr (sizeof(T) == 8 && M % 2 == 0) {
+#pragma unroll
+        for (int l = 0; l < M; l += 2) {
+            const double2 w = *reinterpret_cast<const double2 *>(p + l);
+            v[l] = w.x;
+            v[l + 1] = w.y;
+        }
+    } else if constexpr (sizeof(T) == 4 && M % 4 == 0) {
+#pragma unroll
+        for (int l = 0; l < M; l += 4) {
+            const float4 w = *reinterpret_cast<const float4 *>(p + l);
+            v[l] = w.x; v[l + 1] = w.y; v[l + 2] = w.z; v[l + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) v[l] = p[l];
+    }
+}
+
+template <int M, typename T>
+__device__ __forceinline__ T dot(const T (&u)[M], const T (&v)[M])
+{
+    T s = T(0);
+#pragma unroll
+    for (int l = 0; l < M; ++l) s = fma(u[l], v[l], s);
+    return s;
+}
+
+template <typename F>
+hipError_t dispatch_M(int M, F &&f)
+{
+    switch (M) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename F>
+hipError_t dispatch_KC(int KC, F &&f)
+{
+    return KC == 1 ? f(std::integral_constant<int, 1>{}) : f(std::integral_constant<int, 4>{});
+}
+
+inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)
+{
+    const int64_t gpw = WG / M;
+    return dim3((unsigned)((p + gpw - 1) / gpw), (unsigned)((nrhs + KC - 1) / KC), 1);
+}
+
+}  // namespace
+}  // namespace pf

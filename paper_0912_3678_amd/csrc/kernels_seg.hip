@@ -1,0 +1,573 @@
+// Partition-method factor kernels, segment lane mapping (gfx950).
+//
+// One partition is owned by M*M/E lanes; lane (r, g) holds the E entries
+// (r, g*E .. g*E+E-1) of row r of every block of its chain, the M lanes of
+// one segment column g being consecutive.  E = 1 puts one block entry in each
+// lane: the chain row's work is spread over M*M lanes and its latency is
+// lowest, which is what bounds the reduced levels of the recursion (few
+// partitions).  Larger E spends fewer instructions per partition and suits
+// the finest level (many partitions, bound by issue and bandwidth).
+//
+// Pivot blocks are inverted in place by Gauss-Jordan exchange steps (row
+// partial pivoting inside the block, pivot ranked by pivot_key): step j
+// exchanges unknown j with the equation of its pivot row p_j; with v =
+// b(p_j, j) the tableau becomes b(p_j, j) = 1/v, b(p_j, l) = b(p_j, l)/v,
+// b(i, j) = -b(i, j)/v and b(i, l) = b(i, l) - b(i, j) b(p_j, l)/v.  After the
+// M steps entry (r, c) of the tableau is entry (sigma(r), p_c) of the
+// inverse, sigma(r) being the step at which row r was the pivot.  The pivot
+// search of step j+1 is a DPP reduction in the segment column holding
+// column j+1, right after step j's update, so a step costs one LDS round
+// trip.  Block products read rows of the left operand and columns of the
+// right operand from the partition's LDS slice; the factor kernels can also
+// sweep up to M right-hand sides forward in the same pass (factor-and-solve:
+// the F solve of Sec. 2 alongside the factorization), lane (r, g) carrying
+// right-hand-side columns g*E .. g*E+E-1.
+//
+// Outputs and recurrences are those of the row mapping (kernels_rows.hip):
+// row-major factor blocks E, X, Zh, R per block row, the reduced matrix of
+// eq. (redmatr) / (redmatr1), and for the forward sweep t and the reduced
+// right-hand side.
+#include "kernels_common.h"
+
+namespace pf {
+namespace {
+
+template <int M, int E> constexpr int seg_lanes() { return M * M / E; }
+
+// E consecutive T in LDS <-> registers (16- or 8-byte accesses when the
+// size and the alignment of segment starts allow)
+template <int E, typename T>
+__device__ __forceinline__ void lds_put(T *p, const T (&v)[E])
+{
+    if constexpr (sizeof(T) == 8 && E % 2 == 0) {
+#pragma unroll
+        for (int e = 0; e < E; e += 2) *reinterpret_cast<double2 *>(p + e) = make_double2(v[e], v[e + 1]);
+    } else if constexpr (sizeof(T) == 4 && E % 4 == 0) {
+#pragma unroll
+        for (int e = 0; e < E; e += 4)
+            *reinterpret_cast<float4 *>(p + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) p[e] = v[e];
+    }
+}
+template <int E, typename T>
+__device__ __forceinline__ void lds_get(T (&v)[E], const T *p)
+{
+    lds_row<E, T>(v, p);
+}
+
+// pivot row of column j: reduce in the segment column holding column j,
+// then broadcast to the partition's lanes
+template <int M, int E, typename T>
+__device__ __forceinline__ int seg_pivot(T bj, bool used, int r, int j)
+{
+    constexpr int LP = seg_lanes<M, E>();
+    const int idx = group_pivot<M>(pivot_key(bj, r, used));
+    if constexpr (LP == WG) return __builtin_amdgcn_readlane(idx, (j / E) * M);
+    else return __shfl(idx, (int)((threadIdx.x / LP) * LP) + (j / E) * M, WG);
+}
+
+// In-place Gauss-Jordan of the tableau b = D'(r, c0 .. c0+E-1); returns
+// sigma(r) and p_c of the lane's columns through the references.
+template <int M, int E, typename T>
+__device__ __forceinline__ void seg_invert(T (&b)[E], int r, int c0, T *S, int &sigma,
+                                           int (&pc)[E], bool &sing)
+{
+    constexpr int RS = M + kPad<T>;
+    bool used = false;
+    int pr = seg_pivot<M, E, T>(b[0], used, r, 0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        lds_put<E, T>(S + r * RS + c0, b);
+        wave_sync();
+        T prow[E];
+        lds_get<E, T>(prow, S + pr * RS + c0);
+        const T mcol = S[r * RS + j], pv = S[pr * RS + j];
+        sing = sing || (pv == T(0));
+        const T inv = recip(pv);
+        const bool isr = (r == pr);
+        // exchange step as selects of computed values (no divergent code):
+        // q = 1/v in the pivot row and -b(i,j)/v elsewhere; entries off
+        // column j become q b(p_j, l) + [row is not the pivot] b(i, l)
+        const T q = isr ? inv : -(mcol * inv);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const bool isc = (c0 + e == j);
+            const T sb = isr ? T(0) : b[e];
+            const T w = fma(q, prow[e], sb);
+            b[e] = isc ? q : w;
+            pc[e] = isc ? pr : pc[e];
+        }
+        used = used || isr;
+        sigma = isr ? j : sigma;
+        wave_sync();
+        if (j + 1 < M) pr = seg_pivot<M, E, T>(b[(j + 1) % E], used, r, j + 1);
+    }
+}
+
+// entries (r, c0 .. c0+E-1) of a column-major M x M block (FP64)
+template <int M, int E>
+__device__ __forceinline__ void ld_ent(double (&v)[E], const double *blk, int r, int c0)
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = blk[r + (c0 + e) * M];
+}
+
+// Block tridiagonal factor, segment mapping.  RHS: the forward sweep of up to
+// M right-hand sides runs in the same pass.
+template <int M, int E, typename T, bool ADD, bool RHS>
+__device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArgs &sv,
+                                              int64_t pblock)
+{
+    constexpr int LP = seg_lanes<M, E>(), PPW = WG / LP;
+    constexpr size_t MM = (size_t)M * M;
+    const int tid = threadIdx.x, grp = tid / LP, t = tid % LP;
+    const int r = t % M, c0 = (t / M) * E;
+    constexpr int RS = M + kPad<T>;
+    constexpr int NS = RHS ? 6 : 5;
+    constexpr int GS = group_stride<T>(NS * M * RS);
+    __shared__ __align__(16) T lds[PPW * GS];
+    T *S0 = lds + grp * GS;   // tableau; then E by rows; then R by rows
+    T *S1 = S0 + M * RS;      // Z' by columns; then X by columns
+    T *S2 = S1 + M * RS;      // A(g+1,g) by rows
+    T *S3 = S2 + M * RS;      // Zh by columns
+    T *S5 = S3 + M * RS;      // A(g,g+1) by columns
+    T *S4 = S5 + M * RS;      // (RHS) f' by columns; then t by columns
+
+    const int64_t nb = a.nb;
+    const int64_t part = pblock * PPW + grp;
+    const Geo G = geometry<0>(nb, a.p, part);
+    T *Ef = (T *)a.E, *R = (T *)a.R, *Zs = (T *)a.Z, *Xs = (T *)a.X;
+    T *dump = (T *)a.dump + tid * E;
+    double *ydump = (double *)a.dump + 2048 + tid * E;
+    const double *zero = a.zero;
+    // right-hand-side columns of this lane's entries (clamped to column 0
+    // when there is none; their loads then read the zero block)
+    bool act[E];
+    int64_t fo[E], yo[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        act[e] = RHS && (c0 + e < sv.nrhs);
+        fo[e] = (int64_t)r + (int64_t)(act[e] ? c0 + e : 0) * sv.ldf;
+        yo[e] = (int64_t)r + (int64_t)(act[e] ? c0 + e : 0) * sv.ldy;
+    }
+
+    T d[E], z[E], rr[E], a1[E], fp[E], gl[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) { d[e] = z[e] = rr[e] = a1[e] = fp[e] = gl[e] = T(0); }
+    if (G.valid) {
+        double v[E];
+        ld_ent<M, E>(v, a.D + G.start * MM, r, c0);
+        if constexpr (ADD) {
+            double w[E];
+            ld_ent<M, E>(w, a.Dadd + G.start * MM, r, c0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] += w[e];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) d[e] = (T)v[e];
+        if constexpr (RHS) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                double w = *(act[e] ? sv.F + G.start * M + fo[e] : zero);
+                if constexpr (ADD) w += *(act[e] ? sv.Fadd + G.start * M + fo[e] : zero);
+                fp[e] = (T)w;
+            }
+        }
+    }
+    if (G.hasL) {
+        double v[E], w[E];
+        ld_ent<M, E>(v, a.Lo + (G.start - 1) * MM, r, c0);   // A(g_1, sL)
+        ld_ent<M, E>(w, a.Up + (G.start - 1) * MM, r, c0);   // A(sL, g_1)
+#pragma unroll
+        for (int e = 0; e < E; ++e) { z[e] = (T)v[e]; rr[e] = (T)w[e]; }
+    }
+    unsigned long long bad = ~0ull;
+
+    // Operands of block row g that do not depend on the chain -- A(g,g+1),
+    // A(g+1,g), D[g+1] and f[g+1] at the lane's entries -- loaded one block
+    // row ahead, from the zero block when they do not exist, and kept in FP64
+    // (the two addends of a sum apart) until the row that uses them.
+    struct Next {
+        double up[E], lo[E], dn[E], da[E], fn[E], fa[E];
+    };
+    auto load_next = [&](int64_t g, bool ok, Next &n) {
+        ld_ent<M, E>(n.up, ok ? a.Up + g * MM : zero, r, c0);
+        ld_ent<M, E>(n.lo, ok ? a.Lo + g * MM : zero, r, c0);
+        ld_ent<M, E>(n.dn, ok ? a.D + (g + 1) * MM : zero, r, c0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            n.da[e] = 0.0;
+            n.fn[e] = 0.0;
+            n.fa[e] = 0.0;
+        }
+        if constexpr (ADD) ld_ent<M, E>(n.da, ok ? a.Dadd + (g + 1) * MM : zero, r, c0);
+        if constexpr (RHS) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                n.fn[e] = *((ok && act[e]) ? sv.F + (g + 1) * M + fo[e] : zero);
+                if constexpr (ADD) n.fa[e] = *((ok && act[e]) ? sv.Fadd + (g + 1) * M + fo[e] : zero);
+            }
+        }
+    };
+    Next cur;
+    load_next(G.start, G.len > 0 && G.start + 1 < nb, cur);
+
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        Next nxt;
+        load_next(g + 1, k + 1 < G.len && g + 2 < nb, nxt);
+
+        T b[E];
+        int sigma = 0, pc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) { b[e] = d[e]; pc[e] = 0; }
+        bool sing = false;
+        seg_invert<M, E, T>(b, r, c0, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, g);
+        bad = (sing && code < bad) ? code : bad;
+
+        T lo[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            S0[sigma * RS + pc[e]] = b[e];           // E_k by (logical) rows
+            S1[(c0 + e) * RS + r] = z[e];            // Z'_k by columns
+            S5[(c0 + e) * RS + r] = (T)cur.up[e];    // A(g,g+1) by columns
+            if constexpr (RHS) S4[(c0 + e) * RS + r] = fp[e];   // f'_k by columns
+            lo[e] = (T)cur.lo[e];
+        }
+        lds_put<E, T>(S2 + r * RS + c0, lo);         // A(g+1,g) by rows
+        wave_sync();
+        T er[M];
+        lds_row<M, T>(er, S0 + r * RS);
+        T x[E], zh[E], tk[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            T col[M];
+            lds_row<M, T>(col, S5 + (c0 + e) * RS);
+            x[e] = dot<M, T>(er, col);               // X_k = E_k A(g,g+1)
+            lds_row<M, T>(col, S1 + (c0 + e) * RS);
+            zh[e] = dot<M, T>(er, col);              // Zh_k = E_k Z'_k
+            tk[e] = T(0);
+            if constexpr (RHS) {
+                lds_row<M, T>(col, S4 + (c0 + e) * RS);
+                tk[e] = dot<M, T>(er, col);          // t_k = E_k f'_k
+                *(act[e] ? sv.Y + g * M + yo[e] : ydump + e) = (double)tk[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) Ef[g * MM + sigma * M + pc[e]] = b[e];
+        st_fac<E, T>(G.hasL ? R + g * MM + r * M + c0 : dump, rr);
+        st_fac<E, T>(Xs + g * MM + r * M + c0, x);
+        st_fac<E, T>(Zs + g * MM + r * M + c0, zh);
+        wave_sync();
+        lds_put<E, T>(S0 + r * RS + c0, rr);          // R_k by rows
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            S1[(c0 + e) * RS + r] = x[e];            // X_k by columns
+            S3[(c0 + e) * RS + r] = zh[e];           // Zh_k by columns
+            if constexpr (RHS) S4[(c0 + e) * RS + r] = tk[e];   // t_k by columns
+        }
+        wave_sync();
+        T rw[M], lr[M];
+        lds_row<M, T>(rw, S0 + r * RS);
+        lds_row<M, T>(lr, S2 + r * RS);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            T xc[M], hc[M];
+            lds_row<M, T>(xc, S1 + (c0 + e) * RS);
+            lds_row<M, T>(hc, S3 + (c0 + e) * RS);
+            a1[e] -= dot<M, T>(rw, hc);                                         // alpha_1
+            rr[e] = -dot<M, T>(rw, xc);                                         // R_{k+1}
+            d[e] = (T)(ADD ? cur.dn[e] + cur.da[e] : cur.dn[e]) - dot<M, T>(lr, xc);   // D'_{k+1}
+            z[e] = -dot<M, T>(lr, hc);                                          // Z'_{k+1}
+            if constexpr (RHS) {
+                T tc[M];
+                lds_row<M, T>(tc, S4 + (c0 + e) * RS);
+                gl[e] -= dot<M, T>(rw, tc);                                     // g_sL -= R_k t_k
+                fp[e] = (T)(ADD ? cur.fn[e] + cur.fa[e] : cur.fn[e]) - dot<M, T>(lr, tc);
+            }
+        }
+        cur = nxt;
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int cm = r + (c0 + e) * M;
+        if (G.hasR) {
+            a.nD[part * MM + cm] = (double)d[e];                       // D[sR] + alpha_2
+            if (G.hasL) a.nLo[(part - 1) * MM + cm] = (double)z[e];    // beta
+        }
+        if (G.hasL) {
+            a.nDadd[(part - 1) * MM + cm] = (double)a1[e];             // alpha_1
+            if (G.hasR) a.nUp[(part - 1) * MM + cm] = (double)rr[e];   // gamma
+        }
+        if constexpr (RHS) {
+            if (act[e]) {
+                const int64_t no = (int64_t)r + (int64_t)(c0 + e) * sv.ldn;
+                if (G.hasR) sv.nF[part * M + no] = (double)fp[e];           // f[sR] - A(sR,g_n) t_n
+                if (G.hasL) sv.nFadd[(part - 1) * M + no] = (double)gl[e];  // - sum R_k t_k
+            }
+        }
+    }
+}
+
+// Bidiagonal-plus-corner factor, segment mapping (D' = D: the inversion of
+// a block row does not wait for the chain).
+template <int M, int E, typename T, bool RHS>
+__device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArgs &sv,
+                                              int64_t pblock)
+{
+    constexpr int LP = seg_lanes<M, E>(), PPW = WG / LP;
+    constexpr size_t MM = (size_t)M * M;
+    const int tid = threadIdx.x, grp = tid / LP, t = tid % LP;
+    const int r = t % M, c0 = (t / M) * E;
+    constexpr int RS = M + kPad<T>;
+    constexpr int NS = RHS ? 5 : 4;
+    constexpr int GS = group_stride<T>(NS * M * RS);
+    __shared__ __align__(16) T lds[PPW * GS];
+    T *S0 = lds + grp * GS;   // tableau; then E by rows
+    T *S1 = S0 + M * RS;      // Z' by columns
+    T *S2 = S1 + M * RS;      // A(g+1,g) by rows
+    T *S3 = S2 + M * RS;      // Zh by columns
+    T *S4 = S3 + M * RS;      // (RHS) f' by columns; then t by columns
+
+    const int64_t part = pblock * PPW + grp;
+    const Geo G = geometry<1>(a.nb, a.p, part);
+    T *Ef = (T *)a.E, *Zs = (T *)a.Z;
+    double *ydump = (double *)a.dump + 2048 + tid * E;
+    const double *zero = a.zero;
+    bool act[E];
+    int64_t fo[E], yo[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        act[e] = RHS && (c0 + e < sv.nrhs);
+        fo[e] = (int64_t)r + (int64_t)(act[e] ? c0 + e : 0) * sv.ldf;
+        yo[e] = (int64_t)r + (int64_t)(act[e] ? c0 + e : 0) * sv.ldy;
+    }
+
+    T z[E], fp[E];
+    {
+        double v[E];
+        ld_ent<M, E>(v, G.valid ? a.Lo + (G.start - 1) * MM : zero, r, c0);   // A(g_1, sL)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            z[e] = (T)v[e];
+            fp[e] = (RHS && G.valid && act[e]) ? (T)sv.F[G.start * M + fo[e]] : T(0);
+        }
+    }
+    unsigned long long bad = ~0ull;
+    // D[g], A(g+1,g) and f[g+1] at the lane's entries, one block row ahead
+    struct Next {
+        double dc[E], lc[E], fc[E];
+    };
+    auto load_next = [&](int64_t g, bool ok, Next &n) {
+        ld_ent<M, E>(n.dc, ok ? a.D + g * MM : zero, r, c0);
+        ld_ent<M, E>(n.lc, ok ? a.Lo + g * MM : zero, r, c0);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            n.fc[e] = RHS ? *((ok && act[e]) ? sv.F + (g + 1) * M + fo[e] : zero) : 0.0;
+    };
+    Next cur;
+    load_next(G.start, G.len > 0, cur);
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        Next nxt;
+        load_next(g + 1, k + 1 < G.len, nxt);
+
+        T b[E], lo[E];
+        int sigma = 0, pc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) { b[e] = (T)cur.dc[e]; lo[e] = (T)cur.lc[e]; pc[e] = 0; }
+        bool sing = false;
+        seg_invert<M, E, T>(b, r, c0, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, g);
+        bad = (sing && code < bad) ? code : bad;
+
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            S0[sigma * RS + pc[e]] = b[e];
+            S1[(c0 + e) * RS + r] = z[e];
+            if constexpr (RHS) S4[(c0 + e) * RS + r] = fp[e];
+        }
+        lds_put<E, T>(S2 + r * RS + c0, lo);
+        wave_sync();
+        T er[M];
+        lds_row<M, T>(er, S0 + r * RS);
+        T zh[E], tk[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            T col[M];
+            lds_row<M, T>(col, S1 + (c0 + e) * RS);
+            zh[e] = dot<M, T>(er, col);
+            tk[e] = T(0);
+            if constexpr (RHS) {
+                lds_row<M, T>(col, S4 + (c0 + e) * RS);
+                tk[e] = dot<M, T>(er, col);
+                *(act[e] ? sv.Y + g * M + yo[e] : ydump + e) = (double)tk[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) Ef[g * MM + sigma * M + pc[e]] = b[e];
+        st_fac<E, T>(Zs + g * MM + r * M + c0, zh);
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            S3[(c0 + e) * RS + r] = zh[e];
+            if constexpr (RHS) S4[(c0 + e) * RS + r] = tk[e];
+        }
+        wave_sync();
+        T lr[M];
+        lds_row<M, T>(lr, S2 + r * RS);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            T hc[M];
+            lds_row<M, T>(hc, S3 + (c0 + e) * RS);
+            z[e] = -dot<M, T>(lr, hc);
+            if constexpr (RHS) {
+                T tc[M];
+                lds_row<M, T>(tc, S4 + (c0 + e) * RS);
+                fp[e] = (T)cur.fc[e] - dot<M, T>(lr, tc);
+            }
+        }
+        cur = nxt;
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+    if (G.valid) {
+        const int64_t sR = G.start + G.len;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int cm = r + (c0 + e) * M;
+            a.nLo[part * MM + cm] = (double)z[e];                      // beta
+            a.nD[(part + 1) * MM + cm] = a.D[sR * MM + cm];
+            if (part == 0) {
+                a.nD[cm] = a.D[cm];
+                a.nC[cm] = a.C[cm];
+            }
+            if constexpr (RHS) {
+                if (act[e]) {
+                    const int64_t no = (int64_t)r + (int64_t)(c0 + e) * sv.ldn;
+                    sv.nF[(part + 1) * M + no] = (double)fp[e];
+                    if (part == 0) sv.nF[no] = sv.F[fo[e]];
+                }
+            }
+        }
+    }
+}
+
+// ---- kernels ----------------------------------------------------------------
+template <int M, int E, typename T, bool ADD, bool RHS>
+__global__ __launch_bounds__(WG) void k_btri_seg(LevelArgs a, SolveArgs sv)
+{
+    btri_seg_body<M, E, T, ADD, RHS>(a, sv, blockIdx.x);
+}
+template <int M, int E, typename T, bool RHS>
+__global__ __launch_bounds__(WG) void k_babd_seg(LevelArgs a, SolveArgs sv)
+{
+    babd_seg_body<M, E, T, RHS>(a, sv, blockIdx.x);
+}
+// batched (factor only): workgroup w serves table entry work[w].x, partition
+// block work[w].y
+template <int M, int E, typename T, bool ADD>
+__global__ __launch_bounds__(WG) void kb_btri_seg(const LevelArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    btri_seg_body<M, E, T, ADD, false>(a, SolveArgs{}, w.y);
+}
+template <int M, int E, typename T>
+__global__ __launch_bounds__(WG) void kb_babd_seg(const LevelArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    babd_seg_body<M, E, T, false>(a, SolveArgs{}, w.y);
+}
+
+// the (M, E) pairs with kernels
+template <typename F>
+hipError_t dispatch_ME(int M, int E, F &&f)
+{
+    using std::integral_constant;
+    if (M == 1 && E == 1) return f(integral_constant<int, 1>{}, integral_constant<int, 1>{});
+    if (M == 2 && E == 1) return f(integral_constant<int, 2>{}, integral_constant<int, 1>{});
+    if (M == 4 && E == 1) return f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
+    if (M == 8 && E == 1) return f(integral_constant<int, 8>{}, integral_constant<int, 1>{});
+    if (M == 8 && E == 2) return f(integral_constant<int, 8>{}, integral_constant<int, 2>{});
+    if (M == 16 && E == 4) return f(integral_constant<int, 16>{}, integral_constant<int, 4>{});
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool seg_ok(int M, int E)
+{
+    return (M == 1 && E == 1) || (M == 2 && E == 1) || (M == 4 && E == 1) || (M == 8 && E == 1) ||
+           (M == 8 && E == 2) || (M == 16 && E == 4);
+}
+
+int seg_partitions_per_wg(int M, int E) { return WG / (M * M / E); }
+
+hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &a,
+                             const SolveArgs *sv, hipStream_t s)
+{
+    if (sv && (sv->nrhs < 1 || sv->nrhs > M)) return hipErrorInvalidValue;
+    return dispatch_ME(M, E, [&](auto mc, auto ec) {
+        constexpr int MV = decltype(mc)::value, EV = decltype(ec)::value;
+        const int ppw = seg_partitions_per_wg(MV, EV);
+        const dim3 grid((unsigned)((a.p + ppw - 1) / ppw));
+        const SolveArgs none{};
+        const SolveArgs &v = sv ? *sv : none;
+        if (kind == 1) {
+            if (sv) {
+                if (f32) hipLaunchKernelGGL((k_babd_seg<MV, EV, float, true>), grid, dim3(WG), 0, s, a, v);
+                else hipLaunchKernelGGL((k_babd_seg<MV, EV, double, true>), grid, dim3(WG), 0, s, a, v);
+            } else {
+                if (f32) hipLaunchKernelGGL((k_babd_seg<MV, EV, float, false>), grid, dim3(WG), 0, s, a, v);
+                else hipLaunchKernelGGL((k_babd_seg<MV, EV, double, false>), grid, dim3(WG), 0, s, a, v);
+            }
+        } else if (a.Dadd) {
+            if (sv) {
+                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, true, true>), grid, dim3(WG), 0, s, a, v);
+                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, true, true>), grid, dim3(WG), 0, s, a, v);
+            } else {
+                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, true, false>), grid, dim3(WG), 0, s, a, v);
+                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, true, false>), grid, dim3(WG), 0, s, a, v);
+            }
+        } else {
+            if (sv) {
+                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, false, true>), grid, dim3(WG), 0, s, a, v);
+                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, false, true>), grid, dim3(WG), 0, s, a, v);
+            } else {
+                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, false, false>), grid, dim3(WG), 0, s, a, v);
+                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, false, false>), grid, dim3(WG), 0, s, a, v);
+            }
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_seg_factor_batch(int kind, int M, int E, bool f32, bool add, const LevelArgs *tab,
+                                   const int4 *work, int nwg, hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    return dispatch_ME(M, E, [&](auto mc, auto ec) {
+        constexpr int MV = decltype(mc)::value, EV = decltype(ec)::value;
+        const dim3 grid(nwg);
+        if (kind == 1) {
+            if (f32) hipLaunchKernelGGL((kb_babd_seg<MV, EV, float>), grid, dim3(WG), 0, s, tab, work);
+            else hipLaunchKernelGGL((kb_babd_seg<MV, EV, double>), grid, dim3(WG), 0, s, tab, work);
+        } else if (add) {
+            if (f32) hipLaunchKernelGGL((kb_btri_seg<MV, EV, float, true>), grid, dim3(WG), 0, s, tab, work);
+            else hipLaunchKernelGGL((kb_btri_seg<MV, EV, double, true>), grid, dim3(WG), 0, s, tab, work);
+        } else {
+            if (f32) hipLaunchKernelGGL((kb_btri_seg<MV, EV, float, false>), grid, dim3(WG), 0, s, tab, work);
+            else hipLaunchKernelGGL((kb_btri_seg<MV, EV, double, false>), grid, dim3(WG), 0, s, tab, work);
+        }
+        return hipGetLastError();
+    });
+}
+
+}  // namespace pf

@@ -59,33 +59,38 @@ struct SolveArgs {
     const double *zero;    // kZeroBytes of zeros
 };
 
-// Launchers (kernels.hip).  M must be 1, 2, 4, 8, 16 or 32.  The factor
-// kernels come in two lane mappings: rows (a group of M lanes per partition,
-// lane i holding row i of each block) and tiles (M*M lanes per partition,
-// one block entry per lane; M = 2, 4, 8 only), see tile_mapping_ok.
-bool tile_mapping_ok(int M);
-int partitions_per_wg(int M, bool tile);
-hipError_t launch_btri_factor(int M, bool f32, bool tile, const LevelArgs &a, hipStream_t s);
+// Factor launchers, two lane mappings.
+// Rows (kernels_rows.hip, M = 1..32): a group of M lanes per partition, lane
+// i holding row i of each block.
+hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s);
+hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s);
+// Segments (kernels_seg.hip): M*M/E lanes per partition, E consecutive
+// entries of a block row per lane, for the (M, E) pairs seg_ok accepts.
+// With sv != NULL (1 <= sv->nrhs <= M) the launch also runs the forward
+// sweep of launch_*_fwd for those right-hand sides (factor-and-solve).
+bool seg_ok(int M, int E);
+int seg_partitions_per_wg(int M, int E);
+hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &a,
+                             const SolveArgs *sv, hipStream_t s);
+// Solve launchers (kernels_solve.hip, M = 1..32).
 hipError_t launch_btri_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_btri_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
-hipError_t launch_babd_factor(int M, bool f32, bool tile, const LevelArgs &a, hipStream_t s);
-// Factor-and-solve of one level (tile mapping only, 1 <= sv.nrhs <= M): the
-// factor of launch_*_factor plus the forward sweep of launch_*_fwd in one pass.
-hipError_t launch_factor_solve(int kind, int M, bool f32, const LevelArgs &a, const SolveArgs &sv,
-                               hipStream_t s);
 hipError_t launch_babd_fwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 hipError_t launch_babd_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 
 // Batched launches: one launch serves every entry of a device table; work[w]
 // = (table entry, partition block, right-hand-side block, unused) for
-// workgroup w.  A partition block is groups_per_wg(M) partitions; a
-// right-hand-side block is rhs_chunk(nrhs) columns; a factor work item covers
-// partitions_per_wg(M, tile) partitions.  Entries of one launch
-// share kind, M, precision, the ADD variant and (solves) the chunk size.
+// workgroup w.  A solve partition block is groups_per_wg(M) partitions, a
+// right-hand-side block rhs_chunk(nrhs) columns; a factor work item covers
+// groups_per_wg(M) (rows) or seg_partitions_per_wg(M, E) (segments)
+// partitions.  Entries of one launch share kind, M, the mapping, precision,
+// the ADD variant and (solves) the chunk size.
 int groups_per_wg(int M);
 int rhs_chunk(int nrhs);
-hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, bool tile, const LevelArgs *tab,
+hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, const LevelArgs *tab,
                                const int4 *work, int nwg, hipStream_t s);
+hipError_t launch_seg_factor_batch(int kind, int M, int E, bool f32, bool add, const LevelArgs *tab,
+                                   const int4 *work, int nwg, hipStream_t s);
 hipError_t launch_solve_batch(int kind, bool fwd, int M, bool f32, bool add, int KC,
                               const SolveArgs *tab, const int4 *work, int nwg, hipStream_t s);
 

@@ -38,7 +38,7 @@ class pf_opts(ctypes.Structure):
     _fields_ = [("partitions", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("coarse_rows", ctypes.c_int32),
-                ("tol", ctypes.c_double)]
+                ("lane_entries", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class pf_info(ctypes.Structure):
@@ -129,8 +129,9 @@ def make_matrix(kind, m, nb, D, Lo, Up=None, C=None) -> pf_matrix:
 
 
 def make_opts(partitions=0, prec=PF_FP64, max_refine=0, block_rows=0, flags=0, tol=0.0,
-              coarse_rows=0):
-    return pf_opts(partitions, prec, max_refine, block_rows, flags, coarse_rows, tol)
+              coarse_rows=0, lane_entries=0):
+    return pf_opts(partitions, prec, max_refine, block_rows, flags, coarse_rows, lane_entries,
+                   tol)
 
 
 def pf_factor(A: pf_matrix, opts: pf_opts | None = None, stream=None):

@@ -65,17 +65,27 @@ def test_block_size_32(kind, nb):
     G.check(s, x, tag=f"{kind} m=32 nb={nb} levels={levels}")
 
 
-@pytest.mark.parametrize("flag", ["rows", "tiles"])
+@pytest.mark.parametrize("flag", ["rows", "seg", "wide"])
 @pytest.mark.parametrize("kind,m,nb", [("btri", 2, 301), ("btri", 4, 1001), ("btri", 8, 4099),
                                        ("btri", 3, 77), ("btri", 8, 7), ("babd", 2, 40),
-                                       ("babd", 4, 300), ("babd", 8, 1001), ("babd", 6, 31)])
+                                       ("babd", 4, 300), ("babd", 8, 1001), ("babd", 6, 31),
+                                       ("btri", 16, 600), ("babd", 16, 300), ("btri", 12, 50),
+                                       ("btri", 1, 999)])
 def test_lane_mappings(kind, m, nb, flag):
-    """Both factor lane mappings on every level give the oracle's solution."""
+    """Every factor lane mapping gives the oracle's solution: rows on every
+    level, the default segments, and wider segments at level 0 (m = 8: two
+    entries per lane)."""
     seed = 500 + m * 13 + nb
     s = wl.random_btri(nb, m, seed=seed) if kind == "btri" else wl.random_babd(nb, m, seed=seed)
-    f = pf.PF_FLAG_MAP_ROWS if flag == "rows" else pf.PF_FLAG_MAP_TILES
+    M = 1 << (m - 1).bit_length()
+    if flag == "rows":
+        opts = pf.make_opts(flags=pf.PF_FLAG_MAP_ROWS)
+    elif flag == "wide":
+        opts = pf.make_opts(lane_entries={8: 2, 16: 4}.get(M, 1))
+    else:
+        opts = pf.make_opts()
     _say(kind, "m", m, "nb", nb, flag)
-    x, info, levels = G.gpu_solve(s, pf.make_opts(flags=f))
+    x, info, levels = G.gpu_solve(s, opts)
     assert info.status == 0
     G.check(s, x, tag=f"{kind} m={m} nb={nb} {flag} levels={levels}")
 
@@ -216,7 +226,7 @@ def test_fp32_ir_btri():
 
 # --------------------------------------------------------------------------
 # error path: an exactly singular pivot block
-@pytest.mark.parametrize("flags", [0, pf.PF_FLAG_MAP_TILES])
+@pytest.mark.parametrize("flags", [0, pf.PF_FLAG_MAP_ROWS])
 def test_singular_pivot_reported(flags):
     s = wl.random_btri(64, 4, seed=5)
     s.D[0] = 0.0
