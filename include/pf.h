@@ -76,7 +76,12 @@ enum {
                               finest level for m = 8), 4 for m = 16; m = 32 always
                               uses rows).  The mappings differ
                               only in rounding.                                      */
-    PF_FLAG_MAP_TILES = 4  /* reserved (the segment mapping is the default)         */
+    PF_FLAG_MAP_TILES = 4, /* reserved (the segment mapping is the default)         */
+    PF_FLAG_AUTOTUNE = 8   /* pf_factor / pf_batch_create take block_rows,
+                              coarse_rows, lane_entries and the mapping from the
+                              autotuner's cache for the system's shape class,
+                              tuning on this matrix first when the class is new
+                              (see pf_autotune)                                      */
 };
 
 typedef struct {
@@ -161,6 +166,22 @@ int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *
  * refactors.  Arguments, errors and synchronization as for pf_solve. */
 int pf_factor_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
                     int64_t ldx, void *stream, pf_info *info);
+
+/* Autotuner: time pf_factor_solve of A (nrhs right-hand sides, f = 1) on
+ * `stream` for candidate launch shapes -- finest-level chain length
+ * (block_rows 4..32), its lane mapping (every segment width with a kernel
+ * for the block size, and rows) and the reduced levels' chain length
+ * (coarse_rows 2..6) -- and return the fastest as *best (with its median
+ * time in *best_ms, may be NULL).  Precision, tolerance and the other
+ * fields come from *base (may be NULL).  The choice is also cached for the
+ * system's shape class (kind, block size, precision, nb to half an octave,
+ * right-hand-side bucket), where PF_FLAG_AUTOTUNE finds it.  Allocates and
+ * frees its own scratch; synchronizes `stream`.  Returns 0, -k for invalid
+ * argument k, PF_ENOMEM or PF_EHIP. */
+int pf_autotune(const pf_matrix *A, const pf_opts *base, int32_t nrhs, void *stream,
+                pf_opts *best, float *best_ms);
+/* Forget every cached autotuner choice. */
+void pf_autotune_clear(void);
 
 /* ---- batches of independent systems ---------------------------------------
  * The partitions of many systems run side by side: every system's
@@ -264,6 +285,60 @@ int pf_band_to_btri(int64_t n, int32_t kl, int32_t ku, const double *ab, int64_t
 int pf_abd_to_btri(int32_t m, int64_t N, int32_t qa, const double *Ba, const double *S,
                    const double *R, const double *Bb, double *D, double *Lo, double *Up,
                    void *stream);
+
+/* ---- serving: continuous batching under a device-memory budget ----------
+ * A request factors A and solves for f (or solves with a factor kept from an
+ * earlier request) into x.  Requests are admitted in arrival order as memory
+ * (the budget, counted with pf_factor_bytes / pf_solve_bytes_per_rhs) and
+ * in-flight slots free up -- a request that does not fit waits while later
+ * ones that fit go ahead -- and run concurrently on the server's streams;
+ * least recently used kept factors that no pending request needs are
+ * evicted to make room.  Scheduling happens inside submit / poll / wait /
+ * stats; only pf_server_wait blocks.  FP64 only (the refinement loop of
+ * PF_FP32_IR synchronizes).  Not thread-safe: one host thread drives a
+ * server. */
+typedef struct pf_server_s *pf_server_t;
+
+typedef struct {
+    pf_matrix A;        /* device arrays, valid until the request completes (and while
+                           a kept factor may be used: the refinement-free solve does
+                           not read A, but a factor kept with keep = 1 points to it) */
+    int32_t nrhs;       /* >= 1                                                */
+    int32_t keep;       /* 1: keep the factor resident for later requests     */
+    const double *f;    /* device, n x nrhs, ld ldf                            */
+    int64_t ldf;
+    double *x;          /* device, n x nrhs, ld ldx                            */
+    int64_t ldx;
+    int64_t factor;     /* -1: factor A; else the ticket of a request with keep = 1
+                           whose factor solves this one (same A)               */
+} pf_request;
+
+typedef struct {
+    size_t budget, used;          /* bytes                                     */
+    int64_t queued, inflight, resident, completed, evictions;
+} pf_server_info;
+
+/* budget_bytes: device memory the server may hold; max_inflight: running
+ * requests at once (0 = 8); nstreams: concurrent streams (0 = 4, default
+ * priority).  opts: as for pf_factor (prec must be PF_FP64). */
+int pf_server_create(size_t budget_bytes, const pf_opts *opts, int32_t max_inflight,
+                     int32_t nstreams, pf_server_t *out);
+/* Queue a request; returns its ticket.  PF_ENOMEM if it can never fit. */
+int pf_server_submit(pf_server_t S, const pf_request *req, int64_t *ticket);
+/* 1 and the request's status in *info when it is done, else 0. */
+int pf_server_poll(pf_server_t S, int64_t ticket, pf_info *info);
+/* Block until the request is done; returns its status. */
+int pf_server_wait(pf_server_t S, int64_t ticket, pf_info *info);
+/* Submission (host clock), start and completion (device events) times of a
+ * request in ms since the server's creation; -1 while unknown.  Returns 1
+ * when the request is done. */
+int pf_server_times(pf_server_t S, int64_t ticket, double *submit_ms, double *start_ms,
+                    double *done_ms);
+/* Drop a kept factor (after the requests queued on it). */
+int pf_server_release(pf_server_t S, int64_t factor);
+int pf_server_stats(pf_server_t S, pf_server_info *st);
+/* Wait for all work and free everything. */
+void pf_server_destroy(pf_server_t S);
 
 #ifdef __cplusplus
 }

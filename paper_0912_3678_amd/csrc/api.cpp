@@ -728,9 +728,14 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
     *out = nullptr;
     int rc = check_matrix(A);
     if (rc) return rc;
-    const pf_opts o = resolve_opts(opts);
+    pf_opts o = resolve_opts(opts);
     if ((rc = check_opts(A, o))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if (o.flags & PF_FLAG_AUTOTUNE) {
+        pf_opts t{};
+        if ((rc = tuned_opts(A, o, 1, s, &t))) return rc;
+        o = resolve_opts(&t);
+    }
     pf_factor_s *F = nullptr;
     if ((rc = factor_setup(A, o, s, nullptr, nullptr, &F))) return rc;
     hipError_t e = launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s);
@@ -890,6 +895,20 @@ void pf_destroy(pf_factor_t F)
     free_list(F, F->ws_allocs);
     free_list(F, F->allocs);
     hipStreamSynchronize(F->stream);
+    pf::destroy_async(F);
+}
+
+}  // extern "C"
+
+namespace pf {
+
+// Release a handle whose device work is known to be complete, or whose frees
+// may stay queued on its stream (stream-ordered, no host synchronization).
+void destroy_async(pf_factor_s *F)
+{
+    if (!F) return;
+    free_list(F, F->ws_allocs);
+    free_list(F, F->allocs);
     for (auto *list : {&F->prof_fac, &F->prof_sol})
         for (auto &sl : *list) {
             if (sl.a) hipEventDestroy(sl.a);
@@ -898,6 +917,52 @@ void pf_destroy(pf_factor_t F)
     if (F->arena) arena_release(F->arena, F->stream);
     delete F;
 }
+
+// A new handle for A, factored and its right-hand sides solved on stream s
+// in one pass per level where possible; nothing waits on the host.
+int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int nrhs,
+                     const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out)
+{
+    *out = nullptr;
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    const pf_opts o = resolve_opts(opts);
+    if ((rc = check_opts(A, o))) return rc;
+    pf_factor_s *F = nullptr;
+    if ((rc = factor_setup(A, o, s, nullptr, nullptr, &F))) return rc;
+    if ((rc = ensure_workspace(F, std::max(nrhs, 1)))) {
+        destroy_async(F);
+        return rc;
+    }
+    if (launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s) != hipSuccess) {
+        destroy_async(F);
+        return PF_EHIP;
+    }
+    if (nrhs > 0 && fused_ok(F, nrhs)) rc = run_factor_solve(F, nrhs, f, ldf, x, ldx, s);
+    else {
+        rc = launch_factor_levels(F, s) == hipSuccess ? 0 : PF_EHIP;
+        if (!rc && nrhs > 0) rc = run_solve(F, nrhs, f, ldf, x, ldx, s);
+    }
+    if (rc) {
+        destroy_async(F);
+        return rc;
+    }
+    *out = F;
+    return 0;
+}
+
+// Device status word of a handle whose work has completed (no stream wait).
+int status_nosync(pf_factor_s *F, pf_info *info)
+{
+    std::memset(info, 0, sizeof *info);
+    info->eta = -1.0;
+    read_status(F, info);
+    return info->status;
+}
+
+}  // namespace pf
+
+extern "C" {
 
 int pf_plan(const pf_matrix *A, const pf_opts *opts, int32_t max_levels, int32_t *kinds,
             int64_t *nbs, int64_t *ps)
@@ -1297,6 +1362,15 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
         if (nrhs[i] < 0 || (nrhs[i] > 0 && (!f[i] || !x[i])) || ldf[i] < n || ldx[i] < n) return -4;
     }
     hipStream_t us = (hipStream_t)stream;
+    // per-system launch shapes (the autotuner's, when asked for)
+    std::vector<pf_opts> os(nsys, o);
+    if (o.flags & PF_FLAG_AUTOTUNE)
+        for (int i = 0; i < nsys; ++i) {
+            pf_opts t{};
+            const int rc = tuned_opts(&A[i], o, std::max(nrhs[i], 1), us, &t);
+            if (rc) return rc;
+            os[i] = resolve_opts(&t);
+        }
     pf_batch_s *B = new pf_batch_s();
     B->nsys = nsys;
     B->opts = o;
@@ -1322,7 +1396,7 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
     void *fake = (void *)(uintptr_t)4096;
     for (int i = 0; i < nsys; ++i) {
         pf_factor_s *F = nullptr;
-        if (factor_setup(&A[i], o, us, &count, fake, &F)) return fail(PF_ENOMEM);
+        if (factor_setup(&A[i], os[i], us, &count, fake, &F)) return fail(PF_ENOMEM);
         ensure_workspace(F, std::max(nrhs[i], 1));
         delete F;
     }
@@ -1339,7 +1413,7 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
     B->F.assign(nsys, nullptr);
     for (int i = 0; i < nsys; ++i) {
         pf_factor_s *F = nullptr;
-        if (factor_setup(&A[i], o, us, B->arena, scratch, &F)) return fail(PF_ENOMEM);
+        if (factor_setup(&A[i], os[i], us, B->arena, scratch, &F)) return fail(PF_ENOMEM);
         ++ar.refs;
         B->F[i] = F;
         if (ensure_workspace(F, std::max(nrhs[i], 1))) return fail(PF_ENOMEM);

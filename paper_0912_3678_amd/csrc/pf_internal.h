@@ -1,7 +1,11 @@
 // Internal interface between the host planner (api.cpp) and the HIP kernels.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "pf.h"
 #include <stdint.h>
+
+struct pf_factor_s;
 
 namespace pf {
 
@@ -124,5 +128,17 @@ hipError_t launch_band_to_btri(int64_t n, int kl, int ku, const double *ab, int6
 hipError_t launch_abd_to_btri(int m, int64_t N, int qa, const double *Ba, const double *S,
                               const double *R, const double *Bb, double *D, double *Lo,
                               double *Up, hipStream_t s);
+
+// Handle helpers for the request scheduler (api.cpp): factor a new handle
+// and solve in one go on a stream, release without a host wait, and read the
+// status word of a handle whose work is complete.
+int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int nrhs,
+                     const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out);
+void destroy_async(pf_factor_s *F);
+int status_nosync(pf_factor_s *F, pf_info *info);
+
+// Options of a PF_FLAG_AUTOTUNE factorization (tune.cpp): the cached choice
+// for A's shape class, tuning on A first when there is none.
+int tuned_opts(const pf_matrix *A, const pf_opts &o, int nrhs, hipStream_t s, pf_opts *out);
 
 }  // namespace pf

@@ -1,0 +1,431 @@
+// Request scheduler for serving: continuous batching of factor-and-solve
+// requests of uneven size under a device-memory budget, with a cache of
+// resident factors for requests that bring a new right-hand side for a
+// matrix already factored.
+//
+// Admission is continuous: at every submit / poll / wait the scheduler
+// retires the requests whose completion event has fired (their memory goes
+// back to the budget unless the factor is kept), then admits waiting
+// requests in arrival order while the budget and the in-flight limit allow,
+// evicting least recently used resident factors that no queued or running
+// request needs.  Admitted requests run on a small set of streams, so the
+// work of requests that arrived while others were running overlaps on the
+// device.  All requests on one resident factor run on that factor's stream
+// (they share its workspace).  Nothing here waits on the host for device
+// work except pf_server_wait.
+#include "pf.h"
+#include "pf_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <vector>
+
+using namespace pf;
+
+namespace {
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Ticket {
+    pf_request req{};
+    size_t bytes = 0;          // budget charged while running
+    int stream = -1;
+    int state = 0;             // 0 queued, 1 running, 2 done
+    pf_info info{};
+    double t_submit = 0, t_start = -1, t_done = -1;   // ms, server clock
+    hipEvent_t ev_start = nullptr, ev_done = nullptr;
+    pf_factor_t F = nullptr;   // the factor this request ran on
+};
+
+struct Resident {
+    pf_factor_t F = nullptr;   // null until the request that factors it starts
+    size_t bytes = 0;
+    int stream = 0;
+    int users = 0;             // queued or running requests on it (its own included)
+    double last_use = 0;
+    bool released = false;
+    int failed = 0;            // status of a factoring request that could not start
+};
+
+}  // namespace
+
+struct pf_server_s {
+    size_t budget = 0, used = 0;
+    pf_opts opts{};
+    int max_inflight = 8;
+    std::vector<hipStream_t> streams;
+    std::vector<int> load;                 // running requests per stream
+    hipEvent_t epoch = nullptr;
+    double epoch_ms = 0;
+    int64_t next = 0;
+    std::map<int64_t, Ticket> tickets;
+    std::deque<int64_t> queue;
+    int inflight = 0;
+    std::map<int64_t, Resident> resident;  // keyed by the ticket that factored it
+    int64_t evictions = 0, completed = 0;
+};
+
+namespace {
+
+size_t request_bytes(const pf_server_s *S, const pf_request &r)
+{
+    const size_t per = pf_solve_bytes_per_rhs(&r.A, &S->opts);
+    if (r.factor >= 0) return per * (size_t)std::max(r.nrhs, 1);
+    return pf_factor_bytes(&r.A, &S->opts) + per * (size_t)std::max(r.nrhs, 1);
+}
+
+// evict least recently used resident factors nobody needs until `need`
+// bytes fit
+bool make_room(pf_server_s *S, size_t need)
+{
+    while (S->used + need > S->budget) {
+        int64_t victim = -1;
+        double oldest = 0;
+        for (auto &kv : S->resident) {
+            const Resident &R = kv.second;
+            if (R.users > 0 || !R.F) continue;
+            if (victim < 0 || R.last_use < oldest) {
+                victim = kv.first;
+                oldest = R.last_use;
+            }
+        }
+        if (victim < 0) return false;
+        Resident &R = S->resident[victim];
+        destroy_async(R.F);   // stream-ordered frees after the factor's last work
+        S->used -= R.bytes;
+        S->resident.erase(victim);
+        ++S->evictions;
+    }
+    return true;
+}
+
+void retire(pf_server_s *S)
+{
+    for (auto &kv : S->tickets) {
+        Ticket &T = kv.second;
+        if (T.state != 1) continue;
+        if (hipEventQuery(T.ev_done) != hipSuccess) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, S->epoch, T.ev_done) == hipSuccess) T.t_done = S->epoch_ms + ms;
+        if (hipEventElapsedTime(&ms, S->epoch, T.ev_start) == hipSuccess) T.t_start = S->epoch_ms + ms;
+        status_nosync(T.F, &T.info);
+        T.state = 2;
+        --S->inflight;
+        --S->load[T.stream];
+        ++S->completed;
+        S->used -= T.bytes;
+        if (T.req.factor >= 0) {
+            auto it = S->resident.find(T.req.factor);
+            if (it != S->resident.end()) {
+                --it->second.users;
+                it->second.last_use = now_ms();
+                if (it->second.released && it->second.users == 0) {
+                    if (it->second.F) destroy_async(it->second.F);
+                    S->used -= it->second.bytes;
+                    S->resident.erase(it);
+                }
+            }
+        } else if (T.req.keep) {
+            auto it = S->resident.find(kv.first);
+            if (it != S->resident.end()) {
+                --it->second.users;
+                it->second.last_use = now_ms();
+                if (it->second.released && it->second.users == 0) {
+                    destroy_async(it->second.F);
+                    S->used -= it->second.bytes;
+                    S->resident.erase(it);
+                }
+            }
+        } else {
+            destroy_async(T.F);
+        }
+        hipEventDestroy(T.ev_start);
+        hipEventDestroy(T.ev_done);
+        T.ev_start = T.ev_done = nullptr;
+    }
+}
+
+int launch(pf_server_s *S, int64_t id, Ticket &T)
+{
+    const pf_request &r = T.req;
+    if (hipEventCreateWithFlags(&T.ev_start, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&T.ev_done, 0) != hipSuccess)
+        return PF_EHIP;
+    int si;
+    if (r.factor >= 0) {
+        si = S->resident[r.factor].stream;
+    } else {
+        si = (int)(std::min_element(S->load.begin(), S->load.end()) - S->load.begin());
+    }
+    hipStream_t s = S->streams[si];
+    hipEventRecord(T.ev_start, s);
+    int rc;
+    if (r.factor >= 0) {
+        T.F = S->resident[r.factor].F;
+        rc = pf_solve(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s, nullptr);
+    } else {
+        rc = factor_new_solve(&r.A, &S->opts, s, r.nrhs, r.f, r.ldf, r.x, r.ldx, &T.F);
+    }
+    if (rc) return rc;
+    hipEventRecord(T.ev_done, s);
+    T.stream = si;
+    T.state = 1;
+    ++S->inflight;
+    ++S->load[si];
+    if (r.factor < 0 && r.keep) {
+        // the entry was registered at submission; the factor's memory stays
+        // charged after this request: move it from the request to the entry
+        Resident &R = S->resident[id];
+        R.F = T.F;
+        R.bytes = T.bytes;
+        R.stream = si;
+        R.last_use = now_ms();
+        T.bytes = 0;
+    }
+    return 0;
+}
+
+// a request that cannot run any more (its factor's request failed)
+void fail(pf_server_s *S, Ticket &T, int rc)
+{
+    T.state = 2;
+    T.info = pf_info{};
+    T.info.status = rc;
+    T.info.eta = -1.0;
+    T.info.bad_block = -1;
+    T.t_done = now_ms();
+    if (T.ev_start) hipEventDestroy(T.ev_start);
+    if (T.ev_done) hipEventDestroy(T.ev_done);
+    T.ev_start = T.ev_done = nullptr;
+    (void)S;
+}
+
+// Admit queued requests in arrival order; one that does not fit yet stays
+// queued while later ones that fit go ahead (a request for a resident factor
+// needs only solve workspace).
+void admit(pf_server_s *S)
+{
+    for (auto q = S->queue.begin(); q != S->queue.end() && S->inflight < S->max_inflight;) {
+        const int64_t id = *q;
+        Ticket &T = S->tickets[id];
+        if (T.req.factor >= 0) {
+            Resident &R = S->resident[T.req.factor];
+            if (R.failed) {                  // its factor never came to exist
+                q = S->queue.erase(q);
+                --R.users;
+                fail(S, T, R.failed);
+                continue;
+            }
+            if (!R.F) {                      // its factor's request has not started
+                ++q;
+                continue;
+            }
+        }
+        const size_t need = request_bytes(S, T.req);
+        if (!make_room(S, need)) {
+            ++q;
+            continue;
+        }
+        q = S->queue.erase(q);
+        S->used += need;
+        T.bytes = need;
+        const int rc = launch(S, id, T);
+        if (rc) {
+            S->used -= need;
+            if (T.req.factor >= 0) --S->resident[T.req.factor].users;
+            if (T.req.factor < 0 && T.req.keep) {
+                Resident &R = S->resident[id];
+                R.failed = rc;
+                --R.users;
+            }
+            fail(S, T, rc);
+        }
+    }
+}
+
+void progress(pf_server_s *S)
+{
+    retire(S);
+    admit(S);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_server_create(size_t budget_bytes, const pf_opts *opts, int32_t max_inflight,
+                     int32_t nstreams, pf_server_t *out)
+{
+    if (!out) return -5;
+    *out = nullptr;
+    if (budget_bytes == 0) return -1;
+    if (max_inflight < 0) return -3;
+    if (nstreams < 0) return -4;
+    pf_server_s *S = new pf_server_s();
+    S->budget = budget_bytes;
+    if (opts) S->opts = *opts;
+    S->opts.flags &= ~PF_FLAG_AUTOTUNE;
+    if (S->opts.prec != PF_FP64) {   // the refinement loop synchronizes: not in a server
+        delete S;
+        return -2;
+    }
+    S->max_inflight = max_inflight ? max_inflight : 8;
+    const int ns = nstreams ? nstreams : 4;
+    for (int i = 0; i < ns; ++i) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            pf_server_destroy(S);
+            return PF_EHIP;
+        }
+        S->streams.push_back(s);
+        S->load.push_back(0);
+    }
+    if (hipEventCreate(&S->epoch) != hipSuccess || hipEventRecord(S->epoch, S->streams[0]) != hipSuccess ||
+        hipEventSynchronize(S->epoch) != hipSuccess) {
+        pf_server_destroy(S);
+        return PF_EHIP;
+    }
+    S->epoch_ms = now_ms();
+    *out = S;
+    return 0;
+}
+
+int pf_server_submit(pf_server_t S, const pf_request *req, int64_t *ticket)
+{
+    if (!S) return -1;
+    if (!req) return -2;
+    if (!ticket) return -3;
+    const pf_request &r = *req;
+    if (r.nrhs < 1 || !r.f || !r.x) return -2;
+    const int64_t n = r.A.nb * r.A.m;
+    if (pf_factor_bytes(&r.A, &S->opts) == 0 || r.ldf < n || r.ldx < n) return -2;
+    if (r.factor >= 0) {
+        auto it = S->resident.find(r.factor);
+        if (it == S->resident.end() || it->second.released || it->second.failed) return -2;
+    }
+    if (request_bytes(S, r) > S->budget) return PF_ENOMEM;
+    const int64_t id = S->next++;
+    Ticket &T = S->tickets[id];
+    T.req = r;
+    T.t_submit = now_ms();
+    if (r.factor >= 0) ++S->resident[r.factor].users;
+    if (r.factor < 0 && r.keep) {      // later requests may name it at once
+        Resident R;
+        R.users = 1;
+        R.last_use = T.t_submit;
+        S->resident[id] = R;
+    }
+    S->queue.push_back(id);
+    *ticket = id;
+    progress(S);
+    return 0;
+}
+
+int pf_server_poll(pf_server_t S, int64_t ticket, pf_info *info)
+{
+    if (!S) return -1;
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) return -2;
+    progress(S);
+    if (it->second.state != 2) return 0;
+    if (info) *info = it->second.info;
+    return 1;
+}
+
+int pf_server_wait(pf_server_t S, int64_t ticket, pf_info *info)
+{
+    if (!S) return -1;
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) return -2;
+    for (;;) {
+        progress(S);
+        Ticket &T = it->second;
+        if (T.state == 2) break;
+        if (T.state == 1) {
+            if (hipEventSynchronize(T.ev_done) != hipSuccess) return PF_EHIP;
+        } else {
+            // queued: wait for the oldest running request to make room
+            hipEvent_t ev = nullptr;
+            for (auto &kv : S->tickets)
+                if (kv.second.state == 1) { ev = kv.second.ev_done; break; }
+            if (!ev) return PF_ENOMEM;    // nothing running and still not admitted
+            if (hipEventSynchronize(ev) != hipSuccess) return PF_EHIP;
+        }
+    }
+    if (info) *info = it->second.info;
+    return it->second.info.status;
+}
+
+int pf_server_times(pf_server_t S, int64_t ticket, double *submit_ms, double *start_ms,
+                    double *done_ms)
+{
+    if (!S) return -1;
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) return -2;
+    const Ticket &T = it->second;
+    if (submit_ms) *submit_ms = T.t_submit - S->epoch_ms;
+    if (start_ms) *start_ms = T.t_start < 0 ? -1.0 : T.t_start - S->epoch_ms;
+    if (done_ms) *done_ms = T.t_done < 0 ? -1.0 : T.t_done - S->epoch_ms;
+    return T.state == 2 ? 1 : 0;
+}
+
+int pf_server_release(pf_server_t S, int64_t factor)
+{
+    if (!S) return -1;
+    auto it = S->resident.find(factor);
+    if (it == S->resident.end()) return -2;
+    it->second.released = true;
+    if (it->second.users == 0) {
+        if (it->second.F) destroy_async(it->second.F);
+        S->used -= it->second.bytes;
+        S->resident.erase(it);
+    }
+    return 0;
+}
+
+int pf_server_stats(pf_server_t S, pf_server_info *st)
+{
+    if (!S) return -1;
+    if (!st) return -2;
+    progress(S);
+    std::memset(st, 0, sizeof *st);
+    st->budget = S->budget;
+    st->used = S->used;
+    st->queued = (int64_t)S->queue.size();
+    st->inflight = S->inflight;
+    st->resident = (int64_t)S->resident.size();
+    st->completed = S->completed;
+    st->evictions = S->evictions;
+    return 0;
+}
+
+void pf_server_destroy(pf_server_t S)
+{
+    if (!S) return;
+    for (hipStream_t s : S->streams) hipStreamSynchronize(s);
+    for (auto &kv : S->tickets) {
+        Ticket &T = kv.second;
+        if (T.ev_start) hipEventDestroy(T.ev_start);
+        if (T.ev_done) hipEventDestroy(T.ev_done);
+        if (T.state == 2 && T.req.factor < 0 && !T.req.keep) continue;   // freed at retire
+        if (T.state == 1 && T.req.factor < 0 && !T.req.keep) destroy_async(T.F);
+    }
+    for (auto &kv : S->resident)
+        if (kv.second.F) destroy_async(kv.second.F);
+    for (hipStream_t s : S->streams) {
+        hipStreamSynchronize(s);
+        hipStreamDestroy(s);
+    }
+    if (S->epoch) hipEventDestroy(S->epoch);
+    delete S;
+}
+
+}  // extern "C"

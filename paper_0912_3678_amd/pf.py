@@ -17,7 +17,7 @@ PF_BTRI, PF_BABD = 0, 1
 PF_FP64, PF_FP32_IR = 0, 1
 PF_OK, PF_ESINGULAR, PF_ENOCONV, PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED = 0, 1, 2, 3, 4, 5
 PF_FLAG_ETA = 1
-PF_FLAG_MAP_ROWS, PF_FLAG_MAP_TILES = 2, 4
+PF_FLAG_MAP_ROWS, PF_FLAG_MAP_TILES, PF_FLAG_AUTOTUNE = 2, 4, 8
 
 EXPORTED = [
     "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",
@@ -25,6 +25,9 @@ EXPORTED = [
     "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
     "pf_plan", "pf_refactor", "pf_profile_enable", "pf_profile_read",
     "pf_batch_create", "pf_batch_run", "pf_batch_factor", "pf_batch_destroy", "pf_factor_solve",
+    "pf_autotune", "pf_autotune_clear",
+    "pf_server_create", "pf_server_submit", "pf_server_poll", "pf_server_wait", "pf_server_times",
+    "pf_server_release", "pf_server_stats", "pf_server_destroy",
 ]
 
 
@@ -89,6 +92,9 @@ def load(path: str = LIB_PATH):
         "pf_batch_run": (ctypes.c_int, [vp, vp, P(pf_info)]),
         "pf_batch_factor": (ctypes.c_int, [vp, i32, P(vp)]),
         "pf_batch_destroy": (None, [vp]),
+        "pf_autotune": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, vp, P(pf_opts),
+                                       P(ctypes.c_float)]),
+        "pf_autotune_clear": (None, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -333,4 +339,115 @@ class Batch:
     def destroy(self):
         if self.h:
             load().pf_batch_destroy(self.h)
+            self.h = None
+
+
+def pf_autotune(A: pf_matrix, base: pf_opts | None = None, nrhs: int = 1, stream=None):
+    """Fastest launch shape for A (pf_opts, median ms of pf_factor_solve)."""
+    best = pf_opts()
+    ms = ctypes.c_float()
+    rc = load().pf_autotune(ctypes.byref(A), ctypes.byref(base) if base is not None else None,
+                            nrhs, _stream(stream), ctypes.byref(best), ctypes.byref(ms))
+    if rc != 0:
+        raise PFError(rc, "pf_autotune")
+    return best, float(ms.value)
+
+
+def pf_autotune_clear():
+    load().pf_autotune_clear()
+
+
+class pf_request(ctypes.Structure):
+    _fields_ = [("A", pf_matrix), ("nrhs", ctypes.c_int32), ("keep", ctypes.c_int32),
+                ("f", ctypes.c_void_p), ("ldf", ctypes.c_int64), ("x", ctypes.c_void_p),
+                ("ldx", ctypes.c_int64), ("factor", ctypes.c_int64)]
+
+
+class pf_server_info(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_size_t), ("used", ctypes.c_size_t), ("queued", ctypes.c_int64),
+                ("inflight", ctypes.c_int64), ("resident", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _server_sigs(lib):
+    vp, i32, i64, P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER
+    d = ctypes.c_double
+    sigs = {
+        "pf_server_create": (ctypes.c_int, [ctypes.c_size_t, P(pf_opts), i32, i32, P(vp)]),
+        "pf_server_submit": (ctypes.c_int, [vp, P(pf_request), P(i64)]),
+        "pf_server_poll": (ctypes.c_int, [vp, i64, P(pf_info)]),
+        "pf_server_wait": (ctypes.c_int, [vp, i64, P(pf_info)]),
+        "pf_server_times": (ctypes.c_int, [vp, i64, P(d), P(d), P(d)]),
+        "pf_server_release": (ctypes.c_int, [vp, i64]),
+        "pf_server_stats": (ctypes.c_int, [vp, P(pf_server_info)]),
+        "pf_server_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+class Server:
+    """pf_server_*: continuous batching of factor-and-solve requests under a
+    device-memory budget, with resident factors for repeat right-hand sides."""
+
+    def __init__(self, budget_bytes, opts=None, max_inflight=0, nstreams=0):
+        lib = load()
+        _server_sigs(lib)
+        h = ctypes.c_void_p()
+        rc = lib.pf_server_create(budget_bytes, ctypes.byref(opts) if opts is not None else None,
+                                  max_inflight, nstreams, ctypes.byref(h))
+        if rc != 0:
+            raise PFError(rc, "pf_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, A, f, x, keep=False, factor=-1):
+        """A: pf_matrix; f, x: device tensors (nrhs, n)."""
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+        req = pf_request(A, nrhs, 1 if keep else 0, f.data_ptr(), f.shape[-1], x.data_ptr(),
+                         x.shape[-1], factor)
+        t = ctypes.c_int64()
+        rc = load().pf_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        if rc != 0:
+            raise PFError(rc, "pf_server_submit")
+        self._keep[t.value] = (f, x)
+        return t.value
+
+    def poll(self, ticket):
+        info = pf_info()
+        rc = load().pf_server_poll(self.h, ticket, ctypes.byref(info))
+        if rc < 0:
+            raise PFError(rc, "pf_server_poll")
+        return info if rc == 1 else None
+
+    def wait(self, ticket):
+        info = pf_info()
+        rc = load().pf_server_wait(self.h, ticket, ctypes.byref(info))
+        if rc < 0 or rc in (PF_EHIP,):
+            raise PFError(rc, "pf_server_wait")
+        return info
+
+    def times(self, ticket):
+        s, a, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        load().pf_server_times(self.h, ticket, ctypes.byref(s), ctypes.byref(a), ctypes.byref(d))
+        return s.value, a.value, d.value
+
+    def release(self, factor):
+        rc = load().pf_server_release(self.h, factor)
+        if rc != 0:
+            raise PFError(rc, "pf_server_release")
+
+    def stats(self):
+        st = pf_server_info()
+        load().pf_server_stats(self.h, ctypes.byref(st))
+        return st.as_dict()
+
+    def destroy(self):
+        if self.h:
+            load().pf_server_destroy(self.h)
             self.h = None
