@@ -311,6 +311,9 @@ typedef struct {
     int64_t ldx;
     int64_t factor;     /* -1: factor A; else the ticket of a request with keep = 1
                            whose factor solves this one (same A)               */
+    void *after;        /* stream whose work queued so far produces A and f: an event
+                           recorded on it at submission orders the request after
+                           that work (NULL = the default stream)               */
 } pf_request;
 
 typedef struct {

@@ -38,14 +38,19 @@ struct Arena {
     char *base = nullptr;
     size_t off = 0, cap = 0;
     bool counting = false;
+    bool stream_ordered = false;   // base from hipMallocAsync: freed the same way
     int refs = 0;
 };
 
 void arena_release(Arena *ar, hipStream_t s)
 {
     if (--ar->refs > 0) return;
-    hipStreamSynchronize(s);
-    if (ar->base) hipFree(ar->base);
+    if (ar->stream_ordered) {
+        if (ar->base) hipFreeAsync(ar->base, s);
+    } else {
+        hipStreamSynchronize(s);
+        if (ar->base) hipFree(ar->base);
+    }
     delete ar;
 }
 
@@ -415,10 +420,12 @@ int ensure_workspace(pf_factor_s *F, int nrhs)
         if (dalloc(F, &p, nP, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
         F->wsPadX = (double *)p;
     }
-    if (dalloc(F, &p, n, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
-    F->wsR = (double *)p;
-    if (dalloc(F, &p, n, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
-    F->wsD = (double *)p;
+    if (F->opts.prec == PF_FP32_IR) {   // residual and correction of the refinement
+        if (dalloc(F, &p, n, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        F->wsR = (double *)p;
+        if (dalloc(F, &p, n, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        F->wsD = (double *)p;
+    }
     if (dalloc(F, &p, 3 * (size_t)cap * sizeof(unsigned long long), F->ws_allocs) != hipSuccess)
         return PF_ENOMEM;
     F->d_norms = (unsigned long long *)p;
@@ -603,7 +610,8 @@ size_t pf_solve_bytes_per_rhs(const pf_matrix *A, const pf_opts *opts)
     size_t b = 0;
     for (size_t l = 1; l < plan.size(); ++l) b += 3 * (size_t)plan[l].nb * M * 8;
     if (M != A->m) b += 2 * (size_t)A->nb * M * 8;
-    b += 2 * (size_t)A->nb * A->m * 8 + 24;
+    if (o.prec == PF_FP32_IR) b += 2 * (size_t)A->nb * A->m * 8;   // residual, correction
+    b += 24;
     return b;
 }
 
@@ -718,6 +726,44 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
     return 0;
 }
 
+// A handle whose memory (factors, reduced systems, status, scratch and the
+// solve workspace for nrhs right-hand sides) is one stream-ordered device
+// allocation: the sizes come from a counting pass through the same set-up
+// code.  One allocation instead of dozens keeps the host cost of a new
+// factorization low (a serving request pays it every time).
+int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, int nrhs,
+                         pf_factor_s **out)
+{
+    Arena count;
+    count.counting = true;
+    pf_factor_s *T = nullptr;
+    int rc = factor_setup(A, o, s, &count, nullptr, &T);
+    if (rc) return rc;
+    rc = ensure_workspace(T, nrhs);
+    delete T;
+    if (rc) return rc;
+    Arena *ar = new Arena();
+    ar->cap = count.off + 256;
+    ar->refs = 1;
+    ar->stream_ordered = true;
+    if (hipMallocAsync((void **)&ar->base, ar->cap, s) != hipSuccess) {
+        delete ar;
+        return PF_ENOMEM;
+    }
+    pf_factor_s *F = nullptr;
+    if ((rc = factor_setup(A, o, s, ar, nullptr, &F)) || (rc = ensure_workspace(F, nrhs))) {
+        if (F) {
+            F->arena = nullptr;
+            delete F;
+        }
+        hipFreeAsync(ar->base, s);
+        delete ar;
+        return rc;
+    }
+    *out = F;
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -737,7 +783,7 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
         o = resolve_opts(&t);
     }
     pf_factor_s *F = nullptr;
-    if ((rc = factor_setup(A, o, s, nullptr, nullptr, &F))) return rc;
+    if ((rc = factor_setup_private(A, o, s, 1, &F))) return rc;
     hipError_t e = launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s);
     if (e == hipSuccess) e = launch_factor_levels(F, s);
     if (e != hipSuccess) {
@@ -929,7 +975,7 @@ int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int
     const pf_opts o = resolve_opts(opts);
     if ((rc = check_opts(A, o))) return rc;
     pf_factor_s *F = nullptr;
-    if ((rc = factor_setup(A, o, s, nullptr, nullptr, &F))) return rc;
+    if ((rc = factor_setup_private(A, o, s, std::max(nrhs, 1), &F))) return rc;
     if ((rc = ensure_workspace(F, std::max(nrhs, 1)))) {
         destroy_async(F);
         return rc;

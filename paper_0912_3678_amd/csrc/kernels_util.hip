@@ -21,8 +21,23 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// One thread per (row, right-hand side); blockIdx.y = right-hand side, so
-// every wave reduces its three norms before one atomic each.
+// max over the 256 threads of a workgroup (waves reduce with shuffles, then
+// one LDS exchange); the result is valid in thread 0
+__device__ __forceinline__ double block_max(double v, double *sh)
+{
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) v = sh[k] > v ? sh[k] : v;
+    return v;
+}
+
+// Grid-stride loops over rows with a bounded grid, and one atomic per
+// workgroup and norm: the atomics to the few norm words stay few.
+// blockIdx.y = right-hand side.
 __global__ __launch_bounds__(256) void k_residual(int kind, int m, int64_t nb,
                                                   const double *__restrict__ D,
                                                   const double *__restrict__ Lo,
@@ -67,10 +82,11 @@ __global__ __launch_bounds__(256) void k_residual(int kind, int m, int64_t nb,
         mx = fmax(mx, fabs(xc[row]));
         mf = fmax(mf, fabs(fv));
     }
-    mr = wave_max(mr);
-    mx = wave_max(mx);
-    mf = wave_max(mf);
-    if ((threadIdx.x & 63) == 0) {
+    __shared__ double sh[4];
+    mr = block_max(mr, sh);
+    mx = block_max(mx, sh);
+    mf = block_max(mf, sh);
+    if (threadIdx.x == 0) {
         atomicMax(norms + 3 * c + 0, dbits(mr));
         atomicMax(norms + 3 * c + 1, dbits(mx));
         atomicMax(norms + 3 * c + 2, dbits(mf));
@@ -101,8 +117,9 @@ __global__ __launch_bounds__(256) void k_norminf(int kind, int m, int64_t nb,
             for (int j = 0; j < m; ++j) s += fabs(C[i + (int64_t)j * m]);
         best = fmax(best, s);
     }
-    best = wave_max(best);
-    if ((threadIdx.x & 63) == 0) atomicMax(out, dbits(best));
+    __shared__ double sh[4];
+    best = block_max(best, sh);
+    if (threadIdx.x == 0) atomicMax(out, dbits(best));
 }
 
 __global__ void k_axpy(int64_t n, const double *__restrict__ d, int64_t ldd,
@@ -206,6 +223,15 @@ __global__ void k_abd_to_btri(int m, int64_t N, int qa, const double *__restrict
     }
 }
 
+// workgroups for the reductions: enough to stream HBM, few atomics
+inline unsigned grid_reduce(int64_t work, int block)
+{
+    int64_t g = (work + block - 1) / block;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
 inline unsigned grid1(int64_t work, int block)
 {
     int64_t g = (work + block - 1) / block;
@@ -222,7 +248,7 @@ hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const d
                            unsigned long long *norms, hipStream_t s)
 {
     const int64_t n = (int64_t)m * nb;
-    hipLaunchKernelGGL(k_residual, dim3(grid1(n, 256), nrhs), dim3(256), 0, s, kind, m, nb, D,
+    hipLaunchKernelGGL(k_residual, dim3(grid_reduce(n, 256), nrhs), dim3(256), 0, s, kind, m, nb, D,
                        Lo, Up, C, f, ldf, x, ldx, r, ldr, norms);
     return hipGetLastError();
 }
@@ -232,7 +258,7 @@ hipError_t launch_norminf(int kind, int m, int64_t nb, const double *D, const do
                           hipStream_t s)
 {
     const int64_t n = (int64_t)m * nb;
-    hipLaunchKernelGGL(k_norminf, dim3(grid1(n, 256)), dim3(256), 0, s, kind, m, nb, D, Lo, Up,
+    hipLaunchKernelGGL(k_norminf, dim3(grid_reduce(n, 256)), dim3(256), 0, s, kind, m, nb, D, Lo, Up,
                        C, out);
     return hipGetLastError();
 }

@@ -42,6 +42,7 @@ struct Ticket {
     pf_info info{};
     double t_submit = 0, t_start = -1, t_done = -1;   // ms, server clock
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
+    hipEvent_t ev_ready = nullptr;   // inputs ready (recorded on req.after at submission)
     pf_factor_t F = nullptr;   // the factor this request ran on
 };
 
@@ -149,7 +150,8 @@ void retire(pf_server_s *S)
         }
         hipEventDestroy(T.ev_start);
         hipEventDestroy(T.ev_done);
-        T.ev_start = T.ev_done = nullptr;
+        if (T.ev_ready) hipEventDestroy(T.ev_ready);
+        T.ev_start = T.ev_done = T.ev_ready = nullptr;
     }
 }
 
@@ -166,6 +168,7 @@ int launch(pf_server_s *S, int64_t id, Ticket &T)
         si = (int)(std::min_element(S->load.begin(), S->load.end()) - S->load.begin());
     }
     hipStream_t s = S->streams[si];
+    if (T.ev_ready && hipStreamWaitEvent(s, T.ev_ready, 0) != hipSuccess) return PF_EHIP;
     hipEventRecord(T.ev_start, s);
     int rc;
     if (r.factor >= 0) {
@@ -204,7 +207,8 @@ void fail(pf_server_s *S, Ticket &T, int rc)
     T.t_done = now_ms();
     if (T.ev_start) hipEventDestroy(T.ev_start);
     if (T.ev_done) hipEventDestroy(T.ev_done);
-    T.ev_start = T.ev_done = nullptr;
+    if (T.ev_ready) hipEventDestroy(T.ev_ready);
+    T.ev_start = T.ev_done = T.ev_ready = nullptr;
     (void)S;
 }
 
@@ -316,6 +320,12 @@ int pf_server_submit(pf_server_t S, const pf_request *req, int64_t *ticket)
     Ticket &T = S->tickets[id];
     T.req = r;
     T.t_submit = now_ms();
+    if (hipEventCreateWithFlags(&T.ev_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(T.ev_ready, (hipStream_t)r.after) != hipSuccess) {
+        if (T.ev_ready) hipEventDestroy(T.ev_ready);
+        S->tickets.erase(id);
+        return PF_EHIP;
+    }
     if (r.factor >= 0) ++S->resident[r.factor].users;
     if (r.factor < 0 && r.keep) {      // later requests may name it at once
         Resident R;
@@ -415,6 +425,7 @@ void pf_server_destroy(pf_server_t S)
         Ticket &T = kv.second;
         if (T.ev_start) hipEventDestroy(T.ev_start);
         if (T.ev_done) hipEventDestroy(T.ev_done);
+        if (T.ev_ready) hipEventDestroy(T.ev_ready);
         if (T.state == 2 && T.req.factor < 0 && !T.req.keep) continue;   // freed at retire
         if (T.state == 1 && T.req.factor < 0 && !T.req.keep) destroy_async(T.F);
     }

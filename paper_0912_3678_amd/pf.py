@@ -360,7 +360,7 @@ def pf_autotune_clear():
 class pf_request(ctypes.Structure):
     _fields_ = [("A", pf_matrix), ("nrhs", ctypes.c_int32), ("keep", ctypes.c_int32),
                 ("f", ctypes.c_void_p), ("ldf", ctypes.c_int64), ("x", ctypes.c_void_p),
-                ("ldx", ctypes.c_int64), ("factor", ctypes.c_int64)]
+                ("ldx", ctypes.c_int64), ("factor", ctypes.c_int64), ("after", ctypes.c_void_p)]
 
 
 class pf_server_info(ctypes.Structure):
@@ -406,11 +406,13 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, A, f, x, keep=False, factor=-1):
-        """A: pf_matrix; f, x: device tensors (nrhs, n)."""
+    def submit(self, A, f, x, keep=False, factor=-1, stream=None):
+        """A: pf_matrix; f, x: device tensors (nrhs, n).  The request runs
+        after the work queued so far on `stream` (torch's current stream by
+        default), which is where A and f were produced."""
         nrhs = 1 if f.dim() == 1 else f.shape[0]
         req = pf_request(A, nrhs, 1 if keep else 0, f.data_ptr(), f.shape[-1], x.data_ptr(),
-                         x.shape[-1], factor)
+                         x.shape[-1], factor, _stream(stream))
         t = ctypes.c_int64()
         rc = load().pf_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
         if rc != 0:
