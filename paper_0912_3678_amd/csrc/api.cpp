@@ -275,11 +275,17 @@ hipError_t prof_launch(pf_factor_s *F, bool factor, int phase, int level, hipStr
     auto &sl = list[n++];
     sl.phase = phase;
     sl.level = level;
-    hipError_t e = hipEventRecord(sl.a, s);
-    if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    return hipEventRecord(sl.b, s);
+    // the launch stamps its kernel's own start and end into the events
+    LaunchTiming &t = launch_timing();
+    t.start = sl.a;
+    t.stop = sl.b;
+    hipError_t e = fn();
+    if (t.start) {   // nothing was launched: mark the point in the stream
+        t.start = t.stop = nullptr;
+        if (e == hipSuccess) e = hipEventRecord(sl.a, s);
+        if (e == hipSuccess) e = hipEventRecord(sl.b, s);
+    }
+    return e;
 }
 
 // Kernel arguments of the factorization of level l.

@@ -15,6 +15,8 @@
 #pragma once
 #include "pf_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 namespace pf {
@@ -257,6 +259,20 @@ inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)
 {
     const int64_t gpw = WG / M;
     return dim3((unsigned)((p + gpw - 1) / gpw), (unsigned)((nrhs + KC - 1) / KC), 1);
+}
+
+// Launch a kernel on stream s; when launch_timing() holds events, the
+// kernel's own start and end are stamped into them (and they are consumed).
+template <typename K, typename... Args>
+inline void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    LaunchTiming &t = launch_timing();
+    if (t.start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.start, t.stop, 0, args...);
+        t.start = t.stop = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
 }
 
 }  // namespace

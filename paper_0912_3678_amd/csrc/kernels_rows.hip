@@ -364,11 +364,11 @@ hipError_t launch_btri_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
         constexpr int MV = decltype(mc)::value;
         const dim3 grid = grid_for(MV, a.p, 1, 1);
         if (a.Dadd) {
-            if (f32) hipLaunchKernelGGL((k_btri_factor<MV, float, true>), grid, dim3(WG), 0, s, a);
-            else hipLaunchKernelGGL((k_btri_factor<MV, double, true>), grid, dim3(WG), 0, s, a);
+            if (f32) launch_k((k_btri_factor<MV, float, true>), grid, dim3(WG), s, a);
+            else launch_k((k_btri_factor<MV, double, true>), grid, dim3(WG), s, a);
         } else {
-            if (f32) hipLaunchKernelGGL((k_btri_factor<MV, float, false>), grid, dim3(WG), 0, s, a);
-            else hipLaunchKernelGGL((k_btri_factor<MV, double, false>), grid, dim3(WG), 0, s, a);
+            if (f32) launch_k((k_btri_factor<MV, float, false>), grid, dim3(WG), s, a);
+            else launch_k((k_btri_factor<MV, double, false>), grid, dim3(WG), s, a);
         }
         return hipGetLastError();
     });
@@ -379,8 +379,8 @@ hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
         const dim3 grid = grid_for(MV, a.p, 1, 1);
-        if (f32) hipLaunchKernelGGL((k_babd_factor<MV, float>), grid, dim3(WG), 0, s, a);
-        else hipLaunchKernelGGL((k_babd_factor<MV, double>), grid, dim3(WG), 0, s, a);
+        if (f32) launch_k((k_babd_factor<MV, float>), grid, dim3(WG), s, a);
+        else launch_k((k_babd_factor<MV, double>), grid, dim3(WG), s, a);
         return hipGetLastError();
     });
 }
@@ -393,14 +393,14 @@ hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, const LevelA
         constexpr int MV = decltype(mc)::value;
         const dim3 grid(nwg);
         if (kind == 1) {
-            if (f32) hipLaunchKernelGGL((kb_babd_factor<MV, float>), grid, dim3(WG), 0, s, tab, work);
-            else hipLaunchKernelGGL((kb_babd_factor<MV, double>), grid, dim3(WG), 0, s, tab, work);
+            if (f32) launch_k((kb_babd_factor<MV, float>), grid, dim3(WG), s, tab, work);
+            else launch_k((kb_babd_factor<MV, double>), grid, dim3(WG), s, tab, work);
         } else if (add) {
-            if (f32) hipLaunchKernelGGL((kb_btri_factor<MV, float, true>), grid, dim3(WG), 0, s, tab, work);
-            else hipLaunchKernelGGL((kb_btri_factor<MV, double, true>), grid, dim3(WG), 0, s, tab, work);
+            if (f32) launch_k((kb_btri_factor<MV, float, true>), grid, dim3(WG), s, tab, work);
+            else launch_k((kb_btri_factor<MV, double, true>), grid, dim3(WG), s, tab, work);
         } else {
-            if (f32) hipLaunchKernelGGL((kb_btri_factor<MV, float, false>), grid, dim3(WG), 0, s, tab, work);
-            else hipLaunchKernelGGL((kb_btri_factor<MV, double, false>), grid, dim3(WG), 0, s, tab, work);
+            if (f32) launch_k((kb_btri_factor<MV, float, false>), grid, dim3(WG), s, tab, work);
+            else launch_k((kb_btri_factor<MV, double, false>), grid, dim3(WG), s, tab, work);
         }
         return hipGetLastError();
     });

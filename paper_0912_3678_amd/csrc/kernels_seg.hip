@@ -522,27 +522,27 @@ hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &
         const SolveArgs &v = sv ? *sv : none;
         if (kind == 1) {
             if (sv) {
-                if (f32) hipLaunchKernelGGL((k_babd_seg<MV, EV, float, true>), grid, dim3(WG), 0, s, a, v);
-                else hipLaunchKernelGGL((k_babd_seg<MV, EV, double, true>), grid, dim3(WG), 0, s, a, v);
+                if (f32) launch_k((k_babd_seg<MV, EV, float, true>), grid, dim3(WG), s, a, v);
+                else launch_k((k_babd_seg<MV, EV, double, true>), grid, dim3(WG), s, a, v);
             } else {
-                if (f32) hipLaunchKernelGGL((k_babd_seg<MV, EV, float, false>), grid, dim3(WG), 0, s, a, v);
-                else hipLaunchKernelGGL((k_babd_seg<MV, EV, double, false>), grid, dim3(WG), 0, s, a, v);
+                if (f32) launch_k((k_babd_seg<MV, EV, float, false>), grid, dim3(WG), s, a, v);
+                else launch_k((k_babd_seg<MV, EV, double, false>), grid, dim3(WG), s, a, v);
             }
         } else if (a.Dadd) {
             if (sv) {
-                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, true, true>), grid, dim3(WG), 0, s, a, v);
-                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, true, true>), grid, dim3(WG), 0, s, a, v);
+                if (f32) launch_k((k_btri_seg<MV, EV, float, true, true>), grid, dim3(WG), s, a, v);
+                else launch_k((k_btri_seg<MV, EV, double, true, true>), grid, dim3(WG), s, a, v);
             } else {
-                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, true, false>), grid, dim3(WG), 0, s, a, v);
-                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, true, false>), grid, dim3(WG), 0, s, a, v);
+                if (f32) launch_k((k_btri_seg<MV, EV, float, true, false>), grid, dim3(WG), s, a, v);
+                else launch_k((k_btri_seg<MV, EV, double, true, false>), grid, dim3(WG), s, a, v);
             }
         } else {
             if (sv) {
-                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, false, true>), grid, dim3(WG), 0, s, a, v);
-                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, false, true>), grid, dim3(WG), 0, s, a, v);
+                if (f32) launch_k((k_btri_seg<MV, EV, float, false, true>), grid, dim3(WG), s, a, v);
+                else launch_k((k_btri_seg<MV, EV, double, false, true>), grid, dim3(WG), s, a, v);
             } else {
-                if (f32) hipLaunchKernelGGL((k_btri_seg<MV, EV, float, false, false>), grid, dim3(WG), 0, s, a, v);
-                else hipLaunchKernelGGL((k_btri_seg<MV, EV, double, false, false>), grid, dim3(WG), 0, s, a, v);
+                if (f32) launch_k((k_btri_seg<MV, EV, float, false, false>), grid, dim3(WG), s, a, v);
+                else launch_k((k_btri_seg<MV, EV, double, false, false>), grid, dim3(WG), s, a, v);
             }
         }
         return hipGetLastError();
@@ -557,14 +557,14 @@ hipError_t launch_seg_factor_batch(int kind, int M, int E, bool f32, bool add, c
         constexpr int MV = decltype(mc)::value, EV = decltype(ec)::value;
         const dim3 grid(nwg);
         if (kind == 1) {
-            if (f32) hipLaunchKernelGGL((kb_babd_seg<MV, EV, float>), grid, dim3(WG), 0, s, tab, work);
-            else hipLaunchKernelGGL((kb_babd_seg<MV, EV, double>), grid, dim3(WG), 0, s, tab, work);
+            if (f32) launch_k((kb_babd_seg<MV, EV, float>), grid, dim3(WG), s, tab, work);
+            else launch_k((kb_babd_seg<MV, EV, double>), grid, dim3(WG), s, tab, work);
         } else if (add) {
-            if (f32) hipLaunchKernelGGL((kb_btri_seg<MV, EV, float, true>), grid, dim3(WG), 0, s, tab, work);
-            else hipLaunchKernelGGL((kb_btri_seg<MV, EV, double, true>), grid, dim3(WG), 0, s, tab, work);
+            if (f32) launch_k((kb_btri_seg<MV, EV, float, true>), grid, dim3(WG), s, tab, work);
+            else launch_k((kb_btri_seg<MV, EV, double, true>), grid, dim3(WG), s, tab, work);
         } else {
-            if (f32) hipLaunchKernelGGL((kb_btri_seg<MV, EV, float, false>), grid, dim3(WG), 0, s, tab, work);
-            else hipLaunchKernelGGL((kb_btri_seg<MV, EV, double, false>), grid, dim3(WG), 0, s, tab, work);
+            if (f32) launch_k((kb_btri_seg<MV, EV, float, false>), grid, dim3(WG), s, tab, work);
+            else launch_k((kb_btri_seg<MV, EV, double, false>), grid, dim3(WG), s, tab, work);
         }
         return hipGetLastError();
     });

@@ -250,15 +250,15 @@ static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t 
             const bool add = KIND == 0 && a.Fadd;
             if (FWD) {
                 if (add) {
-                    if (f32) hipLaunchKernelGGL((k_fwd<KIND, MV, KC, float, true>), grid, dim3(WG), 0, s, a);
-                    else hipLaunchKernelGGL((k_fwd<KIND, MV, KC, double, true>), grid, dim3(WG), 0, s, a);
+                    if (f32) launch_k((k_fwd<KIND, MV, KC, float, true>), grid, dim3(WG), s, a);
+                    else launch_k((k_fwd<KIND, MV, KC, double, true>), grid, dim3(WG), s, a);
                 } else {
-                    if (f32) hipLaunchKernelGGL((k_fwd<KIND, MV, KC, float, false>), grid, dim3(WG), 0, s, a);
-                    else hipLaunchKernelGGL((k_fwd<KIND, MV, KC, double, false>), grid, dim3(WG), 0, s, a);
+                    if (f32) launch_k((k_fwd<KIND, MV, KC, float, false>), grid, dim3(WG), s, a);
+                    else launch_k((k_fwd<KIND, MV, KC, double, false>), grid, dim3(WG), s, a);
                 }
             } else {
-                if (f32) hipLaunchKernelGGL((k_bwd<KIND, MV, KC, float>), grid, dim3(WG), 0, s, a);
-                else hipLaunchKernelGGL((k_bwd<KIND, MV, KC, double>), grid, dim3(WG), 0, s, a);
+                if (f32) launch_k((k_bwd<KIND, MV, KC, float>), grid, dim3(WG), s, a);
+                else launch_k((k_bwd<KIND, MV, KC, double>), grid, dim3(WG), s, a);
             }
             return hipGetLastError();
         });
@@ -294,15 +294,15 @@ static hipError_t launch_solve_batch_k(bool fwd, int M, bool f32, bool add, int 
             const dim3 grid(nwg);
             if (fwd) {
                 if (KIND == 0 && add) {
-                    if (f32) hipLaunchKernelGGL((kb_fwd<KIND, MV, K, float, true>), grid, dim3(WG), 0, s, tab, work);
-                    else hipLaunchKernelGGL((kb_fwd<KIND, MV, K, double, true>), grid, dim3(WG), 0, s, tab, work);
+                    if (f32) launch_k((kb_fwd<KIND, MV, K, float, true>), grid, dim3(WG), s, tab, work);
+                    else launch_k((kb_fwd<KIND, MV, K, double, true>), grid, dim3(WG), s, tab, work);
                 } else {
-                    if (f32) hipLaunchKernelGGL((kb_fwd<KIND, MV, K, float, false>), grid, dim3(WG), 0, s, tab, work);
-                    else hipLaunchKernelGGL((kb_fwd<KIND, MV, K, double, false>), grid, dim3(WG), 0, s, tab, work);
+                    if (f32) launch_k((kb_fwd<KIND, MV, K, float, false>), grid, dim3(WG), s, tab, work);
+                    else launch_k((kb_fwd<KIND, MV, K, double, false>), grid, dim3(WG), s, tab, work);
                 }
             } else {
-                if (f32) hipLaunchKernelGGL((kb_bwd<KIND, MV, K, float>), grid, dim3(WG), 0, s, tab, work);
-                else hipLaunchKernelGGL((kb_bwd<KIND, MV, K, double>), grid, dim3(WG), 0, s, tab, work);
+                if (f32) launch_k((kb_bwd<KIND, MV, K, float>), grid, dim3(WG), s, tab, work);
+                else launch_k((kb_bwd<KIND, MV, K, double>), grid, dim3(WG), s, tab, work);
             }
             return hipGetLastError();
         });

@@ -242,6 +242,12 @@ inline unsigned grid1(int64_t work, int block)
 
 }  // namespace
 
+LaunchTiming &launch_timing()
+{
+    static thread_local LaunchTiming t;
+    return t;
+}
+
 hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const double *Lo,
                            const double *Up, const double *C, int32_t nrhs, const double *f,
                            int64_t ldf, const double *x, int64_t ldx, double *r, int64_t ldr,

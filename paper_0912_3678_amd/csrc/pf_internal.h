@@ -129,6 +129,15 @@ hipError_t launch_abd_to_btri(int m, int64_t N, int qa, const double *Ba, const 
                               const double *R, const double *Bb, double *D, double *Lo,
                               double *Up, hipStream_t s);
 
+// Timing of one launch from inside its dispatch packet: a launcher whose
+// next kernel launch finds these events set launches it with
+// hipExtLaunchKernel, which stamps the kernel's own start and end into them,
+// and clears them (kernels_util.hip holds the thread-local instance).
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchTiming &launch_timing();
+
 // Handle helpers for the request scheduler (api.cpp): factor a new handle
 // and solve in one go on a stream, release without a host wait, and read the
 // status word of a handle whose work is complete.
