@@ -60,8 +60,9 @@ def parse():
     ap.add_argument("--coarse-rows", type=int, default=0)
     ap.add_argument("--split", action="store_true",
                     help="time pf_refactor + pf_solve instead of the fused pf_factor_solve")
-    ap.add_argument("--map", choices=["auto", "rows"], default="auto",
-                    help="factor lane mapping: planner default (segments), or rows on every level")
+    ap.add_argument("--map", choices=["auto", "segments", "rows"], default="auto",
+                    help="factor lane mapping: planner default (matrix cores at the finest "
+                         "level for m = 8, segments elsewhere), segments only, or rows")
     ap.add_argument("--lane-entries", type=int, default=0,
                     help="segment mapping at level 0: block entries per lane (0 = planner)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -92,7 +93,8 @@ def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
     return level_nb * (mm * w + 2 * m * 8 * nrhs)           # read Z, t; write x
 
 
-KERNEL_SOURCES = ("kernels_common.h", "kernels_seg.hip", "kernels_rows.hip", "kernels_solve.hip")
+KERNEL_SOURCES = ("kernels_common.h", "kernels_gj.h", "kernels_seg.hip", "kernels_mfma.hip",
+                  "kernels_rows.hip", "kernels_solve.hip")
 
 
 def source_hash():
@@ -146,7 +148,7 @@ def run_bvp(args):
     f = wl.to_device_rhs(s.f, dev)
     x = torch.empty_like(f)
     A = pf.make_matrix(pf.PF_BTRI, m, nb, D, Lo, Up)
-    flags = {"auto": 0, "rows": pf.PF_FLAG_MAP_ROWS}[args.map]
+    flags = {"auto": 0, "segments": pf.PF_FLAG_MAP_SEGMENTS, "rows": pf.PF_FLAG_MAP_ROWS}[args.map]
     opts = pf.make_opts(partitions=args.partitions, block_rows=args.block_rows,
                         coarse_rows=args.coarse_rows, flags=flags, lane_entries=args.lane_entries)
     F = pf.pf_factor(A, opts)
@@ -214,9 +216,12 @@ def run_bvp(args):
     dom = max(kernels, key=lambda k: k["avg_us"])
     M = 1 << (m - 1).bit_length()
     E = 0 if args.map == "rows" else (args.lane_entries or {8: 2, 16: 4, 32: 0}.get(M, 1))
-    names = {"factor": (f"k_btri_seg<{M}, {E}, double, false, false>" if E else
+    mfma = args.map == "auto" and not args.lane_entries and M == 8
+    names = {"factor": ("k_btri_mfma<false>" if mfma else
+                        f"k_btri_seg<{M}, {E}, double, false, false>" if E else
                         f"k_btri_factor<{M}, double, false>"),
-             "factor+forward": f"k_btri_seg<{M}, {E}, double, false, true>",
+             "factor+forward": ("k_btri_mfma<true>" if mfma else
+                                f"k_btri_seg<{M}, {E}, double, false, true>"),
              "forward": f"k_fwd<0, {M}, 1, double, false>", "backward": f"k_bwd<0, {M}, 1, double>"}
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6
@@ -240,7 +245,9 @@ def run_bvp(args):
         "config": {"workload": "trapezoid_bvp_btri", "N": args.N, "m": m, "nb": nb,
                    "unknowns": n, "nrhs": 1,
                    "partitions": args.partitions or "planner",
-                   "lane_mapping": "rows" if args.map == "rows" else f"segments of {E}",
+                   "lane_mapping": ("rows" if args.map == "rows" else
+                                    "matrix cores at level 0, segments above" if mfma else
+                                    f"segments of {E}"),
                    "levels": [[k, a, b] for k, a, b in levels],
                    "step": "pf_refactor + pf_solve" if args.split else
                            "pf_factor_solve (refactor + solve, forward sweep fused per level)"},

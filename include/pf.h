@@ -77,11 +77,17 @@ enum {
                               uses rows).  The mappings differ
                               only in rounding.                                      */
     PF_FLAG_MAP_TILES = 4, /* reserved (the segment mapping is the default)         */
-    PF_FLAG_AUTOTUNE = 8   /* pf_factor / pf_batch_create take block_rows,
+    PF_FLAG_AUTOTUNE = 8,  /* pf_factor / pf_batch_create take block_rows,
                               coarse_rows, lane_entries and the mapping from the
                               autotuner's cache for the system's shape class,
                               tuning on this matrix first when the class is new
                               (see pf_autotune)                                      */
+    PF_FLAG_MAP_SEGMENTS = 16 /* the finest level of an FP64 PF_BTRI matrix with
+                              m = 8 (after padding) runs its block products on the
+                              matrix cores by default (v_mfma_f64_16x16x4f64,
+                              two partitions per wave); this flag, or lane_entries
+                              > 0, keeps it on the segment mapping.  The mappings
+                              differ only in rounding.                               */
 };
 
 typedef struct {

@@ -10,13 +10,15 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_rows.hip", "kernels_seg.hip", "kernels_solve.hip", "kernels_util.hip", "api.cpp", "tune.cpp", "server.cpp"]
+SOURCES = ["kernels_rows.hip", "kernels_seg.hip", "kernels_mfma.hip", "kernels_solve.hip", "kernels_util.hip", "api.cpp", "tune.cpp", "server.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results straight into VGPRs (no copies out of AGPRs)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

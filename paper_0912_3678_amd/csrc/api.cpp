@@ -21,7 +21,8 @@ struct Level {
     int kind = PF_BTRI;
     int64_t nb = 0, p = 1;
     bool f32 = false;
-    int seg = 0;          // factor lane mapping: E entries per lane (segments), 0 = rows
+    int seg = 0;          // factor lane mapping: E entries per lane (segments), 0 = rows,
+                          // kMapMfma = matrix-core products (finest level, m = 8)
     const double *D = nullptr, *Dadd = nullptr, *Lo = nullptr, *Up = nullptr, *C = nullptr;
     void *E = nullptr, *R = nullptr, *Z = nullptr, *X = nullptr;
     double *nD = nullptr, *nDadd = nullptr, *nLo = nullptr, *nUp = nullptr, *nC = nullptr;
@@ -120,11 +121,16 @@ constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chai
 // lanes and gives the lowest latency per row, which bounds the reduced
 // levels; at level 0 (many partitions) fewer, wider lanes spend fewer
 // instructions per partition.  m = 16 uses four entries per lane (one wave
-// per partition), m = 32 the row mapping.
-int seg_width(int M, int level, const pf_opts &o)
+// per partition), m = 32 the row mapping.  The finest level of an FP64 block
+// tridiagonal matrix with m = 8 runs its block products on the matrix cores
+// (kMapMfma), unless a mapping is asked for.
+constexpr int kMapMfma = -1;
+
+int seg_width(int M, int level, int kind, bool f32, const pf_opts &o)
 {
     if (o.flags & PF_FLAG_MAP_ROWS) return 0;
     if (level == 0 && o.lane_entries > 0) return seg_ok(M, o.lane_entries) ? o.lane_entries : 0;
+    if (level == 0 && !(o.flags & PF_FLAG_MAP_SEGMENTS) && mfma_ok(kind, M, f32, false)) return kMapMfma;
     if (level == 0 && M == 8) return 2;   // 0.153 vs 0.156 ms per step with one entry
     for (int E = 1; E <= M; E <<= 1)
         if (seg_ok(M, E)) return E;
@@ -378,6 +384,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         const Level &L = F->lv[l];
         const LevelArgs a = level_args(F, l);
         e = prof_launch(F, true, 0, (int)l, s, [&] {
+            if (L.seg == kMapMfma) return launch_mfma_factor(a, nullptr, s);
             if (L.seg) return launch_seg_factor(L.kind, F->M, L.seg, L.f32, a, nullptr, s);
             return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
                                        : launch_babd_factor(F->M, L.f32, a, s);
@@ -512,6 +519,7 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
         const Level &lv = F->lv[l];
         const LevelArgs a = level_args(F, l);
         HIPCHK(prof_launch(F, true, 3, (int)l, s, [&] {
+            if (lv.seg == kMapMfma) return launch_mfma_factor(a, &args[l], s);
             return launch_seg_factor(lv.kind, M, lv.seg, lv.f32, a, &args[l], s);
         }));
     }
@@ -687,7 +695,7 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         L.nb = plan[l].nb;
         L.p = plan[l].p;
         L.f32 = (l == 0 && o.prec == PF_FP32_IR);
-        L.seg = seg_width(M, (int)l, o);
+        L.seg = seg_width(M, (int)l, L.kind, L.f32, o);
         if (l == 0) {
             L.D = D0; L.Lo = Lo0;
             if (A->kind == PF_BTRI) L.Up = Up0;
@@ -1123,7 +1131,7 @@ struct BatchLaunch {
     int phase;      // 0 factor, 1 forward sweep, 2 back substitution
     int kind, M, KC;
     bool f32, add;
-    int seg;        // factor launches: segment width (0 = rows)
+    int seg;        // factor launches: segment width (0 = rows, kMapMfma = matrix cores)
     size_t work;    // first work item of this launch
     int nwg;
 };
@@ -1192,7 +1200,9 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
             BatchLaunch bl{0, std::get<0>(kv.first), std::get<1>(kv.first), 1,
                            std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0,
                            std::get<4>(kv.first), work.size(), 0};
-            const int gpw = bl.seg ? seg_partitions_per_wg(bl.M, bl.seg) : groups_per_wg(bl.M);
+            const int gpw = bl.seg == kMapMfma ? mfma_partitions_per_wg()
+                            : bl.seg           ? seg_partitions_per_wg(bl.M, bl.seg)
+                                               : groups_per_wg(bl.M);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(level_args(B->all[i], l));
@@ -1261,10 +1271,11 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
         if (e == hipSuccess && F->M != F->m) e = launch_pad_matrix(F, s);
     for (const auto &bl : B->flaunch)
         if (e == hipSuccess)
-            e = bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
-                                                 B->d_lwork + bl.work, bl.nwg, s)
-                       : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
-                                             B->d_lwork + bl.work, bl.nwg, s);
+            e = bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+                : bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
+                                                   B->d_lwork + bl.work, bl.nwg, s)
+                         : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
+                                               B->d_lwork + bl.work, bl.nwg, s);
     if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
         for (auto *F : B->all) {
             const pf_matrix &A = F->A;

@@ -127,6 +127,57 @@ __device__ __forceinline__ void ld_fac(T (&v)[M], const T *__restrict__ p)
     }
 }
 
+// ---- raw buffers -----------------------------------------------------------
+// A raw buffer resource over [base, base + bytes): loads at byte offsets at or
+// past the end return zero and stores there are dropped (the hardware range
+// check of raw buffers, which covers the per-lane offset).  Offsets are 32
+// bits, so kernels rebase a resource per workgroup near the rows it touches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint64_t bytes)
+{
+    const uint32_t n = bytes > 0xFFFFFF00ull ? 0xFFFFFF00u : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
+}
+// an offset past the end of every resource (sizes are clamped below it): a
+// store there is dropped
+constexpr uint32_t kOffNone = 0xFFFFFFF0u;
+
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                          r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+// E consecutive T at byte offset off (16-byte stores where the size allows)
+template <int E, typename T>
+__device__ __forceinline__ void buf_st_row(__amdgpu_buffer_rsrc_t r, uint32_t off, const T (&v)[E])
+{
+    if constexpr (sizeof(T) == 8 && E % 2 == 0) {
+        using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+#pragma unroll
+        for (int e = 0; e < E; e += 2) {
+            const double2 w = make_double2(v[e], v[e + 1]);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, w), r, (int)(off + e * 8), 0, 0);
+        }
+    } else if constexpr (sizeof(T) == 4 && E % 4 == 0) {
+        using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+#pragma unroll
+        for (int e = 0; e < E; e += 4) {
+            const float4 w = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, w), r, (int)(off + e * 4), 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf_st(r, off + e * (uint32_t)sizeof(T), v[e]);
+    }
+}
+
 template <int M, typename T>
 __device__ __forceinline__ void ld_row_d(T (&v)[M], const double *__restrict__ blk, int i)
 {

@@ -8,103 +8,25 @@
 // partitions).  Larger E spends fewer instructions per partition and suits
 // the finest level (many partitions, bound by issue and bandwidth).
 //
-// Pivot blocks are inverted in place by Gauss-Jordan exchange steps (row
-// partial pivoting inside the block, pivot ranked by pivot_key): step j
-// exchanges unknown j with the equation of its pivot row p_j; with v =
-// b(p_j, j) the tableau becomes b(p_j, j) = 1/v, b(p_j, l) = b(p_j, l)/v,
-// b(i, j) = -b(i, j)/v and b(i, l) = b(i, l) - b(i, j) b(p_j, l)/v.  After the
-// M steps entry (r, c) of the tableau is entry (sigma(r), p_c) of the
-// inverse, sigma(r) being the step at which row r was the pivot.  The pivot
-// search of step j+1 is a DPP reduction in the segment column holding
-// column j+1, right after step j's update, so a step costs one LDS round
-// trip.  Block products read rows of the left operand and columns of the
-// right operand from the partition's LDS slice; the factor kernels can also
-// sweep up to M right-hand sides forward in the same pass (factor-and-solve:
-// the F solve of Sec. 2 alongside the factorization), lane (r, g) carrying
-// right-hand-side columns g*E .. g*E+E-1.
+// Pivot blocks are inverted in place by the Gauss-Jordan exchange steps of
+// kernels_gj.h.  Block products read rows of the left operand and columns of
+// the right operand from the partition's LDS slice; the factor kernels can
+// also sweep up to M right-hand sides forward in the same pass
+// (factor-and-solve: the F solve of Sec. 2 alongside the factorization), lane
+// (r, g) carrying right-hand-side columns g*E .. g*E+E-1.
 //
 // Outputs and recurrences are those of the row mapping (kernels_rows.hip):
 // row-major factor blocks E, X, Zh, R per block row, the reduced matrix of
 // eq. (redmatr) / (redmatr1), and for the forward sweep t and the reduced
 // right-hand side.
-#include "kernels_common.h"
+#include "kernels_gj.h"
 
 namespace pf {
 namespace {
 
-template <int M, int E> constexpr int seg_lanes() { return M * M / E; }
-
-// E consecutive T in LDS <-> registers (16- or 8-byte accesses when the
-// size and the alignment of segment starts allow)
-template <int E, typename T>
-__device__ __forceinline__ void lds_put(T *p, const T (&v)[E])
-{
-    if constexpr (sizeof(T) == 8 && E % 2 == 0) {
-#pragma unroll
-        for (int e = 0; e < E; e += 2) *reinterpret_cast<double2 *>(p + e) = make_double2(v[e], v[e + 1]);
-    } else if constexpr (sizeof(T) == 4 && E % 4 == 0) {
-#pragma unroll
-        for (int e = 0; e < E; e += 4)
-            *reinterpret_cast<float4 *>(p + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-    } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) p[e] = v[e];
-    }
-}
-template <int E, typename T>
-__device__ __forceinline__ void lds_get(T (&v)[E], const T *p)
-{
-    lds_row<E, T>(v, p);
-}
-
-// pivot row of column j: reduce in the segment column holding column j,
-// then broadcast to the partition's lanes
-template <int M, int E, typename T>
-__device__ __forceinline__ int seg_pivot(T bj, bool used, int r, int j)
-{
-    constexpr int LP = seg_lanes<M, E>();
-    const int idx = group_pivot<M>(pivot_key(bj, r, used));
-    if constexpr (LP == WG) return __builtin_amdgcn_readlane(idx, (j / E) * M);
-    else return __shfl(idx, (int)((threadIdx.x / LP) * LP) + (j / E) * M, WG);
-}
-
-// In-place Gauss-Jordan of the tableau b = D'(r, c0 .. c0+E-1); returns
-// sigma(r) and p_c of the lane's columns through the references.
-template <int M, int E, typename T>
-__device__ __forceinline__ void seg_invert(T (&b)[E], int r, int c0, T *S, int &sigma,
-                                           int (&pc)[E], bool &sing)
-{
-    constexpr int RS = M + kPad<T>;
-    bool used = false;
-    int pr = seg_pivot<M, E, T>(b[0], used, r, 0);
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        lds_put<E, T>(S + r * RS + c0, b);
-        wave_sync();
-        T prow[E];
-        lds_get<E, T>(prow, S + pr * RS + c0);
-        const T mcol = S[r * RS + j], pv = S[pr * RS + j];
-        sing = sing || (pv == T(0));
-        const T inv = recip(pv);
-        const bool isr = (r == pr);
-        // exchange step as selects of computed values (no divergent code):
-        // q = 1/v in the pivot row and -b(i,j)/v elsewhere; entries off
-        // column j become q b(p_j, l) + [row is not the pivot] b(i, l)
-        const T q = isr ? inv : -(mcol * inv);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool isc = (c0 + e == j);
-            const T sb = isr ? T(0) : b[e];
-            const T w = fma(q, prow[e], sb);
-            b[e] = isc ? q : w;
-            pc[e] = isc ? pr : pc[e];
-        }
-        used = used || isr;
-        sigma = isr ? j : sigma;
-        wave_sync();
-        if (j + 1 < M) pr = seg_pivot<M, E, T>(b[(j + 1) % E], used, r, j + 1);
-    }
-}
+// prefetch depth of the chain loops (block rows): a row's operands take 6E
+// registers per lane, which bounds the depth for the widest segments
+template <int E> constexpr int seg_prefetch() { return E <= 2 ? 2 : 1; }
 
 // entries (r, c0 .. c0+E-1) of a column-major M x M block (FP64)
 template <int M, int E>
@@ -134,12 +56,38 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
     T *S3 = S2 + M * RS;      // Zh by columns
     T *S5 = S3 + M * RS;      // A(g,g+1) by columns
     T *S4 = S5 + M * RS;      // (RHS) f' by columns; then t by columns
+    constexpr int PD = seg_prefetch<E>();
 
     const int64_t nb = a.nb;
     const int64_t part = pblock * PPW + grp;
     const Geo G = geometry<0>(nb, a.p, part);
-    T *Ef = (T *)a.E, *R = (T *)a.R, *Zs = (T *)a.Z, *Xs = (T *)a.X;
-    T *dump = (T *)a.dump + tid * E;
+    const int gc = t / M;   // segment column
+
+    // Block arrays and factors through raw buffers based one block row before
+    // the workgroup's first partition: every row a partition touches lies at
+    // or past the base (its left separator's couplings included), and rows
+    // past an array's end read zero, as a missing operand must.
+    const int64_t s0 = geometry<0>(nb, a.p, pblock * PPW).start;
+    const int64_t gb = s0 > 0 ? s0 - 1 : 0;
+    constexpr uint32_t BB = MM * 8, BT = MM * sizeof(T);
+    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
+    const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
+    const auto rDa = buf_rsrc(ADD ? a.Dadd + gb * MM : a.D, ADD ? nr * BB : 0);
+    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
+    const auto rU = buf_rsrc(a.Up + gb * MM, nr1 * BB);
+    const auto rE = buf_rsrc((T *)a.E + gb * MM, nr * BT);
+    const auto rR = buf_rsrc((T *)a.R + gb * MM, nr * BT);
+    const auto rZ = buf_rsrc((T *)a.Z + gb * MM, nr * BT);
+    const auto rX = buf_rsrc((T *)a.X + gb * MM, nr * BT);
+    const uint32_t rel = (uint32_t)(G.start - gb);          // partition start, relative
+    const uint32_t ent = (uint32_t)(r + c0 * M) * 8;        // entry (r, c0), column-major FP64
+    const uint32_t fen = (uint32_t)(r * M + c0) * sizeof(T);   // entry (r, c0), row-major factor
+    auto ld_blk = [&](double (&v)[E], __amdgpu_buffer_rsrc_t rs, uint32_t row) {
+        const uint32_t o = row * BB + ent;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = buf_ld(rs, o + (uint32_t)(e * M * 8));
+    };
+
     double *ydump = (double *)a.dump + 2048 + tid * E;
     const double *zero = a.zero;
     // right-hand-side columns of this lane's entries (clamped to column 0
@@ -158,10 +106,10 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
     for (int e = 0; e < E; ++e) { d[e] = z[e] = rr[e] = a1[e] = fp[e] = gl[e] = T(0); }
     if (G.valid) {
         double v[E];
-        ld_ent<M, E>(v, a.D + G.start * MM, r, c0);
+        ld_blk(v, rD, rel);
         if constexpr (ADD) {
             double w[E];
-            ld_ent<M, E>(w, a.Dadd + G.start * MM, r, c0);
+            ld_blk(w, rDa, rel);
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] += w[e];
         }
@@ -178,32 +126,36 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
     }
     if (G.hasL) {
         double v[E], w[E];
-        ld_ent<M, E>(v, a.Lo + (G.start - 1) * MM, r, c0);   // A(g_1, sL)
-        ld_ent<M, E>(w, a.Up + (G.start - 1) * MM, r, c0);   // A(sL, g_1)
+        ld_blk(v, rL, rel - 1);   // A(g_1, sL)
+        ld_blk(w, rU, rel - 1);   // A(sL, g_1)
 #pragma unroll
         for (int e = 0; e < E; ++e) { z[e] = (T)v[e]; rr[e] = (T)w[e]; }
     }
     unsigned long long bad = ~0ull;
 
     // Operands of block row g that do not depend on the chain -- A(g,g+1),
-    // A(g+1,g), D[g+1] and f[g+1] at the lane's entries -- loaded one block
-    // row ahead, from the zero block when they do not exist, and kept in FP64
-    // (the two addends of a sum apart) until the row that uses them.
+    // A(g+1,g), D[g+1] and f[g+1] at the lane's entries -- loaded PD block
+    // rows ahead and kept in FP64 (the two addends of a sum apart) until the
+    // row that uses them.  Rows past the partition's end are loaded too
+    // (never used); rows past the matrix read zero.
     struct Next {
         double up[E], lo[E], dn[E], da[E], fn[E], fa[E];
     };
-    auto load_next = [&](int64_t g, bool ok, Next &n) {
-        ld_ent<M, E>(n.up, ok ? a.Up + g * MM : zero, r, c0);
-        ld_ent<M, E>(n.lo, ok ? a.Lo + g * MM : zero, r, c0);
-        ld_ent<M, E>(n.dn, ok ? a.D + (g + 1) * MM : zero, r, c0);
+    auto load_next = [&](int k, Next &n) {
+        const uint32_t row = rel + (uint32_t)k;
+        ld_blk(n.up, rU, row);
+        ld_blk(n.lo, rL, row);
+        ld_blk(n.dn, rD, row + 1);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             n.da[e] = 0.0;
             n.fn[e] = 0.0;
             n.fa[e] = 0.0;
         }
-        if constexpr (ADD) ld_ent<M, E>(n.da, ok ? a.Dadd + (g + 1) * MM : zero, r, c0);
+        if constexpr (ADD) ld_blk(n.da, rDa, row + 1);
         if constexpr (RHS) {
+            const int64_t g = G.start + k;
+            const bool ok = k < G.len && g + 1 < nb;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 n.fn[e] = *((ok && act[e]) ? sv.F + (g + 1) * M + fo[e] : zero);
@@ -211,20 +163,22 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
             }
         }
     };
-    Next cur;
-    load_next(G.start, G.len > 0 && G.start + 1 < nb, cur);
+    Next buf[PD + 1];   // buf[0]: the operands of the row in use
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_next(d, buf[d]);
 
     for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
-        Next nxt;
-        load_next(g + 1, k + 1 < G.len && g + 2 < nb, nxt);
+        const uint32_t frow = (rel + (uint32_t)k) * BT;   // this block row's factors
+        load_next(k + PD, buf[PD]);
+        const Next &cur = buf[0];
 
         T b[E];
         int sigma = 0, pc[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) { b[e] = d[e]; pc[e] = 0; }
         bool sing = false;
-        seg_invert<M, E, T>(b, r, c0, S0, sigma, pc, sing);
+        seg_invert<M, E, T>(b, r, gc, S0, sigma, pc, sing);
         const unsigned long long code = status_code(a.level, g);
         bad = (sing && code < bad) ? code : bad;
 
@@ -257,10 +211,11 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
             }
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) Ef[g * MM + sigma * M + pc[e]] = b[e];
-        st_fac<E, T>(G.hasL ? R + g * MM + r * M + c0 : dump, rr);
-        st_fac<E, T>(Xs + g * MM + r * M + c0, x);
-        st_fac<E, T>(Zs + g * MM + r * M + c0, zh);
+        for (int e = 0; e < E; ++e)
+            buf_st(rE, frow + (uint32_t)(sigma * M + pc[e]) * (uint32_t)sizeof(T), b[e]);
+        buf_st_row<E, T>(rR, G.hasL ? frow + fen : kOffNone, rr);
+        buf_st_row<E, T>(rX, frow + fen, x);
+        buf_st_row<E, T>(rZ, frow + fen, zh);
         wave_sync();
         lds_put<E, T>(S0 + r * RS + c0, rr);          // R_k by rows
 #pragma unroll
@@ -289,7 +244,8 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
                 fp[e] = (T)(ADD ? cur.fn[e] + cur.fa[e] : cur.fn[e]) - dot<M, T>(lr, tc);
             }
         }
-        cur = nxt;
+#pragma unroll
+        for (int d = 0; d < PD; ++d) buf[d] = buf[d + 1];
         wave_sync();
     }
     if (bad != ~0ull) atomicMin(a.status, bad);
@@ -333,10 +289,29 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
     T *S2 = S1 + M * RS;      // A(g+1,g) by rows
     T *S3 = S2 + M * RS;      // Zh by columns
     T *S4 = S3 + M * RS;      // (RHS) f' by columns; then t by columns
+    constexpr int PD = seg_prefetch<E>();
 
     const int64_t part = pblock * PPW + grp;
     const Geo G = geometry<1>(a.nb, a.p, part);
-    T *Ef = (T *)a.E, *Zs = (T *)a.Z;
+    const int gc = t / M;   // segment column
+    // raw buffers based one block row before the workgroup's first partition
+    // (its left separator); rows past an array's end read zero
+    const int64_t nb = a.nb;
+    const int64_t gb = geometry<1>(nb, a.p, pblock * PPW).start - 1;
+    constexpr uint32_t BB = MM * 8, BT = MM * sizeof(T);
+    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
+    const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
+    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
+    const auto rE = buf_rsrc((T *)a.E + gb * MM, nr * BT);
+    const auto rZ = buf_rsrc((T *)a.Z + gb * MM, nr * BT);
+    const uint32_t rel = (uint32_t)(G.start - gb);
+    const uint32_t ent = (uint32_t)(r + c0 * M) * 8;
+    const uint32_t fen = (uint32_t)(r * M + c0) * sizeof(T);
+    auto ld_blk = [&](double (&v)[E], __amdgpu_buffer_rsrc_t rs, uint32_t row) {
+        const uint32_t o = row * BB + ent;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = buf_ld(rs, o + (uint32_t)(e * M * 8));
+    };
     double *ydump = (double *)a.dump + 2048 + tid * E;
     const double *zero = a.zero;
     bool act[E];
@@ -351,7 +326,7 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
     T z[E], fp[E];
     {
         double v[E];
-        ld_ent<M, E>(v, G.valid ? a.Lo + (G.start - 1) * MM : zero, r, c0);   // A(g_1, sL)
+        ld_blk(v, rL, rel - 1);   // A(g_1, sL) (read for invalid partitions too: unused)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             z[e] = (T)v[e];
@@ -359,30 +334,35 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
         }
     }
     unsigned long long bad = ~0ull;
-    // D[g], A(g+1,g) and f[g+1] at the lane's entries, one block row ahead
+    // D[g], A(g+1,g) and f[g+1] at the lane's entries, PD block rows ahead
     struct Next {
         double dc[E], lc[E], fc[E];
     };
-    auto load_next = [&](int64_t g, bool ok, Next &n) {
-        ld_ent<M, E>(n.dc, ok ? a.D + g * MM : zero, r, c0);
-        ld_ent<M, E>(n.lc, ok ? a.Lo + g * MM : zero, r, c0);
+    auto load_next = [&](int k, Next &n) {
+        const uint32_t row = rel + (uint32_t)k;
+        ld_blk(n.dc, rD, row);
+        ld_blk(n.lc, rL, row);
+        const int64_t g = G.start + k;
+        const bool ok = k < G.len;
 #pragma unroll
         for (int e = 0; e < E; ++e)
             n.fc[e] = RHS ? *((ok && act[e]) ? sv.F + (g + 1) * M + fo[e] : zero) : 0.0;
     };
-    Next cur;
-    load_next(G.start, G.len > 0, cur);
+    Next buf[PD + 1];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_next(d, buf[d]);
     for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
-        Next nxt;
-        load_next(g + 1, k + 1 < G.len, nxt);
+        const uint32_t frow = (rel + (uint32_t)k) * BT;
+        load_next(k + PD, buf[PD]);
+        const Next &cur = buf[0];
 
         T b[E], lo[E];
         int sigma = 0, pc[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) { b[e] = (T)cur.dc[e]; lo[e] = (T)cur.lc[e]; pc[e] = 0; }
         bool sing = false;
-        seg_invert<M, E, T>(b, r, c0, S0, sigma, pc, sing);
+        seg_invert<M, E, T>(b, r, gc, S0, sigma, pc, sing);
         const unsigned long long code = status_code(a.level, g);
         bad = (sing && code < bad) ? code : bad;
 
@@ -410,8 +390,9 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
             }
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) Ef[g * MM + sigma * M + pc[e]] = b[e];
-        st_fac<E, T>(Zs + g * MM + r * M + c0, zh);
+        for (int e = 0; e < E; ++e)
+            buf_st(rE, frow + (uint32_t)(sigma * M + pc[e]) * (uint32_t)sizeof(T), b[e]);
+        buf_st_row<E, T>(rZ, frow + fen, zh);
         wave_sync();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -432,7 +413,8 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
                 fp[e] = (T)cur.fc[e] - dot<M, T>(lr, tc);
             }
         }
-        cur = nxt;
+#pragma unroll
+        for (int d = 0; d < PD; ++d) buf[d] = buf[d + 1];
         wave_sync();
     }
     if (bad != ~0ull) atomicMin(a.status, bad);
@@ -496,6 +478,7 @@ hipError_t dispatch_ME(int M, int E, F &&f)
     if (M == 4 && E == 1) return f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
     if (M == 8 && E == 1) return f(integral_constant<int, 8>{}, integral_constant<int, 1>{});
     if (M == 8 && E == 2) return f(integral_constant<int, 8>{}, integral_constant<int, 2>{});
+    if (M == 8 && E == 4) return f(integral_constant<int, 8>{}, integral_constant<int, 4>{});
     if (M == 16 && E == 4) return f(integral_constant<int, 16>{}, integral_constant<int, 4>{});
     return hipErrorInvalidValue;
 }
@@ -505,7 +488,7 @@ hipError_t dispatch_ME(int M, int E, F &&f)
 bool seg_ok(int M, int E)
 {
     return (M == 1 && E == 1) || (M == 2 && E == 1) || (M == 4 && E == 1) || (M == 8 && E == 1) ||
-           (M == 8 && E == 2) || (M == 16 && E == 4);
+           (M == 8 && E == 2) || (M == 8 && E == 4) || (M == 16 && E == 4);
 }
 
 int seg_partitions_per_wg(int M, int E) { return WG / (M * M / E); }

@@ -163,6 +163,29 @@ __device__ __forceinline__ void bwd_body(const SolveArgs &a, int64_t pblock, int
 #pragma unroll
     for (int c = 0; c < KC; ++c) col[c] = (int64_t)(c0 + (c < kc ? c : kc - 1));
 
+    // Row i of Zh_g and X_g and row i of t_g, loaded PD block rows ahead of
+    // their use (the chain runs from the last block row up; k < 0 reads the
+    // zero block); the first rows are requested before the separators'
+    // solution, so the waits overlap.  A row costs 2M + KC registers per lane,
+    // which bounds the depth for the larger blocks.
+    constexpr int PD = M <= 8 ? 2 : (M <= 16 ? 1 : 0);
+    struct Row {
+        T zr[M], xr[M];
+        double t[KC];
+    };
+    const T *zt = (const T *)a.zero + i * M;
+    auto load_row = [&](int k, Row &w) {
+        const bool ok = k >= 0;
+        const int64_t g = G.start + (ok ? k : 0);
+        ld_fac<M, T>(w.zr, ok ? Zs + g * MM + i * M : zt);
+        if constexpr (KIND == 0) ld_fac<M, T>(w.xr, ok ? Xs + g * MM + i * M : zt);
+#pragma unroll
+        for (int c = 0; c < KC; ++c) w.t[c] = *(ok ? a.Y + g * M + i + col[c] * a.ldy : a.zero);
+    };
+    Row buf[PD + 1];   // buf[0]: the row in use
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_row(G.len - 1 - d, buf[d]);
+
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
         T xl = T(0), xr = T(0);
@@ -182,19 +205,16 @@ __device__ __forceinline__ void bwd_body(const SolveArgs &a, int64_t pblock, int
     wave_sync();
     for (int k = G.len - 1; k >= 0; --k) {
         const int64_t g = G.start + k;
-        T zr[M], xrw[M], t[KC];
-        ld_fac<M, T>(zr, Zs + g * MM + i * M);
-        if constexpr (KIND == 0) ld_fac<M, T>(xrw, Xs + g * MM + i * M);
-#pragma unroll
-        for (int c = 0; c < KC; ++c) t[c] = (T)a.Y[g * M + i + col[c] * a.ldy];
+        load_row(k - PD, buf[PD]);
+        const Row &cur = buf[0];
         T xk[KC];
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
-            T s = t[c];
+            T s = (T)cur.t[c];
 #pragma unroll
             for (int l = 0; l < M; ++l) {
-                s = fma(-zr[l], SL[l + c * CS], s);
-                if constexpr (KIND == 0) s = fma(-xrw[l], SV[l + c * CS], s);
+                s = fma(-cur.zr[l], SL[l + c * CS], s);
+                if constexpr (KIND == 0) s = fma(-cur.xr[l], SV[l + c * CS], s);
             }
             xk[c] = s;
         }
@@ -206,6 +226,8 @@ __device__ __forceinline__ void bwd_body(const SolveArgs &a, int64_t pblock, int
             if constexpr (KIND == 0) SV[i + c * CS] = xk[c];
         }
         if constexpr (KIND == 0) wave_sync();
+#pragma unroll
+        for (int d = 0; d < PD; ++d) buf[d] = buf[d + 1];
     }
 }
 

@@ -73,6 +73,13 @@ hipError_t launch_babd_factor(int M, bool f32, const LevelArgs &a, hipStream_t s
 // With sv != NULL (1 <= sv->nrhs <= M) the launch also runs the forward
 // sweep of launch_*_fwd for those right-hand sides (factor-and-solve).
 bool seg_ok(int M, int E);
+// matrix-core factor kernel (finest level, FP64 block tridiagonal, M = 8):
+// two partitions per workgroup; the batched form serves work items (table
+// entry, partition block) like the other batched factor launches
+bool mfma_ok(int kind, int M, bool f32, bool add);
+int mfma_partitions_per_wg();
+hipError_t launch_mfma_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
+hipError_t launch_mfma_factor_batch(const LevelArgs *tab, const int4 *work, int nwg, hipStream_t s);
 int seg_partitions_per_wg(int M, int E);
 hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &a,
                              const SolveArgs *sv, hipStream_t s);

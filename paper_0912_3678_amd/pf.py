@@ -17,7 +17,7 @@ PF_BTRI, PF_BABD = 0, 1
 PF_FP64, PF_FP32_IR = 0, 1
 PF_OK, PF_ESINGULAR, PF_ENOCONV, PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED = 0, 1, 2, 3, 4, 5
 PF_FLAG_ETA = 1
-PF_FLAG_MAP_ROWS, PF_FLAG_MAP_TILES, PF_FLAG_AUTOTUNE = 2, 4, 8
+PF_FLAG_MAP_ROWS, PF_FLAG_MAP_TILES, PF_FLAG_AUTOTUNE, PF_FLAG_MAP_SEGMENTS = 2, 4, 8, 16
 
 EXPORTED = [
     "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",

@@ -65,7 +65,7 @@ def test_block_size_32(kind, nb):
     G.check(s, x, tag=f"{kind} m=32 nb={nb} levels={levels}")
 
 
-@pytest.mark.parametrize("flag", ["rows", "seg", "wide"])
+@pytest.mark.parametrize("flag", ["rows", "default", "wide", "segments"])
 @pytest.mark.parametrize("kind,m,nb", [("btri", 2, 301), ("btri", 4, 1001), ("btri", 8, 4099),
                                        ("btri", 3, 77), ("btri", 8, 7), ("babd", 2, 40),
                                        ("babd", 4, 300), ("babd", 8, 1001), ("babd", 6, 31),
@@ -73,8 +73,9 @@ def test_block_size_32(kind, nb):
                                        ("btri", 1, 999)])
 def test_lane_mappings(kind, m, nb, flag):
     """Every factor lane mapping gives the oracle's solution: rows on every
-    level, the default segments, and wider segments at level 0 (m = 8: two
-    entries per lane)."""
+    level; the planner's default (segments, and the matrix-core kernel at the
+    finest level of FP64 block tridiagonal m = 8 matrices); wider segments at
+    level 0 (m = 8: two entries per lane); segments only."""
     seed = 500 + m * 13 + nb
     s = wl.random_btri(nb, m, seed=seed) if kind == "btri" else wl.random_babd(nb, m, seed=seed)
     M = 1 << (m - 1).bit_length()
@@ -82,12 +83,52 @@ def test_lane_mappings(kind, m, nb, flag):
         opts = pf.make_opts(flags=pf.PF_FLAG_MAP_ROWS)
     elif flag == "wide":
         opts = pf.make_opts(lane_entries={8: 2, 16: 4}.get(M, 1))
+    elif flag == "segments":
+        opts = pf.make_opts(flags=pf.PF_FLAG_MAP_SEGMENTS)
     else:
         opts = pf.make_opts()
     _say(kind, "m", m, "nb", nb, flag)
     x, info, levels = G.gpu_solve(s, opts)
     assert info.status == 0
     G.check(s, x, tag=f"{kind} m={m} nb={nb} {flag} levels={levels}")
+
+
+@pytest.mark.parametrize("nb,p", [(2, 1), (3, 1), (5, 2), (9, 3), (100, 7), (301, 0),
+                                  (4099, 33), (65, 32), (1000, 499)])
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_matrix_core_partitions(nb, p, nrhs):
+    """The matrix-core factor kernel (m = 8, FP64 block tridiagonal, finest
+    level) gives the oracle's solution and agrees with the segment mapping
+    for every pairing of partitions in a wave: an odd count (the last wave's
+    second partition shadows its first), lengths that differ by one, single
+    partitions and one-block partitions; with the fused forward sweep for up
+    to 8 right-hand sides."""
+    import torch
+    seed = 1300 + nb + 7 * p + nrhs
+    s = wl.random_btri(nb, 8, seed=seed)
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((nb * 8, nrhs))
+    A, keep = G.to_device(s)
+    xs = {}
+    for name, flags in (("mfma", 0), ("segments", pf.PF_FLAG_MAP_SEGMENTS)):
+        F = pf.pf_factor(A, pf.make_opts(partitions=p, flags=flags))
+        try:
+            fd = G.rhs_to_device(f)
+            x = torch.full_like(fd, np.nan)
+            _say("nb", nb, "p", p, "nrhs", nrhs, name)
+            info = pf.pf_factor_solve(F, fd, x)
+            assert info.status == 0
+            xs[name] = x.cpu().numpy().T
+            G.check(s, xs[name], f=f, tag=f"{name} nb={nb} p={p} k={nrhs}")
+            # the factors left behind serve pf_solve
+            x2 = torch.full_like(fd, np.nan)
+            assert pf.pf_solve(F, fd, x2).status == 0
+            G.check(s, x2.cpu().numpy().T, f=f, tag=f"{name} solve nb={nb} p={p} k={nrhs}")
+        finally:
+            pf.pf_destroy(F)
+    scale = np.abs(xs["segments"]).max()
+    assert np.abs(xs["mfma"] - xs["segments"]).max() <= 1e-11 * scale
+    del keep
 
 
 @pytest.mark.parametrize("kind,m,nb,nrhs,prec", [
