@@ -93,8 +93,8 @@ def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
     return level_nb * (mm * w + 2 * m * 8 * nrhs)           # read Z, t; write x
 
 
-KERNEL_SOURCES = ("kernels_common.h", "kernels_gj.h", "kernels_seg.hip", "kernels_mfma.hip",
-                  "kernels_rows.hip", "kernels_solve.hip")
+KERNEL_SOURCES = ("kernels_common.h", "kernels_gj.h", "kernels_seg.h", "kernels_seg.hip",
+                  "kernels_mfma.hip", "kernels_rows.hip", "kernels_solve.h", "kernels_solve.hip")
 
 
 def source_hash():
