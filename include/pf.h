@@ -71,11 +71,13 @@ enum {
     PF_FLAG_ETA = 1,       /* pf_solve in FP64 also computes eta (one residual pass)  */
     PF_FLAG_MAP_ROWS = 2,  /* factor every level with the row lane mapping (M lanes per
                               partition, lane i holds row i of each block) instead of
-                              the default segment mapping (M*M/E lanes per partition,
-                              E block entries per lane: E = 1 for m <= 8 (2 at the
-                              finest level for m = 8), 4 for m = 16; m = 32 always
-                              uses rows).  The mappings differ
-                              only in rounding.                                      */
+                              the defaults: the segment mapping (M*M/E lanes per
+                              partition, E block entries per lane: E = 1 for m <= 8,
+                              4 for m = 16) with matrix-core products at the finest
+                              level of FP64 PF_BTRI matrices with m = 8, and for FP64
+                              PF_BTRI matrices with m = 32 matrix-core products on
+                              every level (other m = 32 levels use rows).  The
+                              mappings differ only in rounding.                      */
     PF_FLAG_MAP_TILES = 4, /* reserved (the segment mapping is the default)         */
     PF_FLAG_AUTOTUNE = 8,  /* pf_factor / pf_batch_create take block_rows,
                               coarse_rows, lane_entries and the mapping from the

@@ -10,24 +10,29 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_rows.hip", "kernels_seg.hip", "kernels_mfma.hip", "kernels_solve.hip", "kernels_util.hip", "api.cpp", "tune.cpp", "server.cpp"]
+SOURCES = ["kernels_rows.hip", "kernels_seg.hip", "kernels_mfma.hip", "kernels_mfma32.hip", "kernels_solve.hip", "kernels_util.hip", "api.cpp", "tune.cpp", "server.cpp"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # matrix-core results straight into VGPRs (no copies out of AGPRs)
-    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
 
+# m = 8 matrix-core kernel: results straight into VGPRs (its operands are
+# per-lane selects of them); the m = 32 kernel keeps its accumulators in the
+# matrix cores' own registers, which it needs for room
+VGPR_FORM = {"kernels_mfma.hip"}
+
+
 def _compile(src: str) -> str:
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"] if src in VGPR_FORM else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-O2", "-fPIC", "-std=c++17", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}",
                "-c", os.path.join(CSRC, src), "-o", obj]

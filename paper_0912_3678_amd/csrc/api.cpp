@@ -22,7 +22,8 @@ struct Level {
     int64_t nb = 0, p = 1;
     bool f32 = false;
     int seg = 0;          // factor lane mapping: E entries per lane (segments), 0 = rows,
-                          // kMapMfma = matrix-core products (finest level, m = 8)
+                          // kMapMfma / kMapMfma32 = matrix-core products (m = 8 finest
+                          // level / m = 32)
     const double *D = nullptr, *Dadd = nullptr, *Lo = nullptr, *Up = nullptr, *C = nullptr;
     void *E = nullptr, *R = nullptr, *Z = nullptr, *X = nullptr;
     double *nD = nullptr, *nDadd = nullptr, *nLo = nullptr, *nUp = nullptr, *nC = nullptr;
@@ -125,10 +126,14 @@ constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chai
 // tridiagonal matrix with m = 8 runs its block products on the matrix cores
 // (kMapMfma), unless a mapping is asked for.
 constexpr int kMapMfma = -1;
+// every level of an FP64 block tridiagonal matrix with m = 32: matrix-core
+// products, one partition per wave (kernels_mfma32.hip)
+constexpr int kMapMfma32 = -2;
 
 int seg_width(int M, int level, int kind, bool f32, const pf_opts &o)
 {
     if (o.flags & PF_FLAG_MAP_ROWS) return 0;
+    if (M == 32 && kind == PF_BTRI && !f32) return kMapMfma32;
     if (level == 0 && o.lane_entries > 0) return seg_ok(M, o.lane_entries) ? o.lane_entries : 0;
     if (level == 0 && !(o.flags & PF_FLAG_MAP_SEGMENTS) && mfma_ok(kind, M, f32, false)) return kMapMfma;
     if (level == 0 && M == 8) return 2;   // 0.153 vs 0.156 ms per step with one entry
@@ -385,6 +390,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         const LevelArgs a = level_args(F, l);
         e = prof_launch(F, true, 0, (int)l, s, [&] {
             if (L.seg == kMapMfma) return launch_mfma_factor(a, nullptr, s);
+            if (L.seg == kMapMfma32) return launch_mfma32_factor(a, s);
             if (L.seg) return launch_seg_factor(L.kind, F->M, L.seg, L.f32, a, nullptr, s);
             return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
                                        : launch_babd_factor(F->M, L.f32, a, s);
@@ -491,7 +497,7 @@ bool fused_ok(const pf_factor_s *F, int nrhs)
 {
     if (nrhs < 1 || nrhs > F->M) return false;
     for (const Level &L : F->lv)
-        if (!L.seg) return false;
+        if (L.seg == 0 || L.seg == kMapMfma32) return false;
     return true;
 }
 
@@ -1200,9 +1206,10 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
             BatchLaunch bl{0, std::get<0>(kv.first), std::get<1>(kv.first), 1,
                            std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0,
                            std::get<4>(kv.first), work.size(), 0};
-            const int gpw = bl.seg == kMapMfma ? mfma_partitions_per_wg()
-                            : bl.seg           ? seg_partitions_per_wg(bl.M, bl.seg)
-                                               : groups_per_wg(bl.M);
+            const int gpw = bl.seg == kMapMfma   ? mfma_partitions_per_wg()
+                            : bl.seg == kMapMfma32 ? 1
+                            : bl.seg             ? seg_partitions_per_wg(bl.M, bl.seg)
+                                                 : groups_per_wg(bl.M);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(level_args(B->all[i], l));
@@ -1272,6 +1279,8 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
     for (const auto &bl : B->flaunch)
         if (e == hipSuccess)
             e = bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+                : bl.seg == kMapMfma32
+                    ? launch_mfma32_factor_batch(bl.add, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
                                                    B->d_lwork + bl.work, bl.nwg, s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,

@@ -1,0 +1,274 @@
+// Partition-method factor kernel for 32 x 32 blocks with the block products
+// on the matrix cores (gfx950, FP64, block tridiagonal, every level).
+//
+// One partition per wave.  The pivot blocks are inverted by the Gauss-Jordan
+// exchange steps of kernels_gj.h with sixteen entries per lane (lane (r, g)
+// holds row r, columns 16g .. 16g+15).  The six block products of a chain row
+// -- X = E A(g,g+1), Zh = E Z', D'_{k+1} = D[g+1] - A(g+1,g) X,
+// Z'_{k+1} = -A(g+1,g) Zh and the spike-row updates -- run on the matrix
+// cores as 2 x 2 tiles of 16 x 16, each tile product four
+// v_mfma_f64_16x16x4f64 (K = 4 each).
+//
+// "Quad" layout: of a 32 x 32 matrix Y, lane l (n = l & 15, m = l >> 4) holds
+// Y(16I + m + 4q, 16J + n) for tiles I, J in {0, 1} and q = 0..3 -- the
+// result layout of the instruction for each tile.  Instruction h of tile
+// product (I, K) x (K, J) takes the A operand A(16I + n, 16K + 4h + m), entry
+// (K, I, h) of the quad of A^T, and the B operand B(16K + 4h + m, 16J + n),
+// entry (K, J, h) of the quad of B; so a product's result is the next
+// product's right operand as it stands, and the left operand of a transposed
+// product, and the spike rows are carried transposed (R^T, alpha_1^T).  The
+// inverse enters through LDS (its transpose's quad read from the logical rows
+// the exchange steps leave); D' goes back to the inversion layout through
+// LDS.  The operands of a row are requested at the top of the row: the
+// inversion covers their latency.  Outputs and recurrences are those of the
+// other factor kernels.  The accumulators live in the matrix cores' own
+// registers (this file is compiled without the VGPR form).
+#include "kernels_gj.h"
+
+namespace pf {
+namespace {
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+constexpr int kM = 32, kRS = kM + 2;   // padded LDS row stride (doubles)
+
+struct Quad {
+    dv4 t[2][2];   // [I][J], entry q = row m + 4q of the tile, column n
+};
+
+__device__ __forceinline__ Quad qzero()
+{
+    Quad z;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) z.t[I][J] = dv4{0.0, 0.0, 0.0, 0.0};
+    return z;
+}
+__device__ __forceinline__ Quad qneg(const Quad &a)
+{
+    Quad z;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) z.t[I][J] = -a.t[I][J];
+    return z;
+}
+
+// C + A B; aT = quad of A^T, b = quad of B
+__device__ __forceinline__ Quad mm32(const Quad &aT, const Quad &b, Quad c)
+{
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    c.t[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT.t[K][I][h], b.t[K][J][h],
+                                                                     c.t[I][J], 0, 0, 0);
+    return c;
+}
+
+// quad of a column-major FP64 block at byte offset base of resource r
+// (tr: the quad of its transpose)
+template <bool TR>
+__device__ __forceinline__ Quad qload(__amdgpu_buffer_rsrc_t rs, uint32_t base, int m, int n)
+{
+    Quad y;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * I + m + 4 * q, col = 16 * J + n;
+                const int e = TR ? col + kM * row : row + kM * col;
+                y.t[I][J][q] = buf_ld(rs, base + (uint32_t)e * 8);
+            }
+    return y;
+}
+// quad into a row-major factor block (tr: store the transpose's entries)
+template <bool TR>
+__device__ __forceinline__ void qstore(__amdgpu_buffer_rsrc_t rs, uint32_t base, bool keep,
+                                       const Quad &y, int m, int n)
+{
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * I + m + 4 * q, col = 16 * J + n;
+                const int e = TR ? col * kM + row : row * kM + col;
+                buf_st(rs, keep ? base + (uint32_t)e * 8 : kOffNone, y.t[I][J][q]);
+            }
+}
+// quad into a column-major FP64 block of global memory
+template <bool TR>
+__device__ __forceinline__ void qstore_g(double *p, const Quad &y, int m, int n)
+{
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * I + m + 4 * q, col = 16 * J + n;
+                p[TR ? col + kM * row : row + kM * col] = y.t[I][J][q];
+            }
+}
+
+template <bool ADD>
+__device__ __forceinline__ void btri_mfma32_body(const LevelArgs &a, int64_t part, int lane,
+                                                 double *lds)
+{
+    constexpr int M = kM, E = 16;
+    constexpr size_t MM = (size_t)M * M;
+    constexpr uint32_t BB = MM * 8;
+    // inversion role: row r, columns 16g ..; matrix-core role: (m, n)
+    const int r = lane % M, gc = lane / M, c0 = gc * E;
+    const int m = lane >> 4, n = lane & 15;
+    double *S0 = lds;              // tableau
+    double *SE = S0 + M * kRS;     // E by logical rows; then D' handed over
+
+    const int64_t nb = a.nb;
+    const Geo G = geometry<0>(nb, a.p, part);
+    const int64_t gb = G.start > 0 ? G.start - 1 : 0;
+    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
+    const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
+    const auto rDa = buf_rsrc(ADD ? a.Dadd + gb * MM : a.D, ADD ? nr * BB : 0);
+    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
+    const auto rU = buf_rsrc(a.Up + gb * MM, nr1 * BB);
+    const auto rE = buf_rsrc((double *)a.E + gb * MM, nr * BB);
+    const auto rR = buf_rsrc((double *)a.R + gb * MM, nr * BB);
+    const auto rZ = buf_rsrc((double *)a.Z + gb * MM, nr * BB);
+    const auto rX = buf_rsrc((double *)a.X + gb * MM, nr * BB);
+    const uint32_t rel = (uint32_t)(G.start - gb);
+
+    // D'_1 in the inversion layout
+    double d[E];
+    {
+        const uint32_t o = rel * BB + (uint32_t)(r + M * c0) * 8;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            d[e] = buf_ld(rD, o + (uint32_t)(e * M * 8));
+            if constexpr (ADD) d[e] += buf_ld(rDa, o + (uint32_t)(e * M * 8));
+        }
+    }
+    // Z'_1 = A(g_1, sL), R_1^T = A(sL, g_1)^T, alpha_1^T
+    Quad z = qzero(), rT = qzero(), a1 = qzero(), dq = qzero();
+    if (G.hasL) {
+        z = qload<false>(rL, (rel - 1) * BB, m, n);
+        rT = qload<true>(rU, (rel - 1) * BB, m, n);
+    }
+    unsigned long long bad = ~0ull;
+
+    for (int k = 0; k < G.len; ++k) {
+        const uint32_t row = rel + (uint32_t)k;
+        // this row's operands, requested before the inversion
+        const Quad up = qload<false>(rU, row * BB, m, n);     // A(g,g+1)
+        const Quad loT = qload<true>(rL, row * BB, m, n);     // A(g+1,g)^T
+        Quad dn = qload<false>(rD, (row + 1) * BB, m, n);     // D[g+1]
+        if constexpr (ADD) {
+            const Quad da = qload<false>(rDa, (row + 1) * BB, m, n);
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+#pragma unroll
+                for (int J = 0; J < 2; ++J) dn.t[I][J] += da.t[I][J];
+        }
+
+        // E_k = D'_k^{-1}
+        int sigma = 0, pc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) pc[e] = 0;
+        bool sing = false;
+        seg_invert<M, E, double>(d, r, gc, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, G.start + k);
+        bad = (sing && code < bad) ? code : bad;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            SE[sigma * kRS + pc[e]] = d[e];
+            buf_st(rE, row * BB + (uint32_t)(sigma * M + pc[e]) * 8, d[e]);
+        }
+        wave_sync();
+        Quad eT;   // quad of E^T: E(16I' + n, 16K' + m + 4q) at tile [K'][I']
+#pragma unroll
+        for (int K = 0; K < 2; ++K)
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) eT.t[K][I][q] = SE[(16 * I + n) * kRS + 16 * K + m + 4 * q];
+
+        const Quad x = mm32(eT, up, qzero());    // X_k = E_k A(g,g+1)
+        const Quad zh = mm32(eT, z, qzero());    // Zh_k = E_k Z'_k
+        qstore<false>(rX, row * BB, true, x, m, n);
+        qstore<false>(rZ, row * BB, true, zh, m, n);
+        qstore<true>(rR, row * BB, G.hasL, rT, m, n);   // R_k (row-major) from R_k^T
+        const Quad nlo = qneg(loT);
+        dq = mm32(nlo, x, dn);                   // D'_{k+1} = D[g+1] - A(g+1,g) X_k
+        z = mm32(nlo, zh, qzero());              // Z'_{k+1} = -A(g+1,g) Zh_k
+        a1 = mm32(qneg(zh), rT, a1);             // alpha_1^T -= Zh_k^T R_k^T
+        rT = mm32(qneg(x), rT, qzero());         // R_{k+1}^T = -X_k^T R_k^T
+
+        // D'_{k+1} to the inversion layout
+        wave_sync();
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+            for (int J = 0; J < 2; ++J)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) SE[(16 * I + m + 4 * q) * kRS + 16 * J + n] = dq.t[I][J][q];
+        wave_sync();
+        lds_row<E, double>(d, SE + r * kRS + c0);
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+    if (G.hasR) {
+        qstore_g<false>(a.nD + part * MM, dq, m, n);                      // D[sR] + alpha_2
+        if (G.hasL) qstore_g<false>(a.nLo + (part - 1) * MM, z, m, n);    // beta
+    }
+    if (G.hasL) {
+        qstore_g<true>(a.nDadd + (part - 1) * MM, a1, m, n);              // alpha_1
+        if (G.hasR) qstore_g<true>(a.nUp + (part - 1) * MM, rT, m, n);    // gamma
+    }
+}
+
+template <bool ADD>
+__global__ __launch_bounds__(WG) void k_btri_mfma32(LevelArgs a)
+{
+    __shared__ __align__(16) double lds[2 * kM * kRS];
+    btri_mfma32_body<ADD>(a, blockIdx.x, threadIdx.x, lds);
+}
+// batched: workgroup w serves table entry work[w].x, partition work[w].y
+template <bool ADD>
+__global__ __launch_bounds__(WG) void kb_btri_mfma32(const LevelArgs *tab, const int4 *work)
+{
+    __shared__ __align__(16) double lds[2 * kM * kRS];
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    btri_mfma32_body<ADD>(a, w.y, threadIdx.x, lds);
+}
+
+}  // namespace
+
+hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s)
+{
+    if (a.p < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)a.p);
+    if (a.Dadd) launch_k(k_btri_mfma32<true>, grid, dim3(WG), s, a);
+    else launch_k(k_btri_mfma32<false>, grid, dim3(WG), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
+                                      hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    if (add) launch_k(kb_btri_mfma32<true>, dim3(nwg), dim3(WG), s, tab, work);
+    else launch_k(kb_btri_mfma32<false>, dim3(nwg), dim3(WG), s, tab, work);
+    return hipGetLastError();
+}
+
+}  // namespace pf

@@ -80,6 +80,11 @@ bool mfma_ok(int kind, int M, bool f32, bool add);
 int mfma_partitions_per_wg();
 hipError_t launch_mfma_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
 hipError_t launch_mfma_factor_batch(const LevelArgs *tab, const int4 *work, int nwg, hipStream_t s);
+// matrix-core factor kernel for FP64 block tridiagonal levels with M = 32 (any
+// level; one partition per workgroup)
+hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s);
+hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
+                                      hipStream_t s);
 int seg_partitions_per_wg(int M, int E);
 hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &a,
                              const SolveArgs *sv, hipStream_t s);

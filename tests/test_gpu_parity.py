@@ -131,6 +131,38 @@ def test_matrix_core_partitions(nb, p, nrhs):
     del keep
 
 
+@pytest.mark.parametrize("nb,p", [(2, 1), (3, 1), (9, 4), (100, 0), (1001, 0), (4099, 0),
+                                  (600, 299), (257, 5)])
+@pytest.mark.parametrize("m", [32, 27])
+def test_matrix_core_32(nb, p, m):
+    """The m = 32 matrix-core factor kernel (FP64 block tridiagonal, every
+    level, including the reduced levels whose diagonal is a sum of two
+    arrays) gives the oracle's solution and agrees with the row mapping;
+    padded block sizes (m = 27) included."""
+    import torch
+    seed = 1500 + nb + 3 * p + m
+    s = wl.random_btri(nb, m, seed=seed)
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((nb * m, 3))
+    A, keep = G.to_device(s)
+    xs = {}
+    for name, flags in (("mfma", 0), ("rows", pf.PF_FLAG_MAP_ROWS)):
+        F = pf.pf_factor(A, pf.make_opts(partitions=p, flags=flags))
+        try:
+            fd = G.rhs_to_device(f)
+            x = torch.full_like(fd, np.nan)
+            _say("m", m, "nb", nb, "p", p, name)
+            info = pf.pf_solve(F, fd, x)
+            assert info.status == 0
+            xs[name] = x.cpu().numpy().T
+            G.check(s, xs[name], f=f, tag=f"{name} m={m} nb={nb} p={p}")
+        finally:
+            pf.pf_destroy(F)
+    scale = np.abs(xs["rows"]).max()
+    assert np.abs(xs["mfma"] - xs["rows"]).max() <= 1e-11 * scale
+    del keep
+
+
 @pytest.mark.parametrize("kind,m,nb,nrhs,prec", [
     ("btri", 8, 4099, 1, "fp64"), ("btri", 8, 1001, 3, "fp64"), ("btri", 8, 300, 8, "fp64"),
     ("btri", 8, 300, 9, "fp64"), ("btri", 4, 2049, 1, "fp64"), ("btri", 3, 700, 2, "fp64"),
