@@ -1246,13 +1246,13 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
             if (l >= F->lv.size() || B->nrhs[i] == 0) continue;
             const Level &L = F->lv[l];
             const int add = (phase == 1 && L.kind == PF_BTRI && args[i][l].Fadd) ? 1 : 0;
-            groups[{L.kind, F->M, L.f32 ? 1 : 0, add, rhs_chunk(B->nrhs[i])}].push_back(i);
+            groups[{L.kind, F->M, L.f32 ? 1 : 0, add, solve_cols(F->M, L.f32, B->nrhs[i])}].push_back(i);
         }
         for (auto &kv : groups) {
             BatchLaunch bl{phase, std::get<0>(kv.first), std::get<1>(kv.first),
                            std::get<4>(kv.first), std::get<2>(kv.first) != 0,
                            std::get<3>(kv.first) != 0, 0, work.size(), 0};
-            const int gpw = groups_per_wg(bl.M);
+            const int gpw = solve_groups_per_wg(bl.M, bl.f32);
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(args[i][l]);

@@ -251,6 +251,206 @@ __global__ __launch_bounds__(WG) void kb_btri_mfma32(const LevelArgs *tab, const
     btri_mfma32_body<ADD>(a, w.y, threadIdx.x, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Forward sweep and back substitution for M = 32 and FP64 factors (either
+// factor kernel's row-major E, X, Zh, R), the right-hand sides in column
+// tiles of 16: a tile's 32 x 16 block of one block row sits in the quad
+// layout (lane (m, n): rows 16I + m + 4q of column n).  Every block product
+// is a chain of v_mfma_f64_16x16x4f64 whose left operand is a factor block's
+// transpose quad, loaded straight from memory, so the factors of a block row
+// are read once per CT tiles (the row kernels read them once per four
+// columns).  KIND: 0 block tridiagonal, 1 bidiagonal plus corner.
+struct Col {
+    dv4 t[2];   // [I], entry q = row 16I + m + 4q, column n of the tile
+};
+
+__device__ __forceinline__ Col czero()
+{
+    Col c;
+    c.t[0] = dv4{0.0, 0.0, 0.0, 0.0};
+    c.t[1] = c.t[0];
+    return c;
+}
+// C + A B for one tile; aT = quad of A^T
+__device__ __forceinline__ Col mmc(const Quad &aT, const Col &b, Col c)
+{
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int K = 0; K < 2; ++K)
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                c.t[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT.t[K][I][h], b.t[K][h], c.t[I], 0, 0, 0);
+    return c;
+}
+// tile of a column-major array (p: row 0 of the block row, column n of the
+// tile; zero when the column does not exist)
+__device__ __forceinline__ Col cload(const double *p, bool act, int m)
+{
+    Col c;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c.t[I][q] = act ? p[16 * I + m + 4 * q] : 0.0;
+    return c;
+}
+__device__ __forceinline__ void cstore(double *p, bool act, const Col &c, int m)
+{
+    if (!act) return;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) p[16 * I + m + 4 * q] = c.t[I][q];
+}
+__device__ __forceinline__ Col cadd(Col a, const Col &b)
+{
+    a.t[0] += b.t[0];
+    a.t[1] += b.t[1];
+    return a;
+}
+
+template <int KIND, int CT, bool ADD>
+__device__ __forceinline__ void fwd32_body(const SolveArgs &a, int64_t part, int cg, int lane)
+{
+    constexpr int M = kM;
+    constexpr size_t MM = (size_t)M * M;
+    constexpr uint32_t BB = MM * 8;
+    const int m = lane >> 4, n = lane & 15;
+    const int64_t nb = a.nb;
+    const Geo G = geometry<KIND>(nb, a.p, part);
+    const int64_t gb = G.start > 0 ? G.start - 1 : 0;
+    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
+    const auto rE = buf_rsrc((const double *)a.E + gb * MM, nr * BB);
+    const auto rR = buf_rsrc(KIND == 0 ? (const double *)a.R + gb * MM : (const double *)a.E, KIND == 0 ? nr * BB : 0);
+    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
+    const uint32_t rel = (uint32_t)(G.start - gb);
+    bool act[CT];
+    int64_t cf[CT], cy[CT], cn[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        const int c = (cg * CT + j) * 16 + n;
+        act[j] = c < a.nrhs;
+        cf[j] = (int64_t)(act[j] ? c : 0) * a.ldf;
+        cy[j] = (int64_t)(act[j] ? c : 0) * a.ldy;
+        cn[j] = (int64_t)(act[j] ? c : 0) * a.ldn;
+    }
+    Col fp[CT], gl[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        fp[j] = cload(a.F + G.start * M + cf[j], act[j] && G.valid, m);
+        if constexpr (ADD) fp[j] = cadd(fp[j], cload(a.Fadd + G.start * M + cf[j], act[j] && G.valid, m));
+        gl[j] = czero();
+    }
+    for (int k = 0; k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        const uint32_t row = rel + (uint32_t)k;
+        const Quad eT = qload<false>(rE, row * BB, m, n);     // E_g^T (E row-major)
+        const Quad nlo = qneg(qload<true>(rL, row * BB, m, n));   // -A(g+1,g)^T
+        const Quad nrt = (KIND == 0 && G.hasL) ? qneg(qload<false>(rR, row * BB, m, n)) : qzero();
+        const bool nx = g + 1 < nb;
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            Col fn = cload(a.F + (g + 1) * M + cf[j], act[j] && nx, m);
+            if constexpr (ADD) fn = cadd(fn, cload(a.Fadd + (g + 1) * M + cf[j], act[j] && nx, m));
+            const Col t = mmc(eT, fp[j], czero());                   // t_k = E_k f'_k
+            cstore(a.Y + g * M + cy[j], act[j], t, m);
+            fp[j] = mmc(nlo, t, fn);                                 // f'_{k+1} = f[g+1] - A(g+1,g) t_k
+            if constexpr (KIND == 0) gl[j] = mmc(nrt, t, gl[j]);     // g_sL -= R_k t_k
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        if (KIND == 0) {
+            if (G.hasR) cstore(a.nF + part * M + cn[j], act[j], fp[j], m);
+            if (G.hasL) cstore(a.nFadd + (part - 1) * M + cn[j], act[j], gl[j], m);
+        } else if (G.valid) {
+            cstore(a.nF + (part + 1) * M + cn[j], act[j], fp[j], m);
+            if (part == 0) cstore(a.nF + cn[j], act[j], cload(a.F + cf[j], act[j], m), m);
+        }
+    }
+}
+
+template <int KIND, int CT>
+__device__ __forceinline__ void bwd32_body(const SolveArgs &a, int64_t part, int cg, int lane)
+{
+    constexpr int M = kM;
+    constexpr size_t MM = (size_t)M * M;
+    constexpr uint32_t BB = MM * 8;
+    const int m = lane >> 4, n = lane & 15;
+    const int64_t nb = a.nb;
+    const Geo G = geometry<KIND>(nb, a.p, part);
+    const int64_t gb = G.start > 0 ? G.start - 1 : 0;
+    const uint64_t nr = (uint64_t)(nb - gb);
+    const auto rZ = buf_rsrc((const double *)a.Z + gb * MM, nr * BB);
+    const auto rX = buf_rsrc(KIND == 0 ? (const double *)a.X + gb * MM : (const double *)a.Z, KIND == 0 ? nr * BB : 0);
+    const uint32_t rel = (uint32_t)(G.start - gb);
+    const int64_t sR = G.start + G.len;
+    const int64_t jl = (KIND == 0) ? part - 1 : part;
+    const int64_t jr = (KIND == 0) ? part : part + 1;
+    bool act[CT];
+    int64_t cy[CT], cn[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        const int c = (cg * CT + j) * 16 + n;
+        act[j] = c < a.nrhs;
+        cy[j] = (int64_t)(act[j] ? c : 0) * a.ldy;
+        cn[j] = (int64_t)(act[j] ? c : 0) * a.ldn;
+    }
+    Col xl[CT], xn[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        xl[j] = cload(a.Xsep + jl * M + cn[j], act[j] && G.hasL, m);
+        xn[j] = cload(a.Xsep + jr * M + cn[j], act[j] && G.hasR, m);
+        if (G.hasR) cstore(a.Y + sR * M + cy[j], act[j], xn[j], m);
+        if (KIND == 1 && G.valid && part == 0) cstore(a.Y + cy[j], act[j], cload(a.Xsep + cn[j], act[j], m), m);
+    }
+    for (int k = G.len - 1; k >= 0; --k) {
+        const int64_t g = G.start + k;
+        const uint32_t row = rel + (uint32_t)k;
+        const Quad nzt = qneg(qload<false>(rZ, row * BB, m, n));                          // -Zh_g
+        const Quad nxt = KIND == 0 ? qneg(qload<false>(rX, row * BB, m, n)) : qzero();   // -X_g
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            Col c = cload(a.Y + g * M + cy[j], act[j], m);     // t_k
+            c = mmc(nzt, xl[j], c);                             // - Zh_k x_sL
+            if constexpr (KIND == 0) c = mmc(nxt, xn[j], c);    // - X_k x_{k+1}
+            cstore(a.Y + g * M + cy[j], act[j], c, m);
+            xn[j] = c;
+        }
+    }
+}
+
+template <int KIND, int CT, bool ADD>
+__global__ __launch_bounds__(WG) void k_fwd32(SolveArgs a)
+{
+    fwd32_body<KIND, CT, ADD>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+}
+template <int KIND, int CT>
+__global__ __launch_bounds__(WG) void k_bwd32(SolveArgs a)
+{
+    bwd32_body<KIND, CT>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+}
+template <int KIND, int CT, bool ADD>
+__global__ __launch_bounds__(WG) void kb_fwd32(const SolveArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const SolveArgs a = tab[w.x];
+    fwd32_body<KIND, CT, ADD>(a, w.y, w.z, threadIdx.x);
+}
+template <int KIND, int CT>
+__global__ __launch_bounds__(WG) void kb_bwd32(const SolveArgs *tab, const int4 *work)
+{
+    const int4 w = work[blockIdx.x];
+    const SolveArgs a = tab[w.x];
+    bwd32_body<KIND, CT>(a, w.y, w.z, threadIdx.x);
+}
+
+template <typename F>
+hipError_t dispatch_CT(int cols, F &&f)
+{
+    return cols <= 16 ? f(std::integral_constant<int, 1>{}) : f(std::integral_constant<int, 2>{});
+}
+
 }  // namespace
 
 hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s)
@@ -269,6 +469,50 @@ hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4
     if (add) launch_k(kb_btri_mfma32<true>, dim3(nwg), dim3(WG), s, tab, work);
     else launch_k(kb_btri_mfma32<false>, dim3(nwg), dim3(WG), s, tab, work);
     return hipGetLastError();
+}
+
+}  // namespace pf
+
+namespace pf {
+
+// columns a workgroup of the M = 32 solve kernels covers
+int solve32_cols(int nrhs) { return nrhs <= 16 ? 16 : 32; }
+
+hipError_t launch_solve32(int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
+{
+    if (a.nrhs < 1) return hipErrorInvalidValue;
+    const int cols = solve32_cols(a.nrhs);
+    const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
+    return dispatch_CT(cols, [&](auto ct) {
+        constexpr int CT = decltype(ct)::value;
+        if (fwd) {
+            if (kind == 1) launch_k(k_fwd32<1, CT, false>, grid, dim3(WG), s, a);
+            else if (add) launch_k(k_fwd32<0, CT, true>, grid, dim3(WG), s, a);
+            else launch_k(k_fwd32<0, CT, false>, grid, dim3(WG), s, a);
+        } else {
+            if (kind == 1) launch_k(k_bwd32<1, CT>, grid, dim3(WG), s, a);
+            else launch_k(k_bwd32<0, CT>, grid, dim3(WG), s, a);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_solve32_batch(int kind, bool fwd, bool add, int cols, const SolveArgs *tab,
+                                const int4 *work, int nwg, hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    return dispatch_CT(cols, [&](auto ct) {
+        constexpr int CT = decltype(ct)::value;
+        if (fwd) {
+            if (kind == 1) launch_k(kb_fwd32<1, CT, false>, dim3(nwg), dim3(WG), s, tab, work);
+            else if (add) launch_k(kb_fwd32<0, CT, true>, dim3(nwg), dim3(WG), s, tab, work);
+            else launch_k(kb_fwd32<0, CT, false>, dim3(nwg), dim3(WG), s, tab, work);
+        } else {
+            if (kind == 1) launch_k(kb_bwd32<1, CT>, dim3(nwg), dim3(WG), s, tab, work);
+            else launch_k(kb_bwd32<0, CT>, dim3(nwg), dim3(WG), s, tab, work);
+        }
+        return hipGetLastError();
+    });
 }
 
 }  // namespace pf
