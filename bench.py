@@ -94,7 +94,8 @@ def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
 
 
 KERNEL_SOURCES = ("kernels_common.h", "kernels_gj.h", "kernels_seg.h", "kernels_seg.hip",
-                  "kernels_mfma.hip", "kernels_rows.hip", "kernels_solve.h", "kernels_solve.hip")
+                  "kernels_mfma.hip", "kernels_mfma_tiles.hip", "kernels_rows.hip", "kernels_solve.h",
+                  "kernels_solve.hip")
 
 
 def source_hash():

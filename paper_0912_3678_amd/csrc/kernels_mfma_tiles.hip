@@ -1,5 +1,6 @@
-// Partition-method factor kernel for 32 x 32 blocks with the block products
-// on the matrix cores (gfx950, FP64, block tridiagonal, every level).
+// Partition-method kernels on the matrix cores for 16 x 16 and 32 x 32 blocks
+// (gfx950, FP64): the factor kernel for 32 x 32 blocks (block tridiagonal,
+// every level) and the forward sweep and back substitution for both sizes.
 //
 // One partition per wave.  The pivot blocks are inverted by the Gauss-Jordan
 // exchange steps of kernels_gj.h with sixteen entries per lane (lane (r, g)
@@ -9,9 +10,9 @@
 // cores as 2 x 2 tiles of 16 x 16, each tile product four
 // v_mfma_f64_16x16x4f64 (K = 4 each).
 //
-// "Quad" layout: of a 32 x 32 matrix Y, lane l (n = l & 15, m = l >> 4) holds
-// Y(16I + m + 4q, 16J + n) for tiles I, J in {0, 1} and q = 0..3 -- the
-// result layout of the instruction for each tile.  Instruction h of tile
+// "Quad" layout: of an M x M matrix Y (T = M / 16 tiles of 16 a side), lane l
+// (n = l & 15, m = l >> 4) holds Y(16I + m + 4q, 16J + n) for tiles I, J < T
+// and q = 0..3 -- the result layout of the instruction for each tile.  Instruction h of tile
 // product (I, K) x (K, J) takes the A operand A(16I + n, 16K + 4h + m), entry
 // (K, I, h) of the quad of A^T, and the B operand B(16K + 4h + m, 16J + n),
 // entry (K, J, h) of the quad of B; so a product's result is the next
@@ -30,61 +31,67 @@ namespace {
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
-constexpr int kM = 32, kRS = kM + 2;   // padded LDS row stride (doubles)
+constexpr int kM = 32, kRS = kM + 2;   // factor kernel: block size, padded LDS row stride
 
-struct Quad {
-    dv4 t[2][2];   // [I][J], entry q = row m + 4q of the tile, column n
+template <int T> struct QuadT {
+    dv4 t[T][T];   // [I][J], entry q = row m + 4q of the tile, column n
 };
+using Quad = QuadT<2>;
 
-__device__ __forceinline__ Quad qzero()
+template <int T> __device__ __forceinline__ QuadT<T> qzero()
 {
-    Quad z;
+    QuadT<T> z;
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J < 2; ++J) z.t[I][J] = dv4{0.0, 0.0, 0.0, 0.0};
+        for (int J = 0; J < T; ++J) z.t[I][J] = dv4{0.0, 0.0, 0.0, 0.0};
     return z;
 }
-__device__ __forceinline__ Quad qneg(const Quad &a)
+template <int T> __device__ __forceinline__ QuadT<T> qneg(const QuadT<T> &a)
 {
-    Quad z;
+    QuadT<T> z;
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J < 2; ++J) z.t[I][J] = -a.t[I][J];
+        for (int J = 0; J < T; ++J) z.t[I][J] = -a.t[I][J];
     return z;
 }
 
 // C + A B; aT = quad of A^T, b = quad of B
-__device__ __forceinline__ Quad mm32(const Quad &aT, const Quad &b, Quad c)
+template <int T>
+__device__ __forceinline__ QuadT<T> mmq(const QuadT<T> &aT, const QuadT<T> &b, QuadT<T> c)
 {
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J < 2; ++J)
+        for (int J = 0; J < T; ++J)
 #pragma unroll
-            for (int K = 0; K < 2; ++K)
+            for (int K = 0; K < T; ++K)
 #pragma unroll
                 for (int h = 0; h < 4; ++h)
                     c.t[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT.t[K][I][h], b.t[K][J][h],
                                                                      c.t[I][J], 0, 0, 0);
     return c;
 }
+__device__ __forceinline__ Quad mm32(const Quad &aT, const Quad &b, Quad c) { return mmq<2>(aT, b, c); }
+__device__ __forceinline__ Quad qzero() { return qzero<2>(); }
+__device__ __forceinline__ Quad qneg(const Quad &a) { return qneg<2>(a); }
 
-// quad of a column-major FP64 block at byte offset base of resource r
-// (tr: the quad of its transpose)
-template <bool TR>
-__device__ __forceinline__ Quad qload(__amdgpu_buffer_rsrc_t rs, uint32_t base, int m, int n)
+// quad of a column-major FP64 M x M block at byte offset base of resource rs
+// (TR: the quad of its transpose; on a row-major block the roles swap)
+template <bool TR, int T = 2>
+__device__ __forceinline__ QuadT<T> qload(__amdgpu_buffer_rsrc_t rs, uint32_t base, int m, int n)
 {
-    Quad y;
+    constexpr int M = 16 * T;
+    QuadT<T> y;
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J < 2; ++J)
+        for (int J = 0; J < T; ++J)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = 16 * I + m + 4 * q, col = 16 * J + n;
-                const int e = TR ? col + kM * row : row + kM * col;
+                const int e = TR ? col + M * row : row + M * col;
                 y.t[I][J][q] = buf_ld(rs, base + (uint32_t)e * 8);
             }
     return y;
@@ -252,32 +259,33 @@ __global__ __launch_bounds__(WG) void kb_btri_mfma32(const LevelArgs *tab, const
 }
 
 // ---------------------------------------------------------------------------
-// Forward sweep and back substitution for M = 32 and FP64 factors (either
-// factor kernel's row-major E, X, Zh, R), the right-hand sides in column
-// tiles of 16: a tile's 32 x 16 block of one block row sits in the quad
-// layout (lane (m, n): rows 16I + m + 4q of column n).  Every block product
+// Forward sweep and back substitution for M = 16 and 32 and FP64 factors
+// (any factor kernel's row-major E, X, Zh, R), the right-hand sides in column
+// tiles of 16: a tile's M x 16 block of one block row sits in the quad layout
+// (lane (m, n): rows 16I + m + 4q of column n).  Every block product
 // is a chain of v_mfma_f64_16x16x4f64 whose left operand is a factor block's
 // transpose quad, loaded straight from memory, so the factors of a block row
 // are read once per CT tiles (the row kernels read them once per four
 // columns).  KIND: 0 block tridiagonal, 1 bidiagonal plus corner.
-struct Col {
-    dv4 t[2];   // [I], entry q = row 16I + m + 4q, column n of the tile
+template <int T> struct ColT {
+    dv4 t[T];   // [I], entry q = row 16I + m + 4q, column n of the tile
 };
 
-__device__ __forceinline__ Col czero()
+template <int T> __device__ __forceinline__ ColT<T> czero()
 {
-    Col c;
-    c.t[0] = dv4{0.0, 0.0, 0.0, 0.0};
-    c.t[1] = c.t[0];
+    ColT<T> c;
+#pragma unroll
+    for (int I = 0; I < T; ++I) c.t[I] = dv4{0.0, 0.0, 0.0, 0.0};
     return c;
 }
 // C + A B for one tile; aT = quad of A^T
-__device__ __forceinline__ Col mmc(const Quad &aT, const Col &b, Col c)
+template <int T>
+__device__ __forceinline__ ColT<T> mmc(const QuadT<T> &aT, const ColT<T> &b, ColT<T> c)
 {
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int K = 0; K < 2; ++K)
+        for (int K = 0; K < T; ++K)
 #pragma unroll
             for (int h = 0; h < 4; ++h)
                 c.t[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(aT.t[K][I][h], b.t[K][h], c.t[I], 0, 0, 0);
@@ -285,34 +293,35 @@ __device__ __forceinline__ Col mmc(const Quad &aT, const Col &b, Col c)
 }
 // tile of a column-major array (p: row 0 of the block row, column n of the
 // tile; zero when the column does not exist)
-__device__ __forceinline__ Col cload(const double *p, bool act, int m)
+template <int T> __device__ __forceinline__ ColT<T> cload(const double *p, bool act, int m)
 {
-    Col c;
+    ColT<T> c;
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int q = 0; q < 4; ++q) c.t[I][q] = act ? p[16 * I + m + 4 * q] : 0.0;
     return c;
 }
-__device__ __forceinline__ void cstore(double *p, bool act, const Col &c, int m)
+template <int T> __device__ __forceinline__ void cstore(double *p, bool act, const ColT<T> &c, int m)
 {
     if (!act) return;
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int q = 0; q < 4; ++q) p[16 * I + m + 4 * q] = c.t[I][q];
 }
-__device__ __forceinline__ Col cadd(Col a, const Col &b)
+template <int T> __device__ __forceinline__ ColT<T> cadd(ColT<T> a, const ColT<T> &b)
 {
-    a.t[0] += b.t[0];
-    a.t[1] += b.t[1];
+#pragma unroll
+    for (int I = 0; I < T; ++I) a.t[I] += b.t[I];
     return a;
 }
 
-template <int KIND, int CT, bool ADD>
-__device__ __forceinline__ void fwd32_body(const SolveArgs &a, int64_t part, int cg, int lane)
+template <int M, int KIND, int CT, bool ADD>
+__device__ __forceinline__ void fwdt_body(const SolveArgs &a, int64_t part, int cg, int lane)
 {
-    constexpr int M = kM;
+    constexpr int T = M / 16;
+    using Col = ColT<T>;
     constexpr size_t MM = (size_t)M * M;
     constexpr uint32_t BB = MM * 8;
     const int m = lane >> 4, n = lane & 15;
@@ -337,23 +346,23 @@ __device__ __forceinline__ void fwd32_body(const SolveArgs &a, int64_t part, int
     Col fp[CT], gl[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
-        fp[j] = cload(a.F + G.start * M + cf[j], act[j] && G.valid, m);
-        if constexpr (ADD) fp[j] = cadd(fp[j], cload(a.Fadd + G.start * M + cf[j], act[j] && G.valid, m));
-        gl[j] = czero();
+        fp[j] = cload<T>(a.F + G.start * M + cf[j], act[j] && G.valid, m);
+        if constexpr (ADD) fp[j] = cadd<T>(fp[j], cload<T>(a.Fadd + G.start * M + cf[j], act[j] && G.valid, m));
+        gl[j] = czero<T>();
     }
     for (int k = 0; k < G.len; ++k) {
         const int64_t g = G.start + k;
         const uint32_t row = rel + (uint32_t)k;
-        const Quad eT = qload<false>(rE, row * BB, m, n);     // E_g^T (E row-major)
-        const Quad nlo = qneg(qload<true>(rL, row * BB, m, n));   // -A(g+1,g)^T
-        const Quad nrt = (KIND == 0 && G.hasL) ? qneg(qload<false>(rR, row * BB, m, n)) : qzero();
+        const QuadT<T> eT = qload<false, T>(rE, row * BB, m, n);     // E_g^T (E row-major)
+        const QuadT<T> nlo = qneg<T>(qload<true, T>(rL, row * BB, m, n));   // -A(g+1,g)^T
+        const QuadT<T> nrt = (KIND == 0 && G.hasL) ? qneg<T>(qload<false, T>(rR, row * BB, m, n)) : qzero<T>();
         const bool nx = g + 1 < nb;
 #pragma unroll
         for (int j = 0; j < CT; ++j) {
-            Col fn = cload(a.F + (g + 1) * M + cf[j], act[j] && nx, m);
-            if constexpr (ADD) fn = cadd(fn, cload(a.Fadd + (g + 1) * M + cf[j], act[j] && nx, m));
-            const Col t = mmc(eT, fp[j], czero());                   // t_k = E_k f'_k
-            cstore(a.Y + g * M + cy[j], act[j], t, m);
+            Col fn = cload<T>(a.F + (g + 1) * M + cf[j], act[j] && nx, m);
+            if constexpr (ADD) fn = cadd<T>(fn, cload<T>(a.Fadd + (g + 1) * M + cf[j], act[j] && nx, m));
+            const Col t = mmc(eT, fp[j], czero<T>());                   // t_k = E_k f'_k
+            cstore<T>(a.Y + g * M + cy[j], act[j], t, m);
             fp[j] = mmc(nlo, t, fn);                                 // f'_{k+1} = f[g+1] - A(g+1,g) t_k
             if constexpr (KIND == 0) gl[j] = mmc(nrt, t, gl[j]);     // g_sL -= R_k t_k
         }
@@ -361,19 +370,20 @@ __device__ __forceinline__ void fwd32_body(const SolveArgs &a, int64_t part, int
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
         if (KIND == 0) {
-            if (G.hasR) cstore(a.nF + part * M + cn[j], act[j], fp[j], m);
-            if (G.hasL) cstore(a.nFadd + (part - 1) * M + cn[j], act[j], gl[j], m);
+            if (G.hasR) cstore<T>(a.nF + part * M + cn[j], act[j], fp[j], m);
+            if (G.hasL) cstore<T>(a.nFadd + (part - 1) * M + cn[j], act[j], gl[j], m);
         } else if (G.valid) {
-            cstore(a.nF + (part + 1) * M + cn[j], act[j], fp[j], m);
-            if (part == 0) cstore(a.nF + cn[j], act[j], cload(a.F + cf[j], act[j], m), m);
+            cstore<T>(a.nF + (part + 1) * M + cn[j], act[j], fp[j], m);
+            if (part == 0) cstore<T>(a.nF + cn[j], act[j], cload<T>(a.F + cf[j], act[j], m), m);
         }
     }
 }
 
-template <int KIND, int CT>
-__device__ __forceinline__ void bwd32_body(const SolveArgs &a, int64_t part, int cg, int lane)
+template <int M, int KIND, int CT>
+__device__ __forceinline__ void bwdt_body(const SolveArgs &a, int64_t part, int cg, int lane)
 {
-    constexpr int M = kM;
+    constexpr int T = M / 16;
+    using Col = ColT<T>;
     constexpr size_t MM = (size_t)M * M;
     constexpr uint32_t BB = MM * 8;
     const int m = lane >> 4, n = lane & 15;
@@ -399,50 +409,50 @@ __device__ __forceinline__ void bwd32_body(const SolveArgs &a, int64_t part, int
     Col xl[CT], xn[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
-        xl[j] = cload(a.Xsep + jl * M + cn[j], act[j] && G.hasL, m);
-        xn[j] = cload(a.Xsep + jr * M + cn[j], act[j] && G.hasR, m);
-        if (G.hasR) cstore(a.Y + sR * M + cy[j], act[j], xn[j], m);
-        if (KIND == 1 && G.valid && part == 0) cstore(a.Y + cy[j], act[j], cload(a.Xsep + cn[j], act[j], m), m);
+        xl[j] = cload<T>(a.Xsep + jl * M + cn[j], act[j] && G.hasL, m);
+        xn[j] = cload<T>(a.Xsep + jr * M + cn[j], act[j] && G.hasR, m);
+        if (G.hasR) cstore<T>(a.Y + sR * M + cy[j], act[j], xn[j], m);
+        if (KIND == 1 && G.valid && part == 0) cstore<T>(a.Y + cy[j], act[j], cload<T>(a.Xsep + cn[j], act[j], m), m);
     }
     for (int k = G.len - 1; k >= 0; --k) {
         const int64_t g = G.start + k;
         const uint32_t row = rel + (uint32_t)k;
-        const Quad nzt = qneg(qload<false>(rZ, row * BB, m, n));                          // -Zh_g
-        const Quad nxt = KIND == 0 ? qneg(qload<false>(rX, row * BB, m, n)) : qzero();   // -X_g
+        const QuadT<T> nzt = qneg<T>(qload<false, T>(rZ, row * BB, m, n));                          // -Zh_g
+        const QuadT<T> nxt = KIND == 0 ? qneg<T>(qload<false, T>(rX, row * BB, m, n)) : qzero<T>();   // -X_g
 #pragma unroll
         for (int j = 0; j < CT; ++j) {
-            Col c = cload(a.Y + g * M + cy[j], act[j], m);     // t_k
+            Col c = cload<T>(a.Y + g * M + cy[j], act[j], m);     // t_k
             c = mmc(nzt, xl[j], c);                             // - Zh_k x_sL
             if constexpr (KIND == 0) c = mmc(nxt, xn[j], c);    // - X_k x_{k+1}
-            cstore(a.Y + g * M + cy[j], act[j], c, m);
+            cstore<T>(a.Y + g * M + cy[j], act[j], c, m);
             xn[j] = c;
         }
     }
 }
 
-template <int KIND, int CT, bool ADD>
-__global__ __launch_bounds__(WG) void k_fwd32(SolveArgs a)
+template <int M, int KIND, int CT, bool ADD>
+__global__ __launch_bounds__(WG) void k_fwdt(SolveArgs a)
 {
-    fwd32_body<KIND, CT, ADD>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+    fwdt_body<M, KIND, CT, ADD>(a, blockIdx.x, blockIdx.y, threadIdx.x);
 }
-template <int KIND, int CT>
-__global__ __launch_bounds__(WG) void k_bwd32(SolveArgs a)
+template <int M, int KIND, int CT>
+__global__ __launch_bounds__(WG) void k_bwdt(SolveArgs a)
 {
-    bwd32_body<KIND, CT>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+    bwdt_body<M, KIND, CT>(a, blockIdx.x, blockIdx.y, threadIdx.x);
 }
-template <int KIND, int CT, bool ADD>
-__global__ __launch_bounds__(WG) void kb_fwd32(const SolveArgs *tab, const int4 *work)
+template <int M, int KIND, int CT, bool ADD>
+__global__ __launch_bounds__(WG) void kb_fwdt(const SolveArgs *tab, const int4 *work)
 {
     const int4 w = work[blockIdx.x];
     const SolveArgs a = tab[w.x];
-    fwd32_body<KIND, CT, ADD>(a, w.y, w.z, threadIdx.x);
+    fwdt_body<M, KIND, CT, ADD>(a, w.y, w.z, threadIdx.x);
 }
-template <int KIND, int CT>
-__global__ __launch_bounds__(WG) void kb_bwd32(const SolveArgs *tab, const int4 *work)
+template <int M, int KIND, int CT>
+__global__ __launch_bounds__(WG) void kb_bwdt(const SolveArgs *tab, const int4 *work)
 {
     const int4 w = work[blockIdx.x];
     const SolveArgs a = tab[w.x];
-    bwd32_body<KIND, CT>(a, w.y, w.z, threadIdx.x);
+    bwdt_body<M, KIND, CT>(a, w.y, w.z, threadIdx.x);
 }
 
 template <typename F>
@@ -475,43 +485,57 @@ hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4
 
 namespace pf {
 
-// columns a workgroup of the M = 32 solve kernels covers
+// columns a workgroup of the tiled solve kernels covers
 int solve32_cols(int nrhs) { return nrhs <= 16 ? 16 : 32; }
 
-hipError_t launch_solve32(int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
+template <typename F>
+static hipError_t dispatch_T(int M, F &&f)
+{
+    if (M == 16) return f(std::integral_constant<int, 16>{});
+    if (M == 32) return f(std::integral_constant<int, 32>{});
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
 {
     if (a.nrhs < 1) return hipErrorInvalidValue;
     const int cols = solve32_cols(a.nrhs);
     const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
-    return dispatch_CT(cols, [&](auto ct) {
-        constexpr int CT = decltype(ct)::value;
-        if (fwd) {
-            if (kind == 1) launch_k(k_fwd32<1, CT, false>, grid, dim3(WG), s, a);
-            else if (add) launch_k(k_fwd32<0, CT, true>, grid, dim3(WG), s, a);
-            else launch_k(k_fwd32<0, CT, false>, grid, dim3(WG), s, a);
-        } else {
-            if (kind == 1) launch_k(k_bwd32<1, CT>, grid, dim3(WG), s, a);
-            else launch_k(k_bwd32<0, CT>, grid, dim3(WG), s, a);
-        }
-        return hipGetLastError();
+    return dispatch_T(M, [&](auto mc) {
+        constexpr int MV = decltype(mc)::value;
+        return dispatch_CT(cols, [&](auto ct) {
+            constexpr int CT = decltype(ct)::value;
+            if (fwd) {
+                if (kind == 1) launch_k(k_fwdt<MV, 1, CT, false>, grid, dim3(WG), s, a);
+                else if (add) launch_k(k_fwdt<MV, 0, CT, true>, grid, dim3(WG), s, a);
+                else launch_k(k_fwdt<MV, 0, CT, false>, grid, dim3(WG), s, a);
+            } else {
+                if (kind == 1) launch_k(k_bwdt<MV, 1, CT>, grid, dim3(WG), s, a);
+                else launch_k(k_bwdt<MV, 0, CT>, grid, dim3(WG), s, a);
+            }
+            return hipGetLastError();
+        });
     });
 }
 
-hipError_t launch_solve32_batch(int kind, bool fwd, bool add, int cols, const SolveArgs *tab,
-                                const int4 *work, int nwg, hipStream_t s)
+hipError_t launch_solvet_batch(int M, int kind, bool fwd, bool add, int cols, const SolveArgs *tab,
+                               const int4 *work, int nwg, hipStream_t s)
 {
     if (nwg <= 0) return hipSuccess;
-    return dispatch_CT(cols, [&](auto ct) {
-        constexpr int CT = decltype(ct)::value;
-        if (fwd) {
-            if (kind == 1) launch_k(kb_fwd32<1, CT, false>, dim3(nwg), dim3(WG), s, tab, work);
-            else if (add) launch_k(kb_fwd32<0, CT, true>, dim3(nwg), dim3(WG), s, tab, work);
-            else launch_k(kb_fwd32<0, CT, false>, dim3(nwg), dim3(WG), s, tab, work);
-        } else {
-            if (kind == 1) launch_k(kb_bwd32<1, CT>, dim3(nwg), dim3(WG), s, tab, work);
-            else launch_k(kb_bwd32<0, CT>, dim3(nwg), dim3(WG), s, tab, work);
-        }
-        return hipGetLastError();
+    return dispatch_T(M, [&](auto mc) {
+        constexpr int MV = decltype(mc)::value;
+        return dispatch_CT(cols, [&](auto ct) {
+            constexpr int CT = decltype(ct)::value;
+            if (fwd) {
+                if (kind == 1) launch_k(kb_fwdt<MV, 1, CT, false>, dim3(nwg), dim3(WG), s, tab, work);
+                else if (add) launch_k(kb_fwdt<MV, 0, CT, true>, dim3(nwg), dim3(WG), s, tab, work);
+                else launch_k(kb_fwdt<MV, 0, CT, false>, dim3(nwg), dim3(WG), s, tab, work);
+            } else {
+                if (kind == 1) launch_k(kb_bwdt<MV, 1, CT>, dim3(nwg), dim3(WG), s, tab, work);
+                else launch_k(kb_bwdt<MV, 0, CT>, dim3(nwg), dim3(WG), s, tab, work);
+            }
+            return hipGetLastError();
+        });
     });
 }
 

@@ -85,12 +85,14 @@ hipError_t launch_mfma_factor_batch(const LevelArgs *tab, const int4 *work, int 
 hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s);
 hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
                                       hipStream_t s);
-// matrix-core forward sweep / back substitution for M = 32 and FP64 factors:
-// one partition per workgroup, solve32_cols(nrhs) right-hand sides each
+// matrix-core forward sweep / back substitution for M = 16, 32 and FP64
+// factors: one partition per workgroup, solve32_cols(nrhs) right-hand sides
+// each
 int solve32_cols(int nrhs);
-hipError_t launch_solve32(int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s);
-hipError_t launch_solve32_batch(int kind, bool fwd, bool add, int cols, const SolveArgs *tab,
-                                const int4 *work, int nwg, hipStream_t s);
+hipError_t launch_solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s);
+hipError_t launch_solvet_batch(int M, int kind, bool fwd, bool add, int cols, const SolveArgs *tab,
+                               const int4 *work, int nwg, hipStream_t s);
+inline bool solve_tiled(int M, bool f32) { return (M == 16 || M == 32) && !f32; }
 int seg_partitions_per_wg(int M, int E);
 hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &a,
                              const SolveArgs *sv, hipStream_t s);
@@ -169,12 +171,12 @@ int status_nosync(pf_factor_s *F, pf_info *info);
 int tuned_opts(const pf_matrix *A, const pf_opts &o, int nrhs, hipStream_t s, pf_opts *out);
 
 // work decomposition of a solve launch (batched solves): partitions per
-// workgroup and right-hand-side columns per workgroup (M = 32 with FP64
-// factors: the matrix-core kernels)
-inline int solve_groups_per_wg(int M, bool f32) { return (M == 32 && !f32) ? 1 : groups_per_wg(M); }
+// workgroup and right-hand-side columns per workgroup (M = 16 and 32 with
+// FP64 factors: the matrix-core kernels)
+inline int solve_groups_per_wg(int M, bool f32) { return solve_tiled(M, f32) ? 1 : groups_per_wg(M); }
 inline int solve_cols(int M, bool f32, int nrhs)
 {
-    return (M == 32 && !f32) ? solve32_cols(nrhs) : rhs_chunk(nrhs);
+    return solve_tiled(M, f32) ? solve32_cols(nrhs) : rhs_chunk(nrhs);
 }
 
 }  // namespace pf
