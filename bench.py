@@ -556,6 +556,7 @@ def run_serving(args):
         kept = []
         tickets = []
         host_submit = 0.0
+        submit_ms = []
         t0 = time.perf_counter()
         for i, r in enumerate(stream):
             while qps and time.perf_counter() - t0 < r["t"]:
@@ -575,6 +576,7 @@ def run_serving(args):
                 t = S.submit(A, f, x, keep=True)
                 fac = -1
             host_submit += time.perf_counter() - th
+            submit_ms.append((time.perf_counter() - th) * 1e3)
             if fac < 0:
                 kept.append((t, pi))
             tickets.append((t, pi, fac))
@@ -596,7 +598,9 @@ def run_serving(args):
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "bad_status": sum(1 for i in infos if i.status != 0), "eta_max_sample": max(etas),
                 "evictions": st["evictions"], "repeats": sum(1 for _, _, fac in tickets if fac >= 0),
-                "host_submit_ms": round(host_submit * 1e3, 1)}
+                "host_submit_ms": round(host_submit * 1e3, 1),
+                "host_submit_max_ms": round(max(submit_ms), 2),
+                "host_submit_slowest": [int(i) for i in np.argsort(submit_ms)[-5:]]}
 
     sat = run_stream(0)
     rate = sat["throughput_req_s"]
