@@ -1,6 +1,8 @@
 // Partition-method kernels on the matrix cores for 16 x 16 and 32 x 32 blocks
 // (gfx950, FP64): the factor kernel for 32 x 32 blocks (block tridiagonal,
-// every level) and the forward sweep and back substitution for both sizes.
+// every level), the factor kernel for 16 x 16 blocks of the bidiagonal-plus-
+// corner form (every level, further below) and the forward sweep and back
+// substitution for both sizes.
 //
 // One partition per wave.  The pivot blocks are inverted by the Gauss-Jordan
 // exchange steps of kernels_gj.h with sixteen entries per lane (lane (r, g)
@@ -124,6 +126,22 @@ __device__ __forceinline__ void qstore_g(double *p, const Quad &y, int m, int n)
             for (int q = 0; q < 4; ++q) {
                 const int row = 16 * I + m + 4 * q, col = 16 * J + n;
                 p[TR ? col + kM * row : row + kM * col] = y.t[I][J][q];
+            }
+}
+
+// quad (any T) into a column-major FP64 block of global memory
+template <bool TR, int T>
+__device__ __forceinline__ void qstore_gt(double *p, const QuadT<T> &y, int m, int n)
+{
+    constexpr int M = 16 * T;
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * I + m + 4 * q, col = 16 * J + n;
+                p[TR ? col + M * row : row + M * col] = y.t[I][J][q];
             }
 }
 
@@ -455,6 +473,165 @@ __global__ __launch_bounds__(WG) void kb_bwdt(const SolveArgs *tab, const int4 *
     bwdt_body<M, KIND, CT>(a, w.y, w.z, threadIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Factor kernel for 16 x 16 blocks of the bidiagonal-plus-corner form (FP64,
+// every level; RHS: up to 16 right-hand sides swept forward in the same
+// pass).  In this form the pivot blocks do not depend on the chain (D' = D),
+// so a wave inverts four consecutive blocks of its partition at once --
+// sixteen lanes per block, one tableau row per lane, the exchange steps of
+// kernels_gj.h -- and then runs the chain of those rows on the matrix cores
+// (one 16 x 16 tile per product): Zh_k = E_k Z'_k, t_k = E_k f'_k,
+// Z'_{k+1} = -A(g+1,g) Zh_k, f'_{k+1} = f[g+1] - A(g+1,g) t_k.  The chain
+// operands of the four rows are requested before the inversion, which
+// covers their latency.  Outputs are those of the segment kernel (E and Zh
+// row-major; beta, the next diagonal block and the reduced right-hand side).
+constexpr int kBQ = 4;                              // blocks inverted together
+constexpr int kBRS = 16 + kPad<double>;             // padded LDS row stride
+constexpr int kBSL = 16 * kBRS;                     // one block in LDS
+constexpr uint32_t kOffRowNone = 0xFFFFFF80u;       // 128 bytes past every resource
+
+// quad (T = 1) into a row-major factor block
+__device__ __forceinline__ void qstore16(__amdgpu_buffer_rsrc_t rs, uint32_t base, bool keep,
+                                         const QuadT<1> &y, int m, int n)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        buf_st(rs, keep ? base + (uint32_t)((m + 4 * q) * 16 + n) * 8 : kOffNone, y.t[0][0][q]);
+}
+
+template <bool RHS>
+__device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const SolveArgs &sv,
+                                                 int64_t part, int lane, double *lds)
+{
+    constexpr int M = 16, E = 16;
+    constexpr size_t MM = (size_t)M * M;
+    constexpr uint32_t BB = MM * 8;
+    // inversion role: block q of the group, tableau row r; matrix-core role: (m, n)
+    const int q = lane / M, r = lane % M;
+    const int m = lane >> 4, n = lane & 15;
+    double *S0 = lds + q * kBSL;            // tableau of block q
+    double *SE = lds + (kBQ + q) * kBSL;    // E_q by logical rows
+
+    const int64_t nb = a.nb;
+    const Geo G = geometry<1>(nb, a.p, part);
+    const int64_t gb = G.start - 1;         // the left separator (G.start >= 1)
+    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
+    const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
+    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
+    const auto rE = buf_rsrc((double *)a.E + gb * MM, nr * BB);
+    const auto rZ = buf_rsrc((double *)a.Z + gb * MM, nr * BB);
+    const uint32_t rel = (uint32_t)(G.start - gb);
+
+    const bool act = RHS && n < sv.nrhs;    // right-hand-side column n of the tiles
+    const int64_t cf = (int64_t)(act ? n : 0) * sv.ldf, cy = (int64_t)(act ? n : 0) * sv.ldy;
+    const int64_t cn = (int64_t)(act ? n : 0) * sv.ldn;
+
+    // Z'_1 = A(g_1, sL), f'_1 = f[g_1]
+    QuadT<1> z = qload<false, 1>(rL, (rel - 1) * BB, m, n);
+    ColT<1> fp = czero<1>();
+    if constexpr (RHS) fp = cload<1>(sv.F + G.start * M + cf, act && G.valid, m);
+    unsigned long long bad = ~0ull;
+
+    for (int k0 = 0; k0 < G.len; k0 += kBQ) {
+        const int nq = G.len - k0 < kBQ ? G.len - k0 : kBQ;
+        // block q of the group: D[g], row r (column-major block)
+        const bool vq = q < nq;
+        double d[E];
+        {
+            const uint32_t o = (rel + (uint32_t)(k0 + q)) * BB + (uint32_t)r * 8;
+#pragma unroll
+            for (int e = 0; e < E; ++e) d[e] = buf_ld(rD, o + (uint32_t)(e * M * 8));
+        }
+
+        // chain operands of the group's first row, A(g+1,g)^T and f[g+1], then
+        // one row ahead
+        auto load_lo = [&](int k) { return qload<true, 1>(rL, (rel + (uint32_t)k) * BB, m, n); };
+        auto load_fn = [&](int k) {
+            const int64_t g1 = G.start + k + 1;
+            return RHS ? cload<1>(sv.F + g1 * M + cf, act && k < G.len && g1 < nb, m) : czero<1>();
+        };
+        QuadT<1> loN = load_lo(k0);
+        ColT<1> fnN = load_fn(k0);
+
+        // E = D^{-1} of the group's blocks
+        int sigma = 0, pc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) pc[e] = 0;
+        bool sing = false;
+        seg_invert<M, E, double>(d, r, 0, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, G.start + k0 + q);
+        bad = (sing && vq && code < bad) ? code : bad;
+#pragma unroll
+        for (int e = 0; e < E; ++e) SE[sigma * kBRS + pc[e]] = d[e];
+        wave_sync();
+        {
+            double er[E];
+            lds_row<E, double>(er, SE + r * kBRS);
+            buf_st_row<E, double>(rE, vq ? (rel + (uint32_t)(k0 + q)) * BB + (uint32_t)(r * M) * 8
+                                         : kOffRowNone, er);
+        }
+
+        // the chain over the group's rows (matrix-core role)
+#pragma unroll
+        for (int i = 0; i < kBQ; ++i) {
+            if (i < nq) {
+                const int64_t g = G.start + k0 + i;
+                const uint32_t row = rel + (uint32_t)(k0 + i);
+                const double *Ei = lds + (kBQ + i) * kBSL;
+                QuadT<1> eT;   // quad of E^T: E(n, m + 4h)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) eT.t[0][0][h] = Ei[n * kBRS + m + 4 * h];
+                const QuadT<1> nlo = qneg<1>(loN);   // -A(g+1,g)^T
+                const ColT<1> fn = fnN;
+                loN = load_lo(k0 + i + 1);
+                fnN = load_fn(k0 + i + 1);
+                const QuadT<1> zh = mmq<1>(eT, z, qzero<1>());   // Zh_k = E_k Z'_k
+                qstore16(rZ, row * BB, true, zh, m, n);
+                z = mmq<1>(nlo, zh, qzero<1>());                  // Z'_{k+1} = -A(g+1,g) Zh_k
+                if constexpr (RHS) {
+                    const ColT<1> tk = mmc<1>(eT, fp, czero<1>());   // t_k = E_k f'_k
+                    cstore<1>(sv.Y + g * M + cy, act, tk, m);
+                    fp = mmc<1>(nlo, tk, fn);                      // f'_{k+1} = f[g+1] - A(g+1,g) t_k
+                }
+            }
+        }
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+    if (G.valid) {
+        const int64_t sR = G.start + G.len;
+        qstore_gt<false, 1>(a.nLo + part * MM, z, m, n);   // beta
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = lane + 64 * i;
+            a.nD[(part + 1) * MM + e] = a.D[sR * MM + e];
+            if (part == 0) {
+                a.nD[e] = a.D[e];
+                a.nC[e] = a.C[e];
+            }
+        }
+        if constexpr (RHS) {
+            cstore<1>(sv.nF + (part + 1) * M + cn, act, fp, m);
+            if (part == 0) cstore<1>(sv.nF + cn, act, cload<1>(sv.F + cf, act, m), m);
+        }
+    }
+}
+
+template <bool RHS>
+__global__ __launch_bounds__(WG) void k_babd_mfma16(LevelArgs a, SolveArgs sv)
+{
+    __shared__ __align__(16) double lds[2 * kBQ * kBSL];
+    babd_mfma16_body<RHS>(a, sv, blockIdx.x, threadIdx.x, lds);
+}
+// batched (factor only): workgroup w serves table entry work[w].x, partition work[w].y
+__global__ __launch_bounds__(WG) void kb_babd_mfma16(const LevelArgs *tab, const int4 *work)
+{
+    __shared__ __align__(16) double lds[2 * kBQ * kBSL];
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    babd_mfma16_body<false>(a, SolveArgs{}, w.y, threadIdx.x, lds);
+}
+
 template <typename F>
 hipError_t dispatch_CT(int cols, F &&f)
 {
@@ -469,6 +646,24 @@ hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s)
     const dim3 grid((unsigned)a.p);
     if (a.Dadd) launch_k(k_btri_mfma32<true>, grid, dim3(WG), s, a);
     else launch_k(k_btri_mfma32<false>, grid, dim3(WG), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_babd16_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s)
+{
+    if (a.p < 1) return hipErrorInvalidValue;
+    if (sv && (sv->nrhs < 1 || sv->nrhs > 16)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)a.p);
+    if (sv) launch_k(k_babd_mfma16<true>, grid, dim3(WG), s, a, *sv);
+    else launch_k(k_babd_mfma16<false>, grid, dim3(WG), s, a, SolveArgs{});
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_babd16_factor_batch(const LevelArgs *tab, const int4 *work, int nwg,
+                                           hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    launch_k(kb_babd_mfma16, dim3(nwg), dim3(WG), s, tab, work);
     return hipGetLastError();
 }
 

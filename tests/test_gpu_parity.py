@@ -163,6 +163,57 @@ def test_matrix_core_32(nb, p, m):
     del keep
 
 
+@pytest.mark.parametrize("nb,p", [(3, 1), (5, 2), (9, 4), (40, 3), (41, 3), (300, 7), (1000, 0),
+                                  (4097, 0), (1001, 500)])
+@pytest.mark.parametrize("m,nrhs", [(16, 1), (16, 16), (12, 5), (16, 17)])
+def test_matrix_core_babd16(nb, p, m, nrhs):
+    """The m = 16 matrix-core factor kernel of the bidiagonal-plus-corner form
+    (FP64, every level: four pivot blocks inverted together, the chain on the
+    matrix cores) gives the oracle's solution and agrees with the segment
+    mapping: partitions of one to thirteen blocks (groups of four with ragged
+    tails), the fused forward sweep for 1..16 right-hand sides, 17 (no
+    fusion), padded blocks (m = 12), and the factors left for pf_solve."""
+    import torch
+    seed = 1700 + nb + 5 * p + m + nrhs
+    s = wl.random_babd(nb, m, seed=seed)
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((nb * m, nrhs))
+    A, keep = G.to_device(s)
+    xs = {}
+    for name, flags in (("mfma", 0), ("segments", pf.PF_FLAG_MAP_SEGMENTS)):
+        F = pf.pf_factor(A, pf.make_opts(partitions=p, flags=flags))
+        try:
+            fd = G.rhs_to_device(f)
+            x = torch.full_like(fd, np.nan)
+            _say("babd m", m, "nb", nb, "p", p, "nrhs", nrhs, name)
+            info = pf.pf_factor_solve(F, fd, x)
+            assert info.status == 0
+            xs[name] = x.cpu().numpy().T
+            G.check(s, xs[name], f=f, tag=f"{name} babd m={m} nb={nb} p={p} k={nrhs}")
+            x2 = torch.full_like(fd, np.nan)
+            assert pf.pf_solve(F, fd, x2).status == 0
+            G.check(s, x2.cpu().numpy().T, f=f, tag=f"{name} solve babd m={m} nb={nb} p={p}")
+        finally:
+            pf.pf_destroy(F)
+    scale = np.abs(xs["segments"]).max()
+    assert np.abs(xs["mfma"] - xs["segments"]).max() <= 1e-11 * scale
+    del keep
+
+
+@pytest.mark.parametrize("flags", [0, pf.PF_FLAG_MAP_SEGMENTS])
+def test_singular_pivot_babd16(flags):
+    """An exactly singular pivot block inside a partition of the m = 16
+    bidiagonal-plus-corner form is reported with its level and the first such
+    block, by the matrix-core kernel (blocks inverted in groups of four) as by
+    the segment kernel.  Partitions of nine blocks: separators 0, 10, .., 40."""
+    s = wl.random_babd(41, 16, seed=9)
+    s.D[23] = 0.0
+    s.D[17] = 0.0
+    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=4, flags=flags))
+    assert info.status == pf.PF_ESINGULAR
+    assert info.bad_level == 0 and info.bad_block == 17
+
+
 @pytest.mark.parametrize("kind,m,nb,nrhs,prec", [
     ("btri", 8, 4099, 1, "fp64"), ("btri", 8, 1001, 3, "fp64"), ("btri", 8, 300, 8, "fp64"),
     ("btri", 8, 300, 9, "fp64"), ("btri", 4, 2049, 1, "fp64"), ("btri", 3, 700, 2, "fp64"),
