@@ -102,16 +102,19 @@ int padded_block(int m)
 // Blocks per partition (the chain length of one group of lanes).  Short
 // chains give many partitions (parallelism, latency hiding); the reduced
 // system then has about nb/(L+1) blocks and is solved by the next level.
-int target_rows(int M, bool f32, int level, const pf_opts &o)
+int target_rows(int kind, int M, bool f32, int level, const pf_opts &o)
 {
     if (level == 0 && o.block_rows > 0) return o.block_rows;
     if (level > 0 && o.coarse_rows > 0) return o.coarse_rows;
-    (void)f32;
     // measured on MI355X for the m = 8 BVP (segment mapping, two entries per
     // lane at level 0): 16 blocks at level 0, where 3855 partitions fill the
     // resident wave slots about once, and 3 on the reduced levels (latency-
-    // bound: the chain length per level trades against the number of levels)
-    if (level == 0) return M <= 8 ? 16 : 4;
+    // bound: the chain length per level trades against the number of levels).
+    // The m = 16 bidiagonal-plus-corner form in FP64 (its matrix-core kernel
+    // inverts four blocks at a time): 16 at level 0, which costs about as much
+    // as 4 there and leaves a reduced system a quarter the size (m = 16 BVP,
+    // N = 2^18: 0.97 vs 1.08 ms per step).
+    if (level == 0) return (M <= 8 || (kind == PF_BABD && M == 16 && !f32)) ? 16 : 4;
     return 3;
 }
 
@@ -158,7 +161,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
             int64_t p;
             if (lvl == 0 && o.partitions > 0) p = o.partitions;
             else {
-                const int L = target_rows(M, f32, lvl, o);
+                const int L = target_rows(kind, M, f32, lvl, o);
                 p = (cur - 1) / (L + 1);
                 p = std::max<int64_t>(p, 1);
                 p = std::min<int64_t>(p, (cur - 1) / 2);
@@ -175,7 +178,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
         if (lvl == 0 && o.partitions > 0) p = o.partitions;
         else if (cur <= kTail) p = 1;
         else {
-            const int L = target_rows(M, f32, lvl, o);
+            const int L = target_rows(kind, M, f32, lvl, o);
             p = (cur + 1) / (L + 1);
             p = std::max<int64_t>(p, 2);
             p = std::min<int64_t>(p, (cur + 1) / 2);

@@ -66,11 +66,22 @@ __device__ __forceinline__ void seg_invert(T (&b)[E], int r, int gc, T *S, int &
     int pr = seg_pivot<M, E, T>(b[0], used, r, 0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        lds_put<E, T>(S + r * RS + c0, b);
-        wave_sync();
-        T prow[E];
-        lds_get<E, T>(prow, S + __umul24(pr, RS) + c0);
-        const T mcol = S[r * RS + j], pv = S[__umul24(pr, RS) + j];
+        T prow[E], mcol, pv;
+        if constexpr (E == M) {
+            // whole rows per lane: only the pivot row goes through LDS (to
+            // row 0 of the block's area), column j is in the lane's registers
+            if (r == pr) lds_put<E, T>(S, b);
+            wave_sync();
+            lds_get<E, T>(prow, S);
+            mcol = b[j];
+            pv = prow[j];
+        } else {
+            lds_put<E, T>(S + r * RS + c0, b);
+            wave_sync();
+            lds_get<E, T>(prow, S + __umul24(pr, RS) + c0);
+            mcol = S[r * RS + j];
+            pv = S[__umul24(pr, RS) + j];
+        }
         sing = sing || (pv == T(0));
         const T inv = recip(pv);
         const bool isr = (r == pr);
@@ -79,10 +90,11 @@ __device__ __forceinline__ void seg_invert(T (&b)[E], int r, int gc, T *S, int &
         // column j become q b(p_j, l) + [row is not the pivot] b(i, l).
         // Column j is entry j % E of segment column j / E.
         const T q = isr ? inv : -(mcol * inv);
+        const T keep = isr ? T(0) : T(1);   // one select per step, a product per entry
         const bool inc = (gc == j / E);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const T sb = isr ? T(0) : b[e];
+            const T sb = E >= 4 ? b[e] * keep : (isr ? T(0) : b[e]);
             const T w = fma(q, prow[e], sb);
             if (e == j % E) {
                 b[e] = inc ? q : w;
