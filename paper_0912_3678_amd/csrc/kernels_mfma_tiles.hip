@@ -432,6 +432,33 @@ __device__ __forceinline__ void bwdt_body(const SolveArgs &a, int64_t part, int 
         if (G.hasR) cstore<T>(a.Y + sR * M + cy[j], act[j], xn[j], m);
         if (KIND == 1 && G.valid && part == 0) cstore<T>(a.Y + cy[j], act[j], cload<T>(a.Xsep + cn[j], act[j], m), m);
     }
+    if constexpr (KIND == 1) {
+        // x_k = t_k - Zh_k x_sL: the rows are independent, 4 / T at a time
+        // (all loads first)
+        constexpr int R = 4 / T;
+        for (int k0 = 0; k0 < G.len; k0 += R) {
+            QuadT<T> nzt[R];
+            Col c[R][CT];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const bool ok = k0 + i < G.len;
+                nzt[i] = qload<false, T>(rZ, (rel + (uint32_t)(k0 + i)) * BB, m, n);
+#pragma unroll
+                for (int j = 0; j < CT; ++j)
+                    c[i][j] = cload<T>(a.Y + (G.start + k0 + i) * M + cy[j], act[j] && ok, m);
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const bool ok = k0 + i < G.len;
+#pragma unroll
+                for (int j = 0; j < CT; ++j) {
+                    c[i][j] = mmc(qneg<T>(nzt[i]), xl[j], c[i][j]);   // t_k - Zh_k x_sL
+                    cstore<T>(a.Y + (G.start + k0 + i) * M + cy[j], act[j] && ok, c[i][j], m);
+                }
+            }
+        }
+        return;
+    }
     for (int k = G.len - 1; k >= 0; --k) {
         const int64_t g = G.start + k;
         const uint32_t row = rel + (uint32_t)k;
