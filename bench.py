@@ -93,32 +93,46 @@ def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
     return level_nb * (mm * w + 2 * m * 8 * nrhs)           # read Z, t; write x
 
 
-KERNEL_SOURCES = ("kernels_common.h", "kernels_gj.h", "kernels_seg.h", "kernels_seg.hip",
-                  "kernels_mfma.hip", "kernels_mfma_tiles.hip", "kernels_rows.hip", "kernels_solve.h",
-                  "kernels_solve.hip")
+# Sources each profiled kernel is built from: its recorded counters stay valid
+# while these files are unchanged.
+_COMMON = ("pf_internal.h", "kernels_common.h")
+KERNEL_SOURCES = {
+    "k_btri_mfma": _COMMON + ("kernels_gj.h", "kernels_mfma.hip"),
+    "k_btri_seg": _COMMON + ("kernels_gj.h", "kernels_seg.h", "kernels_seg.hip"),
+    "k_babd_seg": _COMMON + ("kernels_gj.h", "kernels_seg.h", "kernels_seg.hip"),
+    "k_fwd": _COMMON + ("kernels_solve.h", "kernels_solve.hip"),
+    "k_bwd": _COMMON + ("kernels_solve.h", "kernels_solve.hip"),
+    "k_btri_factor": _COMMON + ("kernels_rows.hip",),
+    "k_babd_factor": _COMMON + ("kernels_rows.hip",),
+}
+_ALL_SOURCES = _COMMON + ("kernels_gj.h", "kernels_seg.h", "kernels_seg.hip", "kernels_mfma.hip",
+                          "kernels_mfma_tiles.hip", "kernels_rows.hip", "kernels_solve.h",
+                          "kernels_solve.hip")
 
 
-def source_hash():
-    """Hash of the kernel sources the recorded counters belong to."""
+def source_hash(kernel_name):
+    """Hash of the sources the named kernel is built from."""
+    files = KERNEL_SOURCES.get(kernel_name.split("<")[0], _ALL_SOURCES)
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in files:
         with open(os.path.join(ROOT, "paper_0912_3678_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel_name):
-    """HBM traffic measured by rocprofv3 counters for the current kernel
-    source, if recorded (profiles/traffic.json), else None."""
+    """HBM traffic measured by rocprofv3 counters for the kernel's current
+    sources, if recorded (profiles/traffic.json), else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != source_hash():
+    ent = rec.get("kernels", {}).get(kernel_name)
+    if not ent or ent.get("source_hash") != source_hash(kernel_name):
         return None
-    return rec.get("kernels", {}).get(kernel_name)
+    return ent
 
 
 def main():
@@ -262,7 +276,9 @@ def run_bvp(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "alg_bytes_per_launch": int(dom_bytes),
                      "avg_launch_us": dom["avg_us"],
-                     "traffic": traffic},
+                     "traffic": traffic["total_bytes"] if traffic else None,
+                     "traffic_split": ({"fetch_bytes": traffic["fetch_bytes"],
+                                        "write_bytes": traffic["write_bytes"]} if traffic else None)},
         "kernels": kernels,
     }
 
