@@ -136,13 +136,17 @@ constexpr int kMapMfma32 = -2;
 // blocks inverted together, the chain on the matrix cores, one partition per
 // wave (kernels_mfma_tiles.hip)
 constexpr int kMapMfmaB16 = -3;
+// every level of an FP64 block tridiagonal matrix with m = 16: the m = 32
+// kernel's scheme with one tile per product (kernels_mfma_tiles.hip)
+constexpr int kMapMfma16 = -4;
 
 int seg_width(int M, int level, int kind, bool f32, const pf_opts &o)
 {
     if (o.flags & PF_FLAG_MAP_ROWS) return 0;
     if (M == 32 && kind == PF_BTRI && !f32) return kMapMfma32;
     if (level == 0 && o.lane_entries > 0) return seg_ok(M, o.lane_entries) ? o.lane_entries : 0;
-    if (M == 16 && kind == PF_BABD && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS)) return kMapMfmaB16;
+    if (M == 16 && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS))
+        return kind == PF_BABD ? kMapMfmaB16 : kMapMfma16;
     if (level == 0 && !(o.flags & PF_FLAG_MAP_SEGMENTS) && mfma_ok(kind, M, f32, false)) return kMapMfma;
     if (level == 0 && M == 8) return 2;   // 0.153 vs 0.156 ms per step with one entry
     for (int E = 1; E <= M; E <<= 1)
@@ -399,6 +403,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         e = prof_launch(F, true, 0, (int)l, s, [&] {
             if (L.seg == kMapMfma) return launch_mfma_factor(a, nullptr, s);
             if (L.seg == kMapMfma32) return launch_mfma32_factor(a, s);
+            if (L.seg == kMapMfma16) return launch_mfma16_factor(a, nullptr, s);
             if (L.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, nullptr, s);
             if (L.seg) return launch_seg_factor(L.kind, F->M, L.seg, L.f32, a, nullptr, s);
             return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
@@ -536,6 +541,7 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
         HIPCHK(prof_launch(F, true, 3, (int)l, s, [&] {
             if (lv.seg == kMapMfma) return launch_mfma_factor(a, &args[l], s);
             if (lv.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, &args[l], s);
+            if (lv.seg == kMapMfma16) return launch_mfma16_factor(a, &args[l], s);
             return launch_seg_factor(lv.kind, M, lv.seg, lv.f32, a, &args[l], s);
         }));
     }
@@ -1217,7 +1223,7 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
                            std::get<2>(kv.first) != 0, std::get<3>(kv.first) != 0,
                            std::get<4>(kv.first), work.size(), 0};
             const int gpw = bl.seg == kMapMfma   ? mfma_partitions_per_wg()
-                            : bl.seg == kMapMfma32 || bl.seg == kMapMfmaB16 ? 1
+                            : bl.seg == kMapMfma32 || bl.seg == kMapMfmaB16 || bl.seg == kMapMfma16 ? 1
                             : bl.seg             ? seg_partitions_per_wg(bl.M, bl.seg)
                                                  : groups_per_wg(bl.M);
             for (int i : kv.second) {
@@ -1293,6 +1299,8 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
                     ? launch_mfma32_factor_batch(bl.add, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfmaB16
                     ? launch_mfma_babd16_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+                : bl.seg == kMapMfma16
+                    ? launch_mfma16_factor_batch(bl.add, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
                                                    B->d_lwork + bl.work, bl.nwg, s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,

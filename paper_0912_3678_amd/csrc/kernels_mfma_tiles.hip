@@ -1,12 +1,13 @@
 // Partition-method kernels on the matrix cores for 16 x 16 and 32 x 32 blocks
-// (gfx950, FP64): the factor kernel for 32 x 32 blocks (block tridiagonal,
-// every level), the factor kernel for 16 x 16 blocks of the bidiagonal-plus-
-// corner form (every level, further below) and the forward sweep and back
+// (gfx950, FP64): the block tridiagonal factor kernel for both sizes (every
+// level), the factor kernel for 16 x 16 blocks of the bidiagonal-plus-corner
+// form (every level, further below) and the forward sweep and back
 // substitution for both sizes.
 //
-// One partition per wave.  The pivot blocks are inverted by the Gauss-Jordan
-// exchange steps of kernels_gj.h with sixteen entries per lane (lane (r, g)
-// holds row r, columns 16g .. 16g+15).  The six block products of a chain row
+// Block tridiagonal factor: one partition per wave.  The pivot blocks are
+// inverted by the Gauss-Jordan exchange steps of kernels_gj.h with sixteen
+// entries per lane for 32 x 32 blocks (lane (r, g) holds row r, columns
+// 16g .. 16g+15) and four for 16 x 16 blocks.  The six block products of a chain row
 // -- X = E A(g,g+1), Zh = E Z', D'_{k+1} = D[g+1] - A(g+1,g) X,
 // Z'_{k+1} = -A(g+1,g) Zh and the spike-row updates -- run on the matrix
 // cores as 2 x 2 tiles of 16 x 16, each tile product four
@@ -38,7 +39,6 @@ constexpr int kM = 32, kRS = kM + 2;   // factor kernel: block size, padded LDS 
 template <int T> struct QuadT {
     dv4 t[T][T];   // [I][J], entry q = row m + 4q of the tile, column n
 };
-using Quad = QuadT<2>;
 
 template <int T> __device__ __forceinline__ QuadT<T> qzero()
 {
@@ -75,9 +75,6 @@ __device__ __forceinline__ QuadT<T> mmq(const QuadT<T> &aT, const QuadT<T> &b, Q
                                                                      c.t[I][J], 0, 0, 0);
     return c;
 }
-__device__ __forceinline__ Quad mm32(const Quad &aT, const Quad &b, Quad c) { return mmq<2>(aT, b, c); }
-__device__ __forceinline__ Quad qzero() { return qzero<2>(); }
-__device__ __forceinline__ Quad qneg(const Quad &a) { return qneg<2>(a); }
 
 // quad of a column-major FP64 M x M block at byte offset base of resource rs
 // (TR: the quad of its transpose; on a row-major block the roles swap)
@@ -98,37 +95,23 @@ __device__ __forceinline__ QuadT<T> qload(__amdgpu_buffer_rsrc_t rs, uint32_t ba
             }
     return y;
 }
-// quad into a row-major factor block (tr: store the transpose's entries)
-template <bool TR>
-__device__ __forceinline__ void qstore(__amdgpu_buffer_rsrc_t rs, uint32_t base, bool keep,
-                                       const Quad &y, int m, int n)
+// quad into a row-major factor block (TR: store the transpose's entries)
+template <bool TR, int T>
+__device__ __forceinline__ void qstore_t(__amdgpu_buffer_rsrc_t rs, uint32_t base, bool keep,
+                                         const QuadT<T> &y, int m, int n)
 {
+    constexpr int M = 16 * T;
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < T; ++I)
 #pragma unroll
-        for (int J = 0; J < 2; ++J)
+        for (int J = 0; J < T; ++J)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = 16 * I + m + 4 * q, col = 16 * J + n;
-                const int e = TR ? col * kM + row : row * kM + col;
+                const int e = TR ? col * M + row : row * M + col;
                 buf_st(rs, keep ? base + (uint32_t)e * 8 : kOffNone, y.t[I][J][q]);
             }
 }
-// quad into a column-major FP64 block of global memory
-template <bool TR>
-__device__ __forceinline__ void qstore_g(double *p, const Quad &y, int m, int n)
-{
-#pragma unroll
-    for (int I = 0; I < 2; ++I)
-#pragma unroll
-        for (int J = 0; J < 2; ++J)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = 16 * I + m + 4 * q, col = 16 * J + n;
-                p[TR ? col + kM * row : row + kM * col] = y.t[I][J][q];
-            }
-}
-
 // quad (any T) into a column-major FP64 block of global memory
 template <bool TR, int T>
 __device__ __forceinline__ void qstore_gt(double *p, const QuadT<T> &y, int m, int n)
@@ -145,146 +128,8 @@ __device__ __forceinline__ void qstore_gt(double *p, const QuadT<T> &y, int m, i
             }
 }
 
-template <bool ADD>
-__device__ __forceinline__ void btri_mfma32_body(const LevelArgs &a, int64_t part, int lane,
-                                                 double *lds)
-{
-    constexpr int M = kM, E = 16;
-    constexpr size_t MM = (size_t)M * M;
-    constexpr uint32_t BB = MM * 8;
-    // inversion role: row r, columns 16g ..; matrix-core role: (m, n)
-    const int r = lane % M, gc = lane / M, c0 = gc * E;
-    const int m = lane >> 4, n = lane & 15;
-    double *S0 = lds;              // tableau
-    double *SE = S0 + M * kRS;     // E by logical rows; then D' handed over
-
-    const int64_t nb = a.nb;
-    const Geo G = geometry<0>(nb, a.p, part);
-    const int64_t gb = G.start > 0 ? G.start - 1 : 0;
-    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
-    const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
-    const auto rDa = buf_rsrc(ADD ? a.Dadd + gb * MM : a.D, ADD ? nr * BB : 0);
-    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
-    const auto rU = buf_rsrc(a.Up + gb * MM, nr1 * BB);
-    const auto rE = buf_rsrc((double *)a.E + gb * MM, nr * BB);
-    const auto rR = buf_rsrc((double *)a.R + gb * MM, nr * BB);
-    const auto rZ = buf_rsrc((double *)a.Z + gb * MM, nr * BB);
-    const auto rX = buf_rsrc((double *)a.X + gb * MM, nr * BB);
-    const uint32_t rel = (uint32_t)(G.start - gb);
-
-    // D'_1 in the inversion layout
-    double d[E];
-    {
-        const uint32_t o = rel * BB + (uint32_t)(r + M * c0) * 8;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            d[e] = buf_ld(rD, o + (uint32_t)(e * M * 8));
-            if constexpr (ADD) d[e] += buf_ld(rDa, o + (uint32_t)(e * M * 8));
-        }
-    }
-    // Z'_1 = A(g_1, sL), R_1^T = A(sL, g_1)^T, alpha_1^T
-    Quad z = qzero(), rT = qzero(), a1 = qzero(), dq = qzero();
-    if (G.hasL) {
-        z = qload<false>(rL, (rel - 1) * BB, m, n);
-        rT = qload<true>(rU, (rel - 1) * BB, m, n);
-    }
-    unsigned long long bad = ~0ull;
-
-    for (int k = 0; k < G.len; ++k) {
-        const uint32_t row = rel + (uint32_t)k;
-        // this row's operands, requested before the inversion
-        const Quad up = qload<false>(rU, row * BB, m, n);     // A(g,g+1)
-        const Quad loT = qload<true>(rL, row * BB, m, n);     // A(g+1,g)^T
-        Quad dn = qload<false>(rD, (row + 1) * BB, m, n);     // D[g+1]
-        if constexpr (ADD) {
-            const Quad da = qload<false>(rDa, (row + 1) * BB, m, n);
-#pragma unroll
-            for (int I = 0; I < 2; ++I)
-#pragma unroll
-                for (int J = 0; J < 2; ++J) dn.t[I][J] += da.t[I][J];
-        }
-
-        // E_k = D'_k^{-1}
-        int sigma = 0, pc[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) pc[e] = 0;
-        bool sing = false;
-        seg_invert<M, E, double>(d, r, gc, S0, sigma, pc, sing);
-        const unsigned long long code = status_code(a.level, G.start + k);
-        bad = (sing && code < bad) ? code : bad;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            SE[sigma * kRS + pc[e]] = d[e];
-            buf_st(rE, row * BB + (uint32_t)(sigma * M + pc[e]) * 8, d[e]);
-        }
-        wave_sync();
-        Quad eT;   // quad of E^T: E(16I' + n, 16K' + m + 4q) at tile [K'][I']
-#pragma unroll
-        for (int K = 0; K < 2; ++K)
-#pragma unroll
-            for (int I = 0; I < 2; ++I)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) eT.t[K][I][q] = SE[(16 * I + n) * kRS + 16 * K + m + 4 * q];
-
-        const Quad x = mm32(eT, up, qzero());    // X_k = E_k A(g,g+1)
-        const Quad zh = mm32(eT, z, qzero());    // Zh_k = E_k Z'_k
-        qstore<false>(rX, row * BB, true, x, m, n);
-        qstore<false>(rZ, row * BB, true, zh, m, n);
-        qstore<true>(rR, row * BB, G.hasL, rT, m, n);   // R_k (row-major) from R_k^T
-        const Quad nlo = qneg(loT);
-        dq = mm32(nlo, x, dn);                   // D'_{k+1} = D[g+1] - A(g+1,g) X_k
-        z = mm32(nlo, zh, qzero());              // Z'_{k+1} = -A(g+1,g) Zh_k
-        a1 = mm32(qneg(zh), rT, a1);             // alpha_1^T -= Zh_k^T R_k^T
-        rT = mm32(qneg(x), rT, qzero());         // R_{k+1}^T = -X_k^T R_k^T
-
-        // D'_{k+1} to the inversion layout
-        wave_sync();
-#pragma unroll
-        for (int I = 0; I < 2; ++I)
-#pragma unroll
-            for (int J = 0; J < 2; ++J)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) SE[(16 * I + m + 4 * q) * kRS + 16 * J + n] = dq.t[I][J][q];
-        wave_sync();
-        lds_row<E, double>(d, SE + r * kRS + c0);
-        wave_sync();
-    }
-    if (bad != ~0ull) atomicMin(a.status, bad);
-    if (G.hasR) {
-        qstore_g<false>(a.nD + part * MM, dq, m, n);                      // D[sR] + alpha_2
-        if (G.hasL) qstore_g<false>(a.nLo + (part - 1) * MM, z, m, n);    // beta
-    }
-    if (G.hasL) {
-        qstore_g<true>(a.nDadd + (part - 1) * MM, a1, m, n);              // alpha_1
-        if (G.hasR) qstore_g<true>(a.nUp + (part - 1) * MM, rT, m, n);    // gamma
-    }
-}
-
-template <bool ADD>
-__global__ __launch_bounds__(WG) void k_btri_mfma32(LevelArgs a)
-{
-    __shared__ __align__(16) double lds[2 * kM * kRS];
-    btri_mfma32_body<ADD>(a, blockIdx.x, threadIdx.x, lds);
-}
-// batched: workgroup w serves table entry work[w].x, partition work[w].y
-template <bool ADD>
-__global__ __launch_bounds__(WG) void kb_btri_mfma32(const LevelArgs *tab, const int4 *work)
-{
-    __shared__ __align__(16) double lds[2 * kM * kRS];
-    const int4 w = work[blockIdx.x];
-    const LevelArgs a = tab[w.x];
-    btri_mfma32_body<ADD>(a, w.y, threadIdx.x, lds);
-}
-
-// ---------------------------------------------------------------------------
-// Forward sweep and back substitution for M = 16 and 32 and FP64 factors
-// (any factor kernel's row-major E, X, Zh, R), the right-hand sides in column
-// tiles of 16: a tile's M x 16 block of one block row sits in the quad layout
-// (lane (m, n): rows 16I + m + 4q of column n).  Every block product
-// is a chain of v_mfma_f64_16x16x4f64 whose left operand is a factor block's
-// transpose quad, loaded straight from memory, so the factors of a block row
-// are read once per CT tiles (the row kernels read them once per four
-// columns).  KIND: 0 block tridiagonal, 1 bidiagonal plus corner.
+// A column tile: an M x 16 block of right-hand sides of one block row in the
+// quad layout (lane (m, n): rows 16I + m + 4q of column n).
 template <int T> struct ColT {
     dv4 t[T];   // [I], entry q = row 16I + m + 4q, column n of the tile
 };
@@ -335,6 +180,187 @@ template <int T> __device__ __forceinline__ ColT<T> cadd(ColT<T> a, const ColT<T
     return a;
 }
 
+// RHS (one tile, M = 16): up to 16 right-hand sides swept forward in the same
+// pass -- t_k = E_k f'_k, f'_{k+1} = f[g+1] - A(g+1,g) t_k, g_sL -= R_k t_k.
+template <int T, bool ADD, bool RHS = false>
+__device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveArgs &sv,
+                                                int64_t part, int lane, double *lds)
+{
+    static_assert(!RHS || T == 1, "the fused forward sweep is built for 16 x 16 blocks");
+    using Q = QuadT<T>;
+    constexpr int M = 16 * T, E = T == 1 ? 4 : 16, RS = M + kPad<double>;
+    constexpr size_t MM = (size_t)M * M;
+    constexpr uint32_t BB = MM * 8;
+    // inversion role: row r, columns 16g ..; matrix-core role: (m, n)
+    const int r = lane % M, gc = lane / M, c0 = gc * E;
+    const int m = lane >> 4, n = lane & 15;
+    double *S0 = lds;              // tableau
+    double *SE = S0 + M * RS;     // E by logical rows; then D' handed over
+
+    const int64_t nb = a.nb;
+    const Geo G = geometry<0>(nb, a.p, part);
+    const int64_t gb = G.start > 0 ? G.start - 1 : 0;
+    const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
+    const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
+    const auto rDa = buf_rsrc(ADD ? a.Dadd + gb * MM : a.D, ADD ? nr * BB : 0);
+    const auto rL = buf_rsrc(a.Lo + gb * MM, nr1 * BB);
+    const auto rU = buf_rsrc(a.Up + gb * MM, nr1 * BB);
+    const auto rE = buf_rsrc((double *)a.E + gb * MM, nr * BB);
+    const auto rR = buf_rsrc((double *)a.R + gb * MM, nr * BB);
+    const auto rZ = buf_rsrc((double *)a.Z + gb * MM, nr * BB);
+    const auto rX = buf_rsrc((double *)a.X + gb * MM, nr * BB);
+    const uint32_t rel = (uint32_t)(G.start - gb);
+
+    // D'_1 in the inversion layout
+    double d[E];
+    {
+        const uint32_t o = rel * BB + (uint32_t)(r + M * c0) * 8;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            d[e] = buf_ld(rD, o + (uint32_t)(e * M * 8));
+            if constexpr (ADD) d[e] += buf_ld(rDa, o + (uint32_t)(e * M * 8));
+        }
+    }
+    // right-hand-side column n of the tiles; f'_1 = f[g_1], g_sL
+    const bool act = RHS && n < sv.nrhs;
+    const bool fadd = RHS && sv.Fadd != nullptr;
+    const int64_t cf = (int64_t)(act ? n : 0) * sv.ldf, cy = (int64_t)(act ? n : 0) * sv.ldy;
+    const int64_t cn = (int64_t)(act ? n : 0) * sv.ldn;
+    auto load_f = [&](int64_t g, bool ok) {
+        ColT<1> c = cload<1>(sv.F + g * M + cf, act && ok, m);
+        return fadd ? cadd<1>(c, cload<1>(sv.Fadd + g * M + cf, act && ok, m)) : c;
+    };
+    ColT<1> fp = czero<1>(), gl = czero<1>();
+    if constexpr (RHS) fp = load_f(G.start, G.valid);
+    // Z'_1 = A(g_1, sL), R_1^T = A(sL, g_1)^T, alpha_1^T
+    Q z = qzero<T>(), rT = qzero<T>(), a1 = qzero<T>(), dq = qzero<T>();
+    if (G.hasL) {
+        z = qload<false, T>(rL, (rel - 1) * BB, m, n);
+        rT = qload<true, T>(rU, (rel - 1) * BB, m, n);
+    }
+    unsigned long long bad = ~0ull;
+
+    for (int k = 0; k < G.len; ++k) {
+        const uint32_t row = rel + (uint32_t)k;
+        // this row's operands, requested before the inversion
+        const Q up = qload<false, T>(rU, row * BB, m, n);     // A(g,g+1)
+        const Q loT = qload<true, T>(rL, row * BB, m, n);     // A(g+1,g)^T
+        Q dn = qload<false, T>(rD, (row + 1) * BB, m, n);     // D[g+1]
+        if constexpr (ADD) {
+            const Q da = qload<false, T>(rDa, (row + 1) * BB, m, n);
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J) dn.t[I][J] += da.t[I][J];
+        }
+        ColT<1> fn = czero<1>();
+        if constexpr (RHS) fn = load_f(G.start + k + 1, G.start + k + 1 < nb);   // f[g+1]
+
+        // E_k = D'_k^{-1}
+        int sigma = 0, pc[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) pc[e] = 0;
+        bool sing = false;
+        seg_invert<M, E, double>(d, r, gc, S0, sigma, pc, sing);
+        const unsigned long long code = status_code(a.level, G.start + k);
+        bad = (sing && code < bad) ? code : bad;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            SE[sigma * RS + pc[e]] = d[e];
+            buf_st(rE, row * BB + (uint32_t)(sigma * M + pc[e]) * 8, d[e]);
+        }
+        wave_sync();
+        Q eT;   // quad of E^T: E(16I' + n, 16K' + m + 4q) at tile [K'][I']
+#pragma unroll
+        for (int K = 0; K < T; ++K)
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) eT.t[K][I][q] = SE[(16 * I + n) * RS + 16 * K + m + 4 * q];
+
+        const Q x = mmq<T>(eT, up, qzero<T>());    // X_k = E_k A(g,g+1)
+        const Q zh = mmq<T>(eT, z, qzero<T>());    // Zh_k = E_k Z'_k
+        qstore_t<false, T>(rX, row * BB, true, x, m, n);
+        qstore_t<false, T>(rZ, row * BB, true, zh, m, n);
+        qstore_t<true, T>(rR, row * BB, G.hasL, rT, m, n);   // R_k (row-major) from R_k^T
+        const Q nlo = qneg<T>(loT);
+        dq = mmq<T>(nlo, x, dn);                   // D'_{k+1} = D[g+1] - A(g+1,g) X_k
+        z = mmq<T>(nlo, zh, qzero<T>());              // Z'_{k+1} = -A(g+1,g) Zh_k
+        if constexpr (RHS) {
+            const ColT<1> tk = mmc<1>(eT, fp, czero<1>());             // t_k = E_k f'_k
+            cstore<1>(sv.Y + (G.start + k) * M + cy, act, tk, m);
+            gl = mmc<1>(qneg<1>(rT), tk, gl);                         // g_sL -= R_k t_k
+            fp = mmc<1>(nlo, tk, fn);                                 // f'_{k+1} = f[g+1] - A(g+1,g) t_k
+        }
+        a1 = mmq<T>(qneg<T>(zh), rT, a1);             // alpha_1^T -= Zh_k^T R_k^T
+        rT = mmq<T>(qneg<T>(x), rT, qzero<T>());         // R_{k+1}^T = -X_k^T R_k^T
+
+        // D'_{k+1} to the inversion layout
+        wave_sync();
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) SE[(16 * I + m + 4 * q) * RS + 16 * J + n] = dq.t[I][J][q];
+        wave_sync();
+        lds_row<E, double>(d, SE + r * RS + c0);
+        wave_sync();
+    }
+    if (bad != ~0ull) atomicMin(a.status, bad);
+    if (G.hasR) {
+        qstore_gt<false, T>(a.nD + part * MM, dq, m, n);                      // D[sR] + alpha_2
+        if (G.hasL) qstore_gt<false, T>(a.nLo + (part - 1) * MM, z, m, n);    // beta
+    }
+    if (G.hasL) {
+        qstore_gt<true, T>(a.nDadd + (part - 1) * MM, a1, m, n);              // alpha_1
+        if (G.hasR) qstore_gt<true, T>(a.nUp + (part - 1) * MM, rT, m, n);    // gamma
+    }
+    if constexpr (RHS) {
+        if (G.hasR) cstore<1>(sv.nF + part * M + cn, act, fp, m);            // f[sR] - A(sR,g_n) t_n
+        if (G.hasL) cstore<1>(sv.nFadd + (part - 1) * M + cn, act, gl, m);   // -sum R_k t_k
+    }
+}
+
+template <bool ADD>
+__global__ __launch_bounds__(WG) void k_btri_mfma32(LevelArgs a)
+{
+    __shared__ __align__(16) double lds[2 * kM * kRS];
+    btri_mfmat_body<2, ADD>(a, SolveArgs{}, blockIdx.x, threadIdx.x, lds);
+}
+template <bool ADD, bool RHS>
+__global__ __launch_bounds__(WG) void k_btri_mfma16(LevelArgs a, SolveArgs sv)
+{
+    __shared__ __align__(16) double lds[2 * 16 * (16 + kPad<double>)];
+    btri_mfmat_body<1, ADD, RHS>(a, sv, blockIdx.x, threadIdx.x, lds);
+}
+// batched: workgroup w serves table entry work[w].x, partition work[w].y
+template <bool ADD>
+__global__ __launch_bounds__(WG) void kb_btri_mfma32(const LevelArgs *tab, const int4 *work)
+{
+    __shared__ __align__(16) double lds[2 * kM * kRS];
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    btri_mfmat_body<2, ADD>(a, SolveArgs{}, w.y, threadIdx.x, lds);
+}
+template <bool ADD>
+__global__ __launch_bounds__(WG) void kb_btri_mfma16(const LevelArgs *tab, const int4 *work)
+{
+    __shared__ __align__(16) double lds[2 * 16 * (16 + kPad<double>)];
+    const int4 w = work[blockIdx.x];
+    const LevelArgs a = tab[w.x];
+    btri_mfmat_body<1, ADD>(a, SolveArgs{}, w.y, threadIdx.x, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Forward sweep and back substitution for M = 16 and 32 and FP64 factors
+// (any factor kernel's row-major E, X, Zh, R), the right-hand sides in column
+// tiles of 16: a tile's M x 16 block of one block row sits in the quad layout
+// (lane (m, n): rows 16I + m + 4q of column n).  Every block product
+// is a chain of v_mfma_f64_16x16x4f64 whose left operand is a factor block's
+// transpose quad, loaded straight from memory, so the factors of a block row
+// are read once per CT tiles (the row kernels read them once per four
+// columns).  KIND: 0 block tridiagonal, 1 bidiagonal plus corner.
 template <int M, int KIND, int CT, bool ADD>
 __device__ __forceinline__ void fwdt_body(const SolveArgs &a, int64_t part, int cg, int lane)
 {
@@ -517,15 +543,6 @@ constexpr int kBRS = 16 + kPad<double>;             // padded LDS row stride
 constexpr int kBSL = 16 * kBRS;                     // one block in LDS
 constexpr uint32_t kOffRowNone = 0xFFFFFF80u;       // 128 bytes past every resource
 
-// quad (T = 1) into a row-major factor block
-__device__ __forceinline__ void qstore16(__amdgpu_buffer_rsrc_t rs, uint32_t base, bool keep,
-                                         const QuadT<1> &y, int m, int n)
-{
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        buf_st(rs, keep ? base + (uint32_t)((m + 4 * q) * 16 + n) * 8 : kOffNone, y.t[0][0][q]);
-}
-
 template <bool RHS>
 __device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const SolveArgs &sv,
                                                  int64_t part, int lane, double *lds)
@@ -613,7 +630,7 @@ __device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const Solve
                 loN = load_lo(k0 + i + 1);
                 fnN = load_fn(k0 + i + 1);
                 const QuadT<1> zh = mmq<1>(eT, z, qzero<1>());   // Zh_k = E_k Z'_k
-                qstore16(rZ, row * BB, true, zh, m, n);
+                qstore_t<false, 1>(rZ, row * BB, true, zh, m, n);
                 z = mmq<1>(nlo, zh, qzero<1>());                  // Z'_{k+1} = -A(g+1,g) Zh_k
                 if constexpr (RHS) {
                     const ColT<1> tk = mmc<1>(eT, fp, czero<1>());   // t_k = E_k f'_k
@@ -691,6 +708,30 @@ hipError_t launch_mfma_babd16_factor_batch(const LevelArgs *tab, const int4 *wor
 {
     if (nwg <= 0) return hipSuccess;
     launch_k(kb_babd_mfma16, dim3(nwg), dim3(WG), s, tab, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma16_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s)
+{
+    if (a.p < 1) return hipErrorInvalidValue;
+    if (sv && (sv->nrhs < 1 || sv->nrhs > 16)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)a.p);
+    if (sv) {
+        if (a.Dadd) launch_k(k_btri_mfma16<true, true>, grid, dim3(WG), s, a, *sv);
+        else launch_k(k_btri_mfma16<false, true>, grid, dim3(WG), s, a, *sv);
+    } else {
+        if (a.Dadd) launch_k(k_btri_mfma16<true, false>, grid, dim3(WG), s, a, SolveArgs{});
+        else launch_k(k_btri_mfma16<false, false>, grid, dim3(WG), s, a, SolveArgs{});
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma16_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
+                                      hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    if (add) launch_k(kb_btri_mfma16<true>, dim3(nwg), dim3(WG), s, tab, work);
+    else launch_k(kb_btri_mfma16<false>, dim3(nwg), dim3(WG), s, tab, work);
     return hipGetLastError();
 }
 

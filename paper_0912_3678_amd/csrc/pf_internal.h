@@ -85,6 +85,10 @@ hipError_t launch_mfma_factor_batch(const LevelArgs *tab, const int4 *work, int 
 hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s);
 hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
                                       hipStream_t s);
+// the same for M = 16 (sv: also sweep 1..16 right-hand sides forward)
+hipError_t launch_mfma16_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
+hipError_t launch_mfma16_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
+                                      hipStream_t s);
 // matrix-core factor kernel for FP64 bidiagonal-plus-corner levels with M = 16
 // (any level; one partition per workgroup; sv: also sweep 1..16 right-hand
 // sides forward)

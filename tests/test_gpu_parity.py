@@ -163,6 +163,53 @@ def test_matrix_core_32(nb, p, m):
     del keep
 
 
+@pytest.mark.parametrize("nb,p", [(2, 1), (3, 1), (9, 4), (100, 0), (1001, 0), (4099, 0),
+                                  (600, 299), (257, 5)])
+@pytest.mark.parametrize("m,nrhs", [(16, 1), (16, 20), (11, 3)])
+def test_matrix_core_16(nb, p, m, nrhs):
+    """The m = 16 block tridiagonal matrix-core factor kernel (FP64, every
+    level, the m = 32 kernel's scheme with one tile per product and four
+    entries per lane in the inversion) gives the oracle's solution and
+    agrees with the segment mapping; padded blocks (m = 11) and pf_factor_solve
+    included."""
+    import torch
+    seed = 1900 + nb + 3 * p + m + nrhs
+    s = wl.random_btri(nb, m, seed=seed)
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((nb * m, nrhs))
+    A, keep = G.to_device(s)
+    xs = {}
+    for name, flags in (("mfma", 0), ("segments", pf.PF_FLAG_MAP_SEGMENTS)):
+        F = pf.pf_factor(A, pf.make_opts(partitions=p, flags=flags))
+        try:
+            fd = G.rhs_to_device(f)
+            x = torch.full_like(fd, np.nan)
+            _say("btri m", m, "nb", nb, "p", p, "nrhs", nrhs, name)
+            info = pf.pf_solve(F, fd, x)
+            assert info.status == 0
+            xs[name] = x.cpu().numpy().T
+            G.check(s, xs[name], f=f, tag=f"{name} btri m={m} nb={nb} p={p}")
+            x2 = torch.full_like(fd, np.nan)
+            assert pf.pf_factor_solve(F, fd, x2).status == 0
+            G.check(s, x2.cpu().numpy().T, f=f, tag=f"{name} factor_solve m={m} nb={nb} p={p}")
+        finally:
+            pf.pf_destroy(F)
+    scale = np.abs(xs["segments"]).max()
+    assert np.abs(xs["mfma"] - xs["segments"]).max() <= 1e-11 * scale
+    del keep
+
+
+def test_singular_pivot_btri16():
+    """An exactly singular first pivot block is reported by the m = 16 block
+    tridiagonal matrix-core kernel with its level and block."""
+    s = wl.random_btri(64, 16, seed=6)
+    s.D[0] = 0.0
+    s.Up[0] = 0.0
+    x, info, _ = G.gpu_solve(s, pf.make_opts(partitions=4))
+    assert info.status == pf.PF_ESINGULAR
+    assert info.bad_level == 0 and info.bad_block == 0
+
+
 @pytest.mark.parametrize("nb,p", [(3, 1), (5, 2), (9, 4), (40, 3), (41, 3), (300, 7), (1000, 0),
                                   (4097, 0), (1001, 500)])
 @pytest.mark.parametrize("m,nrhs", [(16, 1), (16, 16), (12, 5), (16, 17)])
