@@ -124,10 +124,11 @@ constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chai
 // or rows (0).  One entry per lane (E = 1) spreads a chain row over M*M
 // lanes and gives the lowest latency per row, which bounds the reduced
 // levels; at level 0 (many partitions) fewer, wider lanes spend fewer
-// instructions per partition.  m = 16 uses four entries per lane (one wave
-// per partition), m = 32 the row mapping.  The finest level of an FP64 block
-// tridiagonal matrix with m = 8 runs its block products on the matrix cores
-// (kMapMfma), unless a mapping is asked for.
+// instructions per partition.  With FP32 factors m = 16 uses four entries
+// per lane (one wave per partition) and m = 32 the row mapping.  In FP64 the
+// finest level of a block tridiagonal matrix with m = 8 (kMapMfma) and every
+// level with m = 16 or 32 run their block products on the matrix cores,
+// unless a mapping is asked for.
 constexpr int kMapMfma = -1;
 // every level of an FP64 block tridiagonal matrix with m = 32: matrix-core
 // products, one partition per wave (kernels_mfma_tiles.hip)
