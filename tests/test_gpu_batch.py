@@ -62,7 +62,8 @@ def _alone(A, fd, opts):
 MIXED = [("btri", 8, 1000, 1, 11), ("btri", 4, 77, 3, 12), ("babd", 8, 300, 1, 13),
          ("btri", 16, 50, 5, 14), ("btri", 3, 41, 2, 15), ("babd", 4, 9, 1, 16),
          ("btri", 1, 4099, 1, 17), ("btri", 8, 2, 1, 18), ("babd", 6, 33, 4, 19),
-         ("btri", 8, 513, 0, 20), ("btri", 32, 20, 2, 21), ("babd", 2, 3, 1, 22)]
+         ("btri", 8, 513, 0, 20), ("btri", 32, 20, 2, 21), ("babd", 2, 3, 1, 22),
+         ("babd", 16, 400, 2, 23), ("babd", 12, 50, 1, 24), ("btri", 13, 300, 3, 25)]
 
 
 def _check_against_alone_and_oracle(systems, mats, fs, xs, opts, tag):
