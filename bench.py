@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["bvp", "babd", "batch", "serving"], default="bvp")
+    ap.add_argument("--workload", choices=["bvp", "babd", "batch", "serving", "ivp"], default="bvp")
     ap.add_argument("--prec", choices=["fp64", "fp32ir"], default=None,
                     help="babd / batch: precision (babd default fp32ir, batch default fp64)")
     ap.add_argument("--count", type=int, default=0,
@@ -141,7 +141,8 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the method's multi-GPU "
               "sharding is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
-    run = {"bvp": run_bvp, "babd": run_babd, "batch": run_batch, "serving": run_serving}
+    run = {"bvp": run_bvp, "babd": run_babd, "batch": run_batch, "serving": run_serving,
+           "ivp": run_ivp}
     out = run[args.workload](args)
     print(json.dumps(out), flush=True)
 
@@ -365,6 +366,97 @@ def _profile_dominant(pf, F, step, levels, m, f32, steps):
         kernels.append({"phase": ph, "level": lvl, "nb": lnb, "p": lp, "avg_us": round(avg * 1e3, 2),
                         "alg_MB": round(b / 1e6, 3), "GBps": round(b / (avg * 1e-3) / 1e9, 1)})
     return kernels, max(kernels, key=lambda k: k["avg_us"])
+
+
+def run_ivp(args):
+    """Time-parallel linear IVP (Sec. 3): y' = L y + g(t) on [0, 1], m = 8,
+    N = 65536 trapezoid steps over a coarse mesh of p = 4096 sub-intervals of
+    16 steps.  One step = one pf_ivp_solve call: build the eq. (My) system on
+    the device, factor and solve it with the sub-intervals as partitions,
+    free it (the call synchronizes).  Checked against the oracle's sequential
+    stepping of the same discretization."""
+    import numpy as np
+    import torch
+
+    from paper_0912_3678_amd import pf
+    from paper_0912_3678_amd import workloads as wl
+
+    m, steps = args.m, args.N
+    p = args.partitions or 4096
+    if steps % p:
+        raise SystemExit(f"--N {steps} is not a multiple of the {p} sub-intervals")
+    Nsub = steps // p
+    dev = torch.device("cuda", 0)
+    L, g, y0, t0, T = wl.ivp_problem(m, p, Nsub, seed=wl.seed_for(6))
+    Ld = torch.tensor(np.ascontiguousarray(L.T).reshape(-1), dtype=torch.float64, device=dev)
+    gd = torch.tensor(g.reshape(-1), dtype=torch.float64, device=dev)
+    y0d = torch.tensor(y0, dtype=torch.float64, device=dev)
+    y = torch.empty(((steps + 1) * m,), dtype=torch.float64, device=dev)
+    opts = pf.make_opts(block_rows=args.block_rows, coarse_rows=args.coarse_rows)
+    infos = []
+
+    def step():
+        infos.append(pf.pf_ivp_solve(m, Ld, t0, T, p, Nsub, gd, y0d, y, opts=opts))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    per = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        step()
+        per.append((time.perf_counter() - t1) * 1e3)
+    wall = (time.perf_counter() - t_start) * 1e3 / args.steps
+    # the same system built once and kept: repeated pf_factor_solve on a handle
+    h = (T - t0) / steps
+    nb = steps + 1
+    D = torch.empty((nb * m * m,), dtype=torch.float64, device=dev)
+    Lo = torch.empty(((nb - 1) * m * m,), dtype=torch.float64, device=dev)
+    C = torch.empty((m * m,), dtype=torch.float64, device=dev)
+    f = torch.empty((nb * m,), dtype=torch.float64, device=dev)
+    pf.pf_ivp_trapezoid_system(m, steps, Ld, h, gd, y0d, D, Lo, C, f)
+    y2 = torch.empty_like(y)
+    F = pf.pf_factor(pf.make_matrix(pf.PF_BABD, m, nb, D, Lo, None, C),
+                     pf.make_opts(partitions=p, block_rows=args.block_rows,
+                                  coarse_rows=args.coarse_rows))
+    for _ in range(args.warmup):
+        pf.pf_factor_solve(F, f.view(1, -1), y2.view(1, -1), want_info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        pf.pf_factor_solve(F, f.view(1, -1), y2.view(1, -1), want_info=False)
+    torch.cuda.synchronize()
+    kept_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    pf.pf_destroy(F)
+    kept_same = bool(torch.equal(y, y2))
+    import oracle
+    t1 = time.perf_counter()
+    ref = oracle.ivp_trapezoid(L, h, g, y0)
+    seq_s = time.perf_counter() - t1
+    rel = float(np.abs(y.cpu().numpy().reshape(steps + 1, m) - ref).max() / np.abs(ref).max())
+    n = (steps + 1) * m
+    ok = rel <= 1e-11 and all(i.status == 0 for i in infos)
+    out = {
+        "metric": "unknowns solved/sec (time-parallel IVP, trapezoid rule)",
+        "value": n / (wall * 1e-3) if ok else 0.0,
+        "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "ivp_trapezoid", "m": m, "steps": steps, "subintervals": p,
+                   "steps_per_subinterval": Nsub, "unknowns": n,
+                   "step": "pf_ivp_solve (device build + factor-and-solve + free, synchronized)"},
+        "rel_err_vs_sequential": rel,
+        "kept_handle_ms_per_step": kept_ms, "kept_handle_same_result": kept_same,
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = {"value": n / seq_s, "unit": "unknowns/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"sequential trapezoid stepping of the full problem "
+                                         f"({steps} steps, one numpy solve per step), one run"}
+    return out
 
 
 def run_babd(args):

@@ -294,6 +294,38 @@ int pf_abd_to_btri(int32_t m, int64_t N, int32_t qa, const double *Ba, const dou
                    const double *R, const double *Bb, double *D, double *Lo, double *Up,
                    void *stream);
 
+/* ---- linear initial value problems (Sec. 3) -----------------------------
+ * y' = L y + g(t), y(t0) = y0 (L constant, m x m), discretized by the
+ * trapezoid rule with `steps` steps of size h: the lower block bidiagonal
+ * system of eq. (My) in the bidiagonal-plus-corner form with a zero corner:
+ * D[0] = I, D[n] = I - h/2 L (n >= 1), Lo[n-1] = -(I + h/2 L), C = 0,
+ * f[0] = y0, f[n] = h/2 (g_{n-1} + g_n).  L: device, column-major; g:
+ * device, steps+1 samples g(t0 + n h) of m entries each (sample n at
+ * g + n*m); y0: device, m entries.  Outputs (device, caller-allocated): D
+ * steps+1 blocks, Lo steps blocks, C one block, f (steps+1)*m entries.
+ * Returns 0, -k for invalid argument k, or PF_EHIP. */
+int pf_ivp_trapezoid_system(int32_t m, int64_t steps, const double *L, double h, const double *g,
+                            const double *y0, double *D, double *Lo, double *C, double *f,
+                            void *stream);
+
+/* Time-parallel solution of that IVP on [t0, T] over a coarse mesh of p
+ * sub-intervals of N steps each (Sec. 3): h = (T - t0) / (p N), and the p
+ * partitions of the factorization are the sub-intervals.  The finest level
+ * then solves the p local problems with zero initial values (eq. (D)) and
+ * their fundamental blocks w_i, the reduced system gives the initial values
+ * y_{0i} (eqs. (redsys), (recur); solved by the same method, recursively,
+ * rather than by the sequential recursion), and the back substitution is the
+ * parallel update (eq. (pups)).  g, y0 as for pf_ivp_trapezoid_system (p*N+1
+ * samples); y: device output of p*N+1 vectors (y_n at y + n*m).  N >= 2.
+ * opts may be NULL (its partitions field is replaced by p; PF_FP64 or
+ * PF_FP32_IR).  Allocates the system arrays on `stream` (stream-ordered) and
+ * frees them before returning; synchronizes `stream`.  info may be NULL.
+ * Returns 0, -k for invalid argument k, PF_ENOMEM, PF_EHIP or the numeric
+ * status (PF_ESINGULAR). */
+int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int64_t N,
+                 const double *g, const double *y0, double *y, const pf_opts *opts, void *stream,
+                 pf_info *info);
+
 /* ---- serving: continuous batching under a device-memory budget ----------
  * A request factors A and solves for f (or solves with a factor kept from an
  * earlier request) into x.  Requests are admitted in arrival order as memory

@@ -313,3 +313,22 @@ def schur_complement(A: np.ndarray, m: int, sep_blocks, f=None):
     f = np.asarray(f, dtype=np.float64)
     g = f[sep] - AsI @ np.linalg.solve(AII, f[interior])
     return S, g
+
+
+def ivp_trapezoid(L, h, g, y0):
+    """The trapezoid discretization of y' = L y + g(t), y(t0) = y0, solved in
+    the sequential fashion of Sec. 3 (before eq. (D)): one step at a time,
+    y_0 = y0 and (I - h/2 L) y_n = (I + h/2 L) y_{n-1} + h/2 (g_{n-1} + g_n).
+    L: (m, m); g: (steps+1, m) samples g(t0 + n h); y0: (m,).  Returns the
+    (steps+1, m) array of y_n."""
+    L = np.asarray(L, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = L.shape[0]
+    eye = np.eye(m)
+    left = eye - 0.5 * h * L
+    right = eye + 0.5 * h * L
+    y = np.empty_like(g)
+    y[0] = np.asarray(y0, dtype=np.float64)
+    for n in range(1, g.shape[0]):
+        y[n] = np.linalg.solve(left, right @ y[n - 1] + 0.5 * h * (g[n - 1] + g[n]))
+    return y

@@ -1125,6 +1125,77 @@ int pf_band_to_btri(int64_t n, int32_t kl, int32_t ku, const double *ab, int64_t
                    hipSuccess ? 0 : PF_EHIP;
 }
 
+int pf_ivp_trapezoid_system(int32_t m, int64_t steps, const double *L, double h, const double *g,
+                            const double *y0, double *D, double *Lo, double *C, double *f,
+                            void *stream)
+{
+    if (m < 1) return -1;
+    if (steps < 1) return -2;
+    if (!L) return -3;
+    if (!(h > 0.0) || !std::isfinite(h)) return -4;
+    if (!g) return -5;
+    if (!y0) return -6;
+    if (!D) return -7;
+    if (!Lo) return -8;
+    if (!C) return -9;
+    if (!f) return -10;
+    return launch_ivp_trapezoid(m, steps, L, h, g, y0, D, Lo, C, f, (hipStream_t)stream) ==
+                   hipSuccess ? 0 : PF_EHIP;
+}
+
+int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int64_t N,
+                 const double *g, const double *y0, double *y, const pf_opts *opts, void *stream,
+                 pf_info *info)
+{
+    if (m < 1 || m > 32) return -1;
+    if (!L) return -2;
+    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0)) return -4;
+    if (p < 1) return -5;
+    if (N < 2) return -6;
+    if (!g) return -7;
+    if (!y0) return -8;
+    if (!y) return -9;
+    const int64_t steps = p * N, nb = steps + 1;
+    const double h = (T - t0) / (double)steps;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t mm = (size_t)m * m * sizeof(double);
+    double *D = nullptr, *Lo = nullptr, *C = nullptr, *f = nullptr;
+    auto release = [&] {
+        for (double *q : {D, Lo, C, f})
+            if (q) hipFreeAsync(q, s);
+        hipStreamSynchronize(s);
+    };
+    if (hipMallocAsync((void **)&D, nb * mm, s) != hipSuccess ||
+        hipMallocAsync((void **)&Lo, steps * mm, s) != hipSuccess ||
+        hipMallocAsync((void **)&C, mm, s) != hipSuccess ||
+        hipMallocAsync((void **)&f, (size_t)nb * m * sizeof(double), s) != hipSuccess) {
+        release();
+        return PF_ENOMEM;
+    }
+    if (launch_ivp_trapezoid(m, steps, L, h, g, y0, D, Lo, C, f, s) != hipSuccess) {
+        release();
+        return PF_EHIP;
+    }
+    // the coarse mesh is the partition: sub-interval i is partition i
+    pf_opts o = resolve_opts(opts);
+    o.partitions = (int32_t)p;
+    const pf_matrix A{PF_BABD, m, nb, D, Lo, nullptr, C};
+    int rc = check_matrix(&A);
+    if (!rc) rc = check_opts(&A, o);
+    pf_factor_s *F = nullptr;
+    if (!rc) rc = factor_setup_private(&A, o, s, 1, &F);
+    if (!rc && launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s) != hipSuccess)
+        rc = PF_EHIP;
+    if (!rc) {
+        pf_info tmp;
+        rc = pf_factor_solve(F, 1, f, nb * m, y, nb * m, stream, info ? info : &tmp);
+        if (!rc) rc = (info ? info : &tmp)->status;
+    }
+    if (F) pf_destroy(F);
+    release();
+    return rc;
+}
+
 int pf_abd_to_btri(int32_t m, int64_t N, int32_t qa, const double *Ba, const double *S,
                    const double *R, const double *Bb, double *D, double *Lo, double *Up,
                    void *stream)

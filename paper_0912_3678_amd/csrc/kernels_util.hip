@@ -1,6 +1,7 @@
 // Bandwidth-bound helper kernels: FP64 residual and norms (refinement and
 // the backward-error gate), padding of block sizes without an instantiation,
-// and the structure mappings of Sec. 2 (banded and ABD -> block tridiagonal).
+// the structure mappings of Sec. 2 (banded and ABD -> block tridiagonal) and
+// the trapezoid discretization of a linear IVP (Sec. 3).
 #include "pf_internal.h"
 
 namespace pf {
@@ -223,6 +224,31 @@ __global__ void k_abd_to_btri(int m, int64_t N, int qa, const double *__restrict
     }
 }
 
+// The linear IVP y' = L y + g(t), y(t0) = y0, discretized by the trapezoid
+// rule with stepsize h over `steps` steps, as the lower block bidiagonal
+// system of Sec. 3, eq. (My): y_0 = y0, then for n >= 1
+//   (I - h/2 L) y_n - (I + h/2 L) y_{n-1} = h/2 (g_{n-1} + g_n),
+// stored as the bidiagonal-plus-corner form with a zero corner.
+__global__ void k_ivp_trapezoid(int m, int64_t steps, const double *__restrict__ L, double h,
+                                const double *__restrict__ g, const double *__restrict__ y0,
+                                double *D, double *Lo, double *C, double *f)
+{
+    const int64_t mm = (int64_t)m * m;
+    const int64_t total = (steps + 1) * mm;
+    const double hh = 0.5 * h;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / mm;
+        const int rem = (int)(e - k * mm);
+        const int j = rem / m, i = rem - j * m;
+        const double id = (i == j) ? 1.0 : 0.0, l = L[rem];
+        D[e] = (k == 0) ? id : id - hh * l;
+        if (k < steps) Lo[e] = -(id + hh * l);   // A(k+1, k)
+        if (k == 0) C[rem] = 0.0;
+        if (j == 0) f[k * m + i] = (k == 0) ? y0[i] : hh * (g[(k - 1) * m + i] + g[k * m + i]);
+    }
+}
+
 // workgroups for the reductions: enough to stream HBM, few atomics
 inline unsigned grid_reduce(int64_t work, int block)
 {
@@ -305,6 +331,15 @@ hipError_t launch_band_to_btri(int64_t n, int kl, int ku, const double *ab, int6
 {
     hipLaunchKernelGGL(k_band_to_btri, dim3(grid1(n * m, 256)), dim3(256), 0, s, n, kl, ku, ab,
                        ldab, m, D, Lo, Up);
+    return hipGetLastError();
+}
+
+hipError_t launch_ivp_trapezoid(int m, int64_t steps, const double *L, double h, const double *g,
+                                const double *y0, double *D, double *Lo, double *C, double *f,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ivp_trapezoid, dim3(grid1((steps + 1) * m * m, 256)), dim3(256), 0, s, m,
+                       steps, L, h, g, y0, D, Lo, C, f);
     return hipGetLastError();
 }
 

@@ -151,6 +151,9 @@ hipError_t launch_norminf(int kind, int m, int64_t nb, const double *D, const do
 hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, double *x,
                        int64_t ldx, hipStream_t s);
 // Fill count 64-bit words with a value (kernel, capture-safe).
+hipError_t launch_ivp_trapezoid(int m, int64_t steps, const double *L, double h, const double *g,
+                                const double *y0, double *D, double *Lo, double *C, double *f,
+                                hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v,
                            hipStream_t s);
 hipError_t launch_band_to_btri(int64_t n, int kl, int ku, const double *ab, int64_t ldab,

@@ -23,6 +23,7 @@ EXPORTED = [
     "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",
     "pf_sync_status", "pf_destroy", "pf_strerror", "pf_factor_levels", "pf_factor_level",
     "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
+    "pf_ivp_trapezoid_system", "pf_ivp_solve",
     "pf_plan", "pf_refactor", "pf_profile_enable", "pf_profile_read",
     "pf_batch_create", "pf_batch_run", "pf_batch_factor", "pf_batch_destroy", "pf_factor_solve",
     "pf_autotune", "pf_autotune_clear",
@@ -87,6 +88,10 @@ def load(path: str = LIB_PATH):
         "pf_factor_export_reduced": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "pf_band_to_btri": (ctypes.c_int, [i64, i32, i32, vp, i64, vp, vp, vp, vp]),
         "pf_abd_to_btri": (ctypes.c_int, [i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "pf_ivp_trapezoid_system": (ctypes.c_int, [i32, i64, vp, ctypes.c_double, vp, vp, vp, vp,
+                                                   vp, vp, vp]),
+        "pf_ivp_solve": (ctypes.c_int, [i32, vp, ctypes.c_double, ctypes.c_double, i64, i64, vp,
+                                        vp, vp, P(pf_opts), vp, P(pf_info)]),
         "pf_batch_create": (ctypes.c_int, [i32, P(pf_matrix), P(pf_opts), P(i32), P(vp), P(i64),
                                            P(vp), P(i64), vp, P(vp)]),
         "pf_batch_run": (ctypes.c_int, [vp, vp, P(pf_info)]),
@@ -276,6 +281,27 @@ def pf_abd_to_btri(m, N, qa, Ba, S, R, Bb, D, Lo, Up, stream=None):
                                _ptr(Lo), _ptr(Up), _stream(stream))
     if rc != 0:
         raise PFError(rc, "pf_abd_to_btri")
+
+
+def pf_ivp_trapezoid_system(m, steps, L, h, g, y0, D, Lo, C, f, stream=None):
+    """Device tensors in, device tensors out (see include/pf.h)."""
+    rc = load().pf_ivp_trapezoid_system(m, steps, _ptr(L), float(h), _ptr(g), _ptr(y0), _ptr(D),
+                                        _ptr(Lo), _ptr(C), _ptr(f), _stream(stream))
+    if rc != 0:
+        raise PFError(rc, "pf_ivp_trapezoid_system")
+
+
+def pf_ivp_solve(m, L, t0, T, p, N, g, y0, y, opts=None, stream=None):
+    """Time-parallel trapezoid solution of y' = L y + g(t) on a coarse mesh of
+    p sub-intervals of N steps; returns pf_info.  L (m*m, column-major), g
+    ((p*N+1)*m), y0 (m) and y ((p*N+1)*m) are device tensors."""
+    info = pf_info()
+    rc = load().pf_ivp_solve(m, _ptr(L), float(t0), float(T), p, N, _ptr(g), _ptr(y0), _ptr(y),
+                             ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                             ctypes.byref(info))
+    if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
+        raise PFError(rc, "pf_ivp_solve")
+    return info
 
 
 def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False):

@@ -232,6 +232,24 @@ def ivp_lower_bidiagonal(N: int, m: int, seed: int, nrhs=None) -> System:
                   {"workload": "ivp_lower_bidiagonal", "N": N, "m": m, "seed": seed})
 
 
+def ivp_problem(m: int, p: int, N: int, seed: int, t0: float = 0.0, T: float = 1.0):
+    """A linear IVP y' = L y + g(t), y(t0) = y0 on [t0, T] for the time-parallel
+    driver of Sec. 3, sampled on the grid of p*N steps: L = -I + a skew part
+    + N(0, 0.3/m) (eigenvalues in the left half-plane, moderate stiffness), g
+    a few random sinusoids per component, y0 ~ N(0, 1).  Returns (L (m, m),
+    g (p*N+1, m), y0 (m,), t0, T)."""
+    rng = np.random.default_rng(seed)
+    K = rng.standard_normal((m, m))
+    L = -np.eye(m) + 2.0 * (K - K.T) / math.sqrt(m) + rng.standard_normal((m, m)) * (0.3 / m)
+    t = t0 + (T - t0) * np.arange(p * N + 1) / (p * N)
+    amp = rng.standard_normal((3, m))
+    freq = rng.uniform(0.5, 6.0, (3, m))
+    phase = rng.uniform(0.0, 2 * math.pi, (3, m))
+    g = sum(amp[k] * np.sin(freq[k] * t[:, None] + phase[k]) for k in range(3))
+    y0 = rng.standard_normal(m)
+    return L, np.ascontiguousarray(g), y0, t0, T
+
+
 # ---------------------------------------------------------------------------
 # Workloads 4 and 5: random block tridiagonal systems.
 

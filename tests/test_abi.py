@@ -51,6 +51,31 @@ def test_argument_validation():
     assert lib.pf_strerror(pf.PF_ESINGULAR).decode().startswith("exactly zero")
 
 
+def test_ivp_argument_validation():
+    """The IVP entry points reject bad arguments on the host, before any
+    device allocation or launch."""
+    lib = pf.load()
+    fake = ctypes.c_void_p(256)   # never dereferenced: every call below fails validation
+    ok = dict(m=4, L=fake, t0=0.0, T=1.0, p=8, N=16, g=fake, y0=fake, y=fake)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.pf_ivp_solve(a["m"], a["L"], a["t0"], a["T"], a["p"], a["N"], a["g"],
+                                a["y0"], a["y"], None, None, None)
+    assert call(m=0) == -1 and call(m=33) == -1
+    assert call(L=None) == -2
+    assert call(T=0.0) == -4 and call(T=float("nan")) == -4
+    assert call(p=0) == -5
+    assert call(N=1) == -6                  # a sub-interval needs two steps (p <= (nb-1)/2)
+    assert call(g=None) == -7 and call(y0=None) == -8 and call(y=None) == -9
+    sysargs = [4, 10, fake, 0.1, fake, fake, fake, fake, fake, fake, None]
+    assert lib.pf_ivp_trapezoid_system(0, *sysargs[1:]) == -1
+    assert lib.pf_ivp_trapezoid_system(4, 0, *sysargs[2:]) == -2
+    assert lib.pf_ivp_trapezoid_system(4, 10, fake, -0.1, *sysargs[4:]) == -4
+    assert lib.pf_ivp_trapezoid_system(4, 10, fake, 0.1, fake, fake, fake, fake, None, fake,
+                                       None) == -9
+
+
 def test_plan_btri_levels_shrink_to_one_chain():
     for nb in (2, 7, 100, 65537):
         plan = pf.pf_plan(_mat(nb=nb))

@@ -1,0 +1,107 @@
+"""GPU tests of the time-parallel IVP driver (Sec. 3): the trapezoid
+discretization of y' = L y + g(t) built on the device, and its solution over
+a coarse mesh of p sub-intervals (the partitions) against the oracle's
+sequential stepping."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0912_3678_amd import pf
+from paper_0912_3678_amd import workloads as wl
+
+from . import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=G.device())
+
+
+def _L_dev(L):
+    return _dev(np.asarray(L).T.reshape(-1))     # column-major m x m
+
+
+def test_trapezoid_system_matches_definition():
+    """The device-built eq. (My) system equals its definition entry for entry:
+    D[0] = I, D[n] = I - h/2 L, Lo = -(I + h/2 L), C = 0, f[0] = y0,
+    f[n] = h/2 (g_{n-1} + g_n)."""
+    import torch
+    m, steps = 5, 37
+    L, g, y0, t0, T = wl.ivp_problem(m, 1, steps, seed=3)
+    h = (T - t0) / steps
+    D = torch.full(((steps + 1) * m * m,), np.nan, dtype=torch.float64, device=G.device())
+    Lo = torch.full((steps * m * m,), np.nan, dtype=torch.float64, device=G.device())
+    C = torch.full((m * m,), np.nan, dtype=torch.float64, device=G.device())
+    f = torch.full(((steps + 1) * m,), np.nan, dtype=torch.float64, device=G.device())
+    pf.pf_ivp_trapezoid_system(m, steps, _L_dev(L), h, _dev(g.reshape(-1)), _dev(y0), D, Lo, C, f)
+    torch.cuda.synchronize()
+    eye = np.eye(m)
+    cm = lambda blocks: np.transpose(blocks, (0, 2, 1)).reshape(-1)   # column-major blocks
+    Dref = np.concatenate([eye[None], np.repeat((eye - 0.5 * h * L)[None], steps, 0)])
+    Loref = np.repeat((-(eye + 0.5 * h * L))[None], steps, 0)
+    fref = np.concatenate([y0[None], 0.5 * h * (g[:-1] + g[1:])]).reshape(-1)
+    assert np.array_equal(D.cpu().numpy(), cm(Dref))
+    assert np.array_equal(Lo.cpu().numpy(), cm(Loref))
+    assert np.array_equal(C.cpu().numpy(), np.zeros(m * m))
+    assert np.array_equal(f.cpu().numpy(), fref)
+
+
+@pytest.mark.parametrize("m,p,N", [(1, 1, 2), (1, 4, 50), (4, 8, 100), (8, 64, 40), (16, 16, 33),
+                                   (3, 5, 7), (8, 1, 300), (32, 4, 10), (12, 100, 2), (8, 2048, 8)])
+def test_ivp_solve_matches_sequential_stepping(m, p, N):
+    """The time-parallel solution over p sub-intervals equals the oracle's
+    step-by-step solution of the same discretization (up to rounding):
+    single and many sub-intervals, two-step sub-intervals, padded block
+    sizes, m = 1 and m = 32."""
+    import torch
+    L, g, y0, t0, T = wl.ivp_problem(m, p, N, seed=100 + m + p + N)
+    steps = p * N
+    h = (T - t0) / steps
+    y = torch.full(((steps + 1) * m,), np.nan, dtype=torch.float64, device=G.device())
+    _say("ivp m", m, "p", p, "N", N)
+    info = pf.pf_ivp_solve(m, _L_dev(L), t0, T, p, N, _dev(g.reshape(-1)), _dev(y0), y)
+    assert info.status == 0
+    ref = oracle.ivp_trapezoid(L, h, g, y0)
+    got = y.cpu().numpy().reshape(steps + 1, m)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("   rel err vs sequential", err)
+    assert err <= 1e-11
+
+
+def test_ivp_solve_partition_invariance_and_fp32_refinement():
+    """One sub-interval or 256 give the same solution up to rounding, and
+    FP32 factors with FP64 refinement reach the same result."""
+    import torch
+    m, N0 = 8, 4096
+    L, g, y0, t0, T = wl.ivp_problem(m, 1, N0, seed=7)
+    gd, yd, Ld = _dev(g.reshape(-1)), _dev(y0), _L_dev(L)
+    out = {}
+    for name, p, opts in (("p1", 1, None), ("p256", 256, None),
+                          ("fp32ir", 256, pf.make_opts(prec=pf.PF_FP32_IR))):
+        y = torch.full(((N0 + 1) * m,), np.nan, dtype=torch.float64, device=G.device())
+        info = pf.pf_ivp_solve(m, Ld, t0, T, p, N0 // p, gd, yd, y, opts=opts)
+        assert info.status == 0, name
+        out[name] = y.cpu().numpy()
+    scale = np.abs(out["p1"]).max()
+    assert np.abs(out["p256"] - out["p1"]).max() <= 1e-12 * scale
+    assert np.abs(out["fp32ir"] - out["p1"]).max() <= 1e-10 * scale
+
+
+def test_ivp_singular_step_matrix_reported():
+    """h/2 L with an eigenvalue 1 makes I - h/2 L singular in every step:
+    reported as an exactly singular pivot at level 0, first interior block."""
+    import torch
+    m, p, N = 2, 4, 8
+    h = 1.0 / (p * N)         # a power of two: h/2 * 2/h is exactly 1
+    L = np.diag([2.0 / h, -1.0])
+    g = np.zeros((p * N + 1, m))
+    y = torch.zeros(((p * N + 1) * m,), dtype=torch.float64, device=G.device())
+    info = pf.pf_ivp_solve(m, _L_dev(L), 0.0, 1.0, p, N, _dev(g.reshape(-1)), _dev(np.ones(m)), y)
+    assert info.status == pf.PF_ESINGULAR
+    assert info.bad_level == 0 and info.bad_block == 1

@@ -206,6 +206,65 @@ def test_babd_ivp_equals_time_stepping(oracle):
 
 
 # --------------------------------------------------------------------------
+# the sequential IVP routine (Sec. 3) behind the time-parallel driver's parity
+def test_ivp_trapezoid_scalar_closed_form(oracle):
+    """y' = lam y + c: the trapezoid recursion has the closed form
+    y_n = r^n (y0 + c/lam) - c/lam, r = (1 + h lam/2) / (1 - h lam/2)
+    (the constant -c/lam is a fixed point of every step)."""
+    lam, c, y0, h, steps = -1.7, 0.9, 1.3, 0.01, 400
+    y = oracle.ivp_trapezoid(np.array([[lam]]), h, np.full((steps + 1, 1), c), np.array([y0]))
+    r = (1 + h * lam / 2) / (1 - h * lam / 2)
+    n = np.arange(steps + 1)
+    ref = r ** n * (y0 + c / lam) - c / lam
+    assert _rel(y[:, 0], ref) < 1e-13
+
+
+def test_ivp_trapezoid_diagonal_decouples(oracle):
+    """A diagonal L decouples into scalar problems, each with its closed
+    form; a permutation similarity of L permutes the solution's components."""
+    lams = np.array([-0.3, -2.0, 0.4])
+    c = np.array([0.5, -1.0, 2.0])
+    y0 = np.array([1.0, 0.25, -0.5])
+    h, steps = 0.02, 250
+    y = oracle.ivp_trapezoid(np.diag(lams), h, np.tile(c, (steps + 1, 1)), y0)
+    n = np.arange(steps + 1)[:, None]
+    r = (1 + h * lams / 2) / (1 - h * lams / 2)
+    assert _rel(y, r ** n * (y0 + c / lams) - c / lams) < 1e-13
+    P = np.eye(3)[[2, 0, 1]]
+    yp = oracle.ivp_trapezoid(P @ np.diag(lams) @ P.T, h, np.tile(P @ c, (steps + 1, 1)), P @ y0)
+    assert _rel(yp, y @ P.T) < 1e-15
+
+
+def test_ivp_trapezoid_second_order(oracle):
+    """Against the exact flow exp(L t) y0 of a damped rotation (g = 0), the
+    error at t = 1 falls by about 4 when the step halves (the trapezoid rule
+    is of order 2); a dropped h/2 or sign would break the order."""
+    L = np.array([[-0.5, 2.0], [-2.0, -0.5]])
+    y0 = np.array([1.0, -0.5])
+    exact_y = sla.expm(L) @ y0
+    errs = []
+    for steps in (100, 200, 400):
+        y = oracle.ivp_trapezoid(L, 1.0 / steps, np.zeros((steps + 1, 2)), y0)
+        errs.append(np.abs(y[-1] - exact_y).max())
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2
+
+
+def test_ivp_trapezoid_equals_structured_solve(oracle):
+    """The sequential routine and the structured BABD elimination of the
+    assembled eq. (My) system (B0 = I, B1 = 0) give the same solution."""
+    L, g, y0, t0, T = wl.ivp_problem(5, 4, 30, seed=17)
+    steps = g.shape[0] - 1
+    h = (T - t0) / steps
+    y = oracle.ivp_trapezoid(L, h, g, y0)
+    eye = np.eye(5)
+    D = np.concatenate([eye[None], np.repeat((eye - 0.5 * h * L)[None], steps, 0)])
+    Lo = np.repeat((-(eye + 0.5 * h * L))[None], steps, 0)
+    f = np.concatenate([y0[None], 0.5 * h * (g[:-1] + g[1:])]).reshape(-1)
+    x = oracle.babd_solve(D, Lo, np.zeros((5, 5)), f)
+    assert _rel(x, y.reshape(-1)) < 1e-12
+
+
+# --------------------------------------------------------------------------
 # residuals and norms
 def test_residual_and_norms_vs_dense(oracle):
     rng = np.random.default_rng(17)
