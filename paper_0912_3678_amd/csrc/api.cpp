@@ -1150,8 +1150,8 @@ int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int
     if (m < 1 || m > 32) return -1;
     if (!L) return -2;
     if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0)) return -4;
-    if (p < 1) return -5;
-    if (N < 2) return -6;
+    if (p < 1 || p > INT32_MAX) return -5;
+    if (N < 2 || N > (INT64_MAX / 2) / p) return -6;
     if (!g) return -7;
     if (!y0) return -8;
     if (!y) return -9;

@@ -65,8 +65,9 @@ def test_ivp_argument_validation():
     assert call(m=0) == -1 and call(m=33) == -1
     assert call(L=None) == -2
     assert call(T=0.0) == -4 and call(T=float("nan")) == -4
-    assert call(p=0) == -5
+    assert call(p=0) == -5 and call(p=2 ** 40) == -5
     assert call(N=1) == -6                  # a sub-interval needs two steps (p <= (nb-1)/2)
+    assert call(N=2 ** 61) == -6            # p * N would overflow
     assert call(g=None) == -7 and call(y0=None) == -8 and call(y=None) == -9
     sysargs = [4, 10, fake, 0.1, fake, fake, fake, fake, fake, fake, None]
     assert lib.pf_ivp_trapezoid_system(0, *sysargs[1:]) == -1
