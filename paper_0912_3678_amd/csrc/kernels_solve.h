@@ -180,7 +180,7 @@ __device__ __forceinline__ void bwd_body(const SolveArgs &a, int64_t pblock, int
     // zero block); the first rows are requested before the separators'
     // solution, so the waits overlap.  A row costs 2M + KC registers per lane,
     // which bounds the depth for the larger blocks.
-    constexpr int PD = M <= 8 ? 2 : (M <= 16 ? 1 : 0);
+    constexpr int PD = M <= 4 ? 4 : (M <= 8 ? 3 : (M <= 16 ? 1 : 0));
     struct Row {
         T zr[M], xr[M];
         double t[KC];
