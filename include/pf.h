@@ -308,6 +308,23 @@ int pf_ivp_trapezoid_system(int32_t m, int64_t steps, const double *L, double h,
                             const double *y0, double *D, double *Lo, double *C, double *f,
                             void *stream);
 
+/* A plan for time-parallel solutions of such IVPs with a fixed shape: m,
+ * a coarse mesh of p sub-intervals of N steps each (N >= 2), options (may be
+ * NULL; partitions is replaced by p).  Holds the eq. (My) system arrays and
+ * the factor handle, allocated here on `stream` (stream-ordered; the plan
+ * keeps using that stream by default).  Returns 0, -k for invalid argument
+ * k, PF_ENOMEM or PF_EHIP. */
+typedef struct pf_ivp_s *pf_ivp_t;
+int pf_ivp_create(int32_t m, int64_t p, int64_t N, const pf_opts *opts, void *stream,
+                  pf_ivp_t *out);
+/* Solve one IVP with a plan, as pf_ivp_solve describes: builds the system
+ * for L, [t0, T], g, y0 into the plan's arrays, then factors and solves it
+ * (pf_factor_solve on the plan's handle).  Allocates nothing.  stream NULL =
+ * the plan's stream.  Synchronization and errors as for pf_factor_solve. */
+int pf_ivp_run(pf_ivp_t I, const double *L, double t0, double T, const double *g,
+               const double *y0, double *y, void *stream, pf_info *info);
+void pf_ivp_destroy(pf_ivp_t I);
+
 /* Time-parallel solution of that IVP on [t0, T] over a coarse mesh of p
  * sub-intervals of N steps each (Sec. 3): h = (T - t0) / (p N), and the p
  * partitions of the factorization are the sub-intervals.  The finest level
@@ -318,8 +335,9 @@ int pf_ivp_trapezoid_system(int32_t m, int64_t steps, const double *L, double h,
  * parallel update (eq. (pups)).  g, y0 as for pf_ivp_trapezoid_system (p*N+1
  * samples); y: device output of p*N+1 vectors (y_n at y + n*m).  N >= 2.
  * opts may be NULL (its partitions field is replaced by p; PF_FP64 or
- * PF_FP32_IR).  Allocates the system arrays on `stream` (stream-ordered) and
- * frees them before returning; synchronizes `stream`.  info may be NULL.
+ * PF_FP32_IR).  A one-shot pf_ivp_create + pf_ivp_run + pf_ivp_destroy:
+ * allocates the system arrays on `stream` (stream-ordered) and frees them
+ * before returning; synchronizes `stream`.  info may be NULL.
  * Returns 0, -k for invalid argument k, PF_ENOMEM, PF_EHIP or the numeric
  * status (PF_ESINGULAR). */
 int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int64_t N,

@@ -1125,6 +1125,14 @@ int pf_band_to_btri(int64_t n, int32_t kl, int32_t ku, const double *ab, int64_t
                    hipSuccess ? 0 : PF_EHIP;
 }
 
+struct pf_ivp_s {
+    int32_t m = 0;
+    int64_t p = 0, N = 0;
+    hipStream_t stream = nullptr;
+    double *D = nullptr, *Lo = nullptr, *C = nullptr, *f = nullptr;   // the eq. (My) system
+    pf_factor_s *F = nullptr;
+};
+
 int pf_ivp_trapezoid_system(int32_t m, int64_t steps, const double *L, double h, const double *g,
                             const double *y0, double *D, double *Lo, double *C, double *f,
                             void *stream)
@@ -1143,6 +1151,73 @@ int pf_ivp_trapezoid_system(int32_t m, int64_t steps, const double *L, double h,
                    hipSuccess ? 0 : PF_EHIP;
 }
 
+int pf_ivp_create(int32_t m, int64_t p, int64_t N, const pf_opts *opts, void *stream,
+                  pf_ivp_t *out)
+{
+    if (m < 1 || m > 32) return -1;
+    if (p < 1 || p > INT32_MAX) return -2;
+    if (N < 2 || N > (INT64_MAX / 2) / p) return -3;
+    if (!out) return -6;
+    *out = nullptr;
+    pf_ivp_s *I = new pf_ivp_s();
+    I->m = m;
+    I->p = p;
+    I->N = N;
+    I->stream = (hipStream_t)stream;
+    const int64_t steps = p * N, nb = steps + 1;
+    const size_t mm = (size_t)m * m * sizeof(double);
+    hipStream_t s = I->stream;
+    if (hipMallocAsync((void **)&I->D, nb * mm, s) != hipSuccess ||
+        hipMallocAsync((void **)&I->Lo, steps * mm, s) != hipSuccess ||
+        hipMallocAsync((void **)&I->C, mm, s) != hipSuccess ||
+        hipMallocAsync((void **)&I->f, (size_t)nb * m * sizeof(double), s) != hipSuccess) {
+        pf_ivp_destroy(I);
+        return PF_ENOMEM;
+    }
+    // the coarse mesh is the partition: sub-interval i is partition i
+    pf_opts o = resolve_opts(opts);
+    o.partitions = (int32_t)p;
+    const pf_matrix A{PF_BABD, m, nb, I->D, I->Lo, nullptr, I->C};
+    int rc = check_matrix(&A);
+    if (!rc) rc = check_opts(&A, o);
+    if (!rc) rc = factor_setup_private(&A, o, s, 1, &I->F);
+    if (!rc && launch_fill_u64((unsigned long long *)I->F->d_zero, kZeroBytes / 8, 0ull, s) != hipSuccess)
+        rc = PF_EHIP;
+    if (rc) {
+        pf_ivp_destroy(I);
+        return rc;
+    }
+    *out = I;
+    return 0;
+}
+
+int pf_ivp_run(pf_ivp_t I, const double *L, double t0, double T, const double *g,
+               const double *y0, double *y, void *stream, pf_info *info)
+{
+    if (!I) return -1;
+    if (!L) return -2;
+    if (!std::isfinite(t0) || !std::isfinite(T) || !(T > t0)) return -4;
+    if (!g) return -5;
+    if (!y0) return -6;
+    if (!y) return -7;
+    hipStream_t s = stream ? (hipStream_t)stream : I->stream;
+    const int64_t steps = I->p * I->N, nb = steps + 1;
+    const double h = (T - t0) / (double)steps;
+    if (launch_ivp_trapezoid(I->m, steps, L, h, g, y0, I->D, I->Lo, I->C, I->f, s) != hipSuccess)
+        return PF_EHIP;
+    return pf_factor_solve(I->F, 1, I->f, nb * I->m, y, nb * I->m, s, info);
+}
+
+void pf_ivp_destroy(pf_ivp_t I)
+{
+    if (!I) return;
+    if (I->F) pf_destroy(I->F);
+    for (double *q : {I->D, I->Lo, I->C, I->f})
+        if (q) hipFreeAsync(q, I->stream);
+    hipStreamSynchronize(I->stream);
+    delete I;
+}
+
 int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int64_t N,
                  const double *g, const double *y0, double *y, const pf_opts *opts, void *stream,
                  pf_info *info)
@@ -1155,44 +1230,13 @@ int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int
     if (!g) return -7;
     if (!y0) return -8;
     if (!y) return -9;
-    const int64_t steps = p * N, nb = steps + 1;
-    const double h = (T - t0) / (double)steps;
-    hipStream_t s = (hipStream_t)stream;
-    const size_t mm = (size_t)m * m * sizeof(double);
-    double *D = nullptr, *Lo = nullptr, *C = nullptr, *f = nullptr;
-    auto release = [&] {
-        for (double *q : {D, Lo, C, f})
-            if (q) hipFreeAsync(q, s);
-        hipStreamSynchronize(s);
-    };
-    if (hipMallocAsync((void **)&D, nb * mm, s) != hipSuccess ||
-        hipMallocAsync((void **)&Lo, steps * mm, s) != hipSuccess ||
-        hipMallocAsync((void **)&C, mm, s) != hipSuccess ||
-        hipMallocAsync((void **)&f, (size_t)nb * m * sizeof(double), s) != hipSuccess) {
-        release();
-        return PF_ENOMEM;
-    }
-    if (launch_ivp_trapezoid(m, steps, L, h, g, y0, D, Lo, C, f, s) != hipSuccess) {
-        release();
-        return PF_EHIP;
-    }
-    // the coarse mesh is the partition: sub-interval i is partition i
-    pf_opts o = resolve_opts(opts);
-    o.partitions = (int32_t)p;
-    const pf_matrix A{PF_BABD, m, nb, D, Lo, nullptr, C};
-    int rc = check_matrix(&A);
-    if (!rc) rc = check_opts(&A, o);
-    pf_factor_s *F = nullptr;
-    if (!rc) rc = factor_setup_private(&A, o, s, 1, &F);
-    if (!rc && launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s) != hipSuccess)
-        rc = PF_EHIP;
-    if (!rc) {
-        pf_info tmp;
-        rc = pf_factor_solve(F, 1, f, nb * m, y, nb * m, stream, info ? info : &tmp);
-        if (!rc) rc = (info ? info : &tmp)->status;
-    }
-    if (F) pf_destroy(F);
-    release();
+    pf_ivp_t I = nullptr;
+    int rc = pf_ivp_create(m, p, N, opts, stream, &I);
+    if (rc) return rc;
+    pf_info tmp;
+    rc = pf_ivp_run(I, L, t0, T, g, y0, y, stream, info ? info : &tmp);
+    if (!rc) rc = (info ? info : &tmp)->status;
+    pf_ivp_destroy(I);
     return rc;
 }
 

@@ -23,7 +23,7 @@ EXPORTED = [
     "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",
     "pf_sync_status", "pf_destroy", "pf_strerror", "pf_factor_levels", "pf_factor_level",
     "pf_factor_block_size", "pf_factor_export_reduced", "pf_band_to_btri", "pf_abd_to_btri",
-    "pf_ivp_trapezoid_system", "pf_ivp_solve",
+    "pf_ivp_trapezoid_system", "pf_ivp_solve", "pf_ivp_create", "pf_ivp_run", "pf_ivp_destroy",
     "pf_plan", "pf_refactor", "pf_profile_enable", "pf_profile_read",
     "pf_batch_create", "pf_batch_run", "pf_batch_factor", "pf_batch_destroy", "pf_factor_solve",
     "pf_autotune", "pf_autotune_clear",
@@ -92,6 +92,10 @@ def load(path: str = LIB_PATH):
                                                    vp, vp, vp]),
         "pf_ivp_solve": (ctypes.c_int, [i32, vp, ctypes.c_double, ctypes.c_double, i64, i64, vp,
                                         vp, vp, P(pf_opts), vp, P(pf_info)]),
+        "pf_ivp_create": (ctypes.c_int, [i32, i64, i64, P(pf_opts), vp, P(vp)]),
+        "pf_ivp_run": (ctypes.c_int, [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp,
+                                      P(pf_info)]),
+        "pf_ivp_destroy": (None, [vp]),
         "pf_batch_create": (ctypes.c_int, [i32, P(pf_matrix), P(pf_opts), P(i32), P(vp), P(i64),
                                            P(vp), P(i64), vp, P(vp)]),
         "pf_batch_run": (ctypes.c_int, [vp, vp, P(pf_info)]),
@@ -302,6 +306,30 @@ def pf_ivp_solve(m, L, t0, T, p, N, g, y0, y, opts=None, stream=None):
     if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
         raise PFError(rc, "pf_ivp_solve")
     return info
+
+
+def pf_ivp_create(m, p, N, opts=None, stream=None):
+    """A plan (opaque handle) for IVPs of this shape; free with pf_ivp_destroy."""
+    h = ctypes.c_void_p()
+    rc = load().pf_ivp_create(m, p, N, ctypes.byref(opts) if opts is not None else None,
+                              _stream(stream), ctypes.byref(h))
+    if rc != 0:
+        raise PFError(rc, "pf_ivp_create")
+    return h
+
+
+def pf_ivp_run(plan, L, t0, T, g, y0, y, stream=None, want_info=True):
+    """Solve with a plan; returns pf_info (synchronizing) or None."""
+    info = pf_info() if want_info else None
+    rc = load().pf_ivp_run(plan, _ptr(L), float(t0), float(T), _ptr(g), _ptr(y0), _ptr(y),
+                           _stream(stream), ctypes.byref(info) if info is not None else None)
+    if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
+        raise PFError(rc, "pf_ivp_run")
+    return info
+
+
+def pf_ivp_destroy(plan):
+    load().pf_ivp_destroy(plan)
 
 
 def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False):

@@ -69,6 +69,12 @@ def test_ivp_argument_validation():
     assert call(N=1) == -6                  # a sub-interval needs two steps (p <= (nb-1)/2)
     assert call(N=2 ** 61) == -6            # p * N would overflow
     assert call(g=None) == -7 and call(y0=None) == -8 and call(y=None) == -9
+    h = ctypes.c_void_p()
+    assert lib.pf_ivp_create(0, 8, 16, None, None, ctypes.byref(h)) == -1
+    assert lib.pf_ivp_create(4, 0, 16, None, None, ctypes.byref(h)) == -2
+    assert lib.pf_ivp_create(4, 8, 1, None, None, ctypes.byref(h)) == -3
+    assert lib.pf_ivp_create(4, 8, 16, None, None, None) == -6
+    assert lib.pf_ivp_run(None, fake, 0.0, 1.0, fake, fake, fake, None, None) == -1
     sysargs = [4, 10, fake, 0.1, fake, fake, fake, fake, fake, fake, None]
     assert lib.pf_ivp_trapezoid_system(0, *sysargs[1:]) == -1
     assert lib.pf_ivp_trapezoid_system(4, 0, *sysargs[2:]) == -2

@@ -105,3 +105,27 @@ def test_ivp_singular_step_matrix_reported():
     info = pf.pf_ivp_solve(m, _L_dev(L), 0.0, 1.0, p, N, _dev(g.reshape(-1)), _dev(np.ones(m)), y)
     assert info.status == pf.PF_ESINGULAR
     assert info.bad_level == 0 and info.bad_block == 1
+
+
+def test_ivp_plan_reused_equals_one_shot():
+    """A plan solves several IVPs of its shape (new L, g, y0, interval) with
+    no allocation, each equal bit for bit to the one-shot pf_ivp_solve and to
+    sequential stepping up to rounding."""
+    import torch
+    m, p, N = 8, 32, 16
+    plan = pf.pf_ivp_create(m, p, N)
+    try:
+        for seed, (t0, T) in ((21, (0.0, 1.0)), (22, (0.5, 2.0)), (23, (-1.0, 0.0))):
+            L, g, y0, _, _ = wl.ivp_problem(m, p, N, seed=seed, t0=t0, T=T)
+            Ld, gd, y0d = _L_dev(L), _dev(g.reshape(-1)), _dev(y0)
+            y1 = torch.full(((p * N + 1) * m,), np.nan, dtype=torch.float64, device=G.device())
+            y2 = torch.full_like(y1, np.nan)
+            _say("plan run seed", seed)
+            assert pf.pf_ivp_run(plan, Ld, t0, T, gd, y0d, y1).status == 0
+            assert pf.pf_ivp_solve(m, Ld, t0, T, p, N, gd, y0d, y2).status == 0
+            assert torch.equal(y1, y2)
+            ref = oracle.ivp_trapezoid(L, (T - t0) / (p * N), g, y0)
+            got = y1.cpu().numpy().reshape(p * N + 1, m)
+            assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    finally:
+        pf.pf_ivp_destroy(plan)
