@@ -129,3 +129,28 @@ def test_ivp_plan_reused_equals_one_shot():
             assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
     finally:
         pf.pf_ivp_destroy(plan)
+
+
+def test_ivp_system_through_pf_factor_equals_driver():
+    """The system from pf_ivp_trapezoid_system, factored by pf_factor with the
+    sub-intervals as partitions and solved with pf_factor_solve, is the
+    driver's computation: the same solution bit for bit."""
+    import torch
+    m, p, N = 6, 16, 25
+    L, g, y0, t0, T = wl.ivp_problem(m, p, N, seed=41)
+    steps, nb = p * N, p * N + 1
+    h = (T - t0) / steps
+    Ld, gd, y0d = _L_dev(L), _dev(g.reshape(-1)), _dev(y0)
+    f64 = dict(dtype=torch.float64, device=G.device())
+    D, Lo = torch.empty((nb * m * m,), **f64), torch.empty((steps * m * m,), **f64)
+    C, f = torch.empty((m * m,), **f64), torch.empty((nb * m,), **f64)
+    pf.pf_ivp_trapezoid_system(m, steps, Ld, h, gd, y0d, D, Lo, C, f)
+    F = pf.pf_factor(pf.make_matrix(pf.PF_BABD, m, nb, D, Lo, None, C), pf.make_opts(partitions=p))
+    try:
+        x1 = torch.full((nb * m,), np.nan, **f64)
+        assert pf.pf_factor_solve(F, f.view(1, -1), x1.view(1, -1)).status == 0
+    finally:
+        pf.pf_destroy(F)
+    x2 = torch.full((nb * m,), np.nan, **f64)
+    assert pf.pf_ivp_solve(m, Ld, t0, T, p, N, gd, y0d, x2).status == 0
+    assert torch.equal(x1, x2)
