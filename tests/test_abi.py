@@ -93,6 +93,20 @@ def test_plan_btri_levels_shrink_to_one_chain():
         assert plan[-1][2] == 1
 
 
+def test_plan_finest_chain_lengths():
+    """Level-0 partitions of the planner: 16 blocks for m <= 8 and for the
+    FP64 bidiagonal-plus-corner form with m = 16 (its matrix-core kernel
+    inverts four blocks at a time), 4 for other m >= 16 and for FP32 factors
+    of that form."""
+    def p0(kind, m, nb, prec=pf.PF_FP64):
+        return pf.pf_plan(_mat(kind, m, nb), pf.make_opts(prec=prec))[0][2]
+    assert p0(pf.PF_BTRI, 8, 65537) == (65537 + 1) // 17
+    assert p0(pf.PF_BABD, 16, 262145) == (262145 - 1) // 17
+    assert p0(pf.PF_BABD, 16, 262145, pf.PF_FP32_IR) == (262145 - 1) // 5
+    assert p0(pf.PF_BTRI, 16, 65537) == (65537 + 1) // 5
+    assert p0(pf.PF_BABD, 12, 262145) == (262145 - 1) // 17    # padded to 16
+
+
 def test_plan_reduced_size_depends_only_on_p():
     """The block size of T_p depends only on p, not on n (eq. (redmatr))."""
     for nb in (1000, 5000, 65537):
