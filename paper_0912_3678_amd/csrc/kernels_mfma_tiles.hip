@@ -534,10 +534,11 @@ __global__ __launch_bounds__(WG) void kb_bwdt(const SolveArgs *tab, const int4 *
 // sixteen lanes per block, one tableau row per lane, the exchange steps of
 // kernels_gj.h -- and then runs the chain of those rows on the matrix cores
 // (one 16 x 16 tile per product): Zh_k = E_k Z'_k, t_k = E_k f'_k,
-// Z'_{k+1} = -A(g+1,g) Zh_k, f'_{k+1} = f[g+1] - A(g+1,g) t_k.  The chain
-// operands of the four rows are requested before the inversion, which
-// covers their latency.  Outputs are those of the segment kernel (E and Zh
-// row-major; beta, the next diagonal block and the reduced right-hand side).
+// Z'_{k+1} = -A(g+1,g) Zh_k, f'_{k+1} = f[g+1] - A(g+1,g) t_k.  The first
+// row's chain operands are requested before the inversion, which covers
+// their latency, and each later row's one row ahead.  Outputs are those of
+// the segment kernel (E and Zh row-major; beta, the next diagonal block and
+// the reduced right-hand side).
 constexpr int kBQ = 4;                              // blocks inverted together
 constexpr int kBRS = 16 + kPad<double>;             // padded LDS row stride
 constexpr int kBSL = 16 * kBRS;                     // one block in LDS
