@@ -22,7 +22,12 @@ Other workloads (one JSON line each, same fields where they apply):
   serving  Poisson arrivals of factor-and-solve requests (m in {8,16,32},
            N lognormal with median 2^14, 30 % repeat right-hand sides on
            kept factors) through the request scheduler: p50 / p99 latency
-           and throughput at fractions of the saturation rate.
+           and throughput at fractions of the saturation rate;
+  ivp      the trapezoid rule for an initial value problem, solved in
+           parallel over sub-intervals (Sec. 3);
+  tridiag  a scalar tridiagonal system (m = 1; sub/super diagonals
+           U[-1,1], diagonal 4+U[0,1]) of --n-tri unknowns, FP64, timed
+           like the default workload.
 """
 from __future__ import annotations
 
@@ -42,7 +47,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["bvp", "babd", "batch", "serving", "ivp"], default="bvp")
+    ap.add_argument("--workload", choices=["bvp", "babd", "batch", "serving", "ivp", "tridiag"],
+                    default="bvp")
     ap.add_argument("--prec", choices=["fp64", "fp32ir"], default=None,
                     help="babd / batch: precision (babd default fp32ir, batch default fp64)")
     ap.add_argument("--count", type=int, default=0,
@@ -55,6 +61,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--m", type=int, default=8)
+    ap.add_argument("--n-tri", type=int, default=1 << 24, help="tridiag: unknowns")
     ap.add_argument("--partitions", type=int, default=0, help="finest-level p (0 = planner)")
     ap.add_argument("--block-rows", type=int, default=0)
     ap.add_argument("--coarse-rows", type=int, default=0)
@@ -104,10 +111,12 @@ KERNEL_SOURCES = {
     "k_bwd": _COMMON + ("kernels_solve.h", "kernels_solve.hip"),
     "k_btri_factor": _COMMON + ("kernels_rows.hip",),
     "k_babd_factor": _COMMON + ("kernels_rows.hip",),
+    "k_tri_factor": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
+    "k_tri_bwd": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
 }
 _ALL_SOURCES = _COMMON + ("kernels_gj.h", "kernels_seg.h", "kernels_seg.hip", "kernels_mfma.hip",
                           "kernels_mfma_tiles.hip", "kernels_rows.hip", "kernels_solve.h",
-                          "kernels_solve.hip")
+                          "kernels_solve.hip", "kernels_tri.h", "kernels_tri.hip")
 
 
 def source_hash(kernel_name):
@@ -142,7 +151,7 @@ def main():
               "sharding is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
     run = {"bvp": run_bvp, "babd": run_babd, "batch": run_batch, "serving": run_serving,
-           "ivp": run_ivp}
+           "ivp": run_ivp, "tridiag": run_bvp}
     out = run[args.workload](args)
     print(json.dumps(out), flush=True)
 
@@ -155,7 +164,8 @@ def run_bvp(args):
     from paper_0912_3678_amd import workloads as wl
 
     dev = torch.device("cuda", 0)
-    s = wl.trapezoid_bvp_btri(N=args.N, m=args.m)
+    tri = args.workload == "tridiag"
+    s = wl.scalar_tridiagonal(n=args.n_tri) if tri else wl.trapezoid_bvp_btri(N=args.N, m=args.m)
     m, nb = s.m, s.nb
     n = m * nb
     D = wl.to_device_blocks(s.D, dev)
@@ -233,12 +243,19 @@ def run_bvp(args):
     M = 1 << (m - 1).bit_length()
     E = 0 if args.map == "rows" else (args.lane_entries or {8: 2, 16: 4, 32: 0}.get(M, 1))
     mfma = args.map == "auto" and not args.lane_entries and M == 8
+    # m = 1: rows staged through LDS (chains of up to 5 or 17 blocks)
+    trik = args.map == "auto" and M == 1
+    nint0 = levels[0][1] - (levels[0][2] - 1)
+    km = 5 if -(-nint0 // levels[0][2]) <= 5 else 17
     names = {"factor": ("k_btri_mfma<false>" if mfma else
+                        f"k_tri_factor<{km}, false, false>" if trik else
                         f"k_btri_seg<{M}, {E}, double, false, false>" if E else
                         f"k_btri_factor<{M}, double, false>"),
              "factor+forward": ("k_btri_mfma<true>" if mfma else
+                                f"k_tri_factor<{km}, false, true>" if trik else
                                 f"k_btri_seg<{M}, {E}, double, false, true>"),
-             "forward": f"k_fwd<0, {M}, 1, double, false>", "backward": f"k_bwd<0, {M}, 1, double>"}
+             "forward": f"k_fwd<0, {M}, 1, double, false>",
+             "backward": f"k_tri_bwd<{km}>" if trik else f"k_bwd<0, {M}, 1, double>"}
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6
     achieved = dom_bytes / (dom["avg_us"] * 1e-6) / 1e9
@@ -258,11 +275,13 @@ def run_bvp(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "trapezoid_bvp_btri", "N": args.N, "m": m, "nb": nb,
+        "config": {"workload": "scalar_tridiagonal" if tri else "trapezoid_bvp_btri",
+                   "N": nb if tri else args.N, "m": m, "nb": nb,
                    "unknowns": n, "nrhs": 1,
                    "partitions": args.partitions or "planner",
                    "lane_mapping": ("rows" if args.map == "rows" else
                                     "matrix cores at level 0, segments above" if mfma else
+                                    "one partition per lane, rows staged through LDS" if trik else
                                     f"segments of {E}"),
                    "levels": [[k, a, b] for k, a, b in levels],
                    "step": "pf_refactor + pf_solve" if args.split else
@@ -299,14 +318,19 @@ def run_bvp(args):
         t_end = time.perf_counter() + args.cpu_seconds
         while time.perf_counter() < t_end or not times:
             t1 = time.perf_counter()
-            xo = oracle.btri_solve(s.D, s.Lo, s.Up, s.f)
+            if tri:
+                xo = oracle.thomas(s.Lo.ravel(), s.D.ravel(), s.Up.ravel(), s.f)
+            else:
+                xo = oracle.btri_solve(s.D, s.Lo, s.Up, s.f)
             times.append(time.perf_counter() - t1)
         med = float(np.median(times))
         xg = x[0].cpu().numpy()
+        how = ("Thomas elimination" if tri else
+               f"band LU with partial pivoting (kl=ku={2 * m - 1})")
         out["cpu_baseline"] = {"value": n / med, "unit": "unknowns/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"the full system (n={n}), band LU with partial pivoting "
-                                         f"(kl=ku={2 * m - 1}), median of {len(times)} solves",
+                               "sample": f"the full system (n={n}), {how}, "
+                                         f"median of {len(times)} solves",
                                "gpu_vs_oracle_rel_err": float(np.abs(xg - xo).max() / np.abs(xo).max())}
     return out
 

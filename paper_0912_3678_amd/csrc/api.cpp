@@ -4,6 +4,7 @@
 // FP64 iterative refinement.
 #include "pf.h"
 #include "pf_internal.h"
+#include "kernels_tri.h"
 
 #include <algorithm>
 #include <cmath>
@@ -140,12 +141,17 @@ constexpr int kMapMfmaB16 = -3;
 // every level of an FP64 block tridiagonal matrix with m = 16: the m = 32
 // kernel's scheme with one tile per product (kernels_mfma_tiles.hip)
 constexpr int kMapMfma16 = -4;
+// every level of an FP64 block tridiagonal matrix with m = 1 whose chains fit
+// the workgroup's LDS: the segment mapping's arithmetic, rows staged through
+// LDS so that loads and stores are contiguous (kernels_tri.hip)
+constexpr int kMapTri = -5;
 
 int seg_width(int M, int level, int kind, bool f32, const pf_opts &o)
 {
     if (o.flags & PF_FLAG_MAP_ROWS) return 0;
     if (M == 32 && kind == PF_BTRI && !f32) return kMapMfma32;
     if (level == 0 && o.lane_entries > 0) return seg_ok(M, o.lane_entries) ? o.lane_entries : 0;
+    if (M == 1 && kind == PF_BTRI && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS)) return kMapTri;
     if (M == 16 && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS))
         return kind == PF_BABD ? kMapMfmaB16 : kMapMfma16;
     if (level == 0 && !(o.flags & PF_FLAG_MAP_SEGMENTS) && mfma_ok(kind, M, f32, false)) return kMapMfma;
@@ -406,6 +412,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
             if (L.seg == kMapMfma32) return launch_mfma32_factor(a, s);
             if (L.seg == kMapMfma16) return launch_mfma16_factor(a, nullptr, s);
             if (L.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, nullptr, s);
+            if (L.seg == kMapTri) return launch_tri_factor(a, nullptr, s);
             if (L.seg) return launch_seg_factor(L.kind, F->M, L.seg, L.f32, a, nullptr, s);
             return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
                                        : launch_babd_factor(F->M, L.f32, a, s);
@@ -495,8 +502,9 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
     for (size_t l = L; l-- > 0;) {
         const Level &lv = F->lv[l];
         HIPCHK(prof_launch(F, false, 2, (int)l, s, [&] {
-            return lv.kind == PF_BTRI ? launch_btri_bwd(M, lv.f32, args[l], s)
-                                      : launch_babd_bwd(M, lv.f32, args[l], s);
+            return lv.kind != PF_BTRI ? launch_babd_bwd(M, lv.f32, args[l], s)
+                   : (lv.seg == kMapTri && args[l].nrhs == 1) ? launch_tri_bwd(args[l], s)
+                                                              : launch_btri_bwd(M, lv.f32, args[l], s);
         }));
     }
     if (M != F->m)
@@ -543,6 +551,7 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
             if (lv.seg == kMapMfma) return launch_mfma_factor(a, &args[l], s);
             if (lv.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, &args[l], s);
             if (lv.seg == kMapMfma16) return launch_mfma16_factor(a, &args[l], s);
+            if (lv.seg == kMapTri) return launch_tri_factor(a, &args[l], s);
             return launch_seg_factor(lv.kind, M, lv.seg, lv.f32, a, &args[l], s);
         }));
     }
@@ -550,8 +559,9 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
     for (size_t l = L; l-- > 0;) {
         const Level &lv = F->lv[l];
         HIPCHK(prof_launch(F, false, 2, (int)l, s, [&] {
-            return lv.kind == PF_BTRI ? launch_btri_bwd(M, lv.f32, args[l], s)
-                                      : launch_babd_bwd(M, lv.f32, args[l], s);
+            return lv.kind != PF_BTRI ? launch_babd_bwd(M, lv.f32, args[l], s)
+                   : (lv.seg == kMapTri && args[l].nrhs == 1) ? launch_tri_bwd(args[l], s)
+                                                              : launch_btri_bwd(M, lv.f32, args[l], s);
         }));
     }
     if (M != F->m)
@@ -719,6 +729,7 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         L.p = plan[l].p;
         L.f32 = (l == 0 && o.prec == PF_FP32_IR);
         L.seg = seg_width(M, (int)l, L.kind, L.f32, o);
+        if (L.seg == kMapTri && !tri_fits(L.nb, L.p)) L.seg = 1;
         if (l == 0) {
             L.D = D0; L.Lo = Lo0;
             if (A->kind == PF_BTRI) L.Up = Up0;
@@ -1624,6 +1635,9 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
         if (factor_setup(&A[i], os[i], us, B->arena, scratch, &F)) return fail(PF_ENOMEM);
         ++ar.refs;
         B->F[i] = F;
+        // grouped launches run the segment kernels (same arithmetic)
+        for (Level &L : F->lv)
+            if (L.seg == kMapTri) L.seg = 1;
         if (ensure_workspace(F, std::max(nrhs[i], 1))) return fail(PF_ENOMEM);
         // status, ||A|| and per-column norm words of all systems are
         // contiguous: one fill, one read-back per refinement sweep
