@@ -113,6 +113,7 @@ KERNEL_SOURCES = {
     "k_babd_factor": _COMMON + ("kernels_rows.hip",),
     "k_tri_factor": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
     "k_tri_bwd": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
+    "k_tri_fwd": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
 }
 _ALL_SOURCES = _COMMON + ("kernels_gj.h", "kernels_seg.h", "kernels_seg.hip", "kernels_mfma.hip",
                           "kernels_mfma_tiles.hip", "kernels_rows.hip", "kernels_solve.h",
@@ -243,10 +244,10 @@ def run_bvp(args):
     M = 1 << (m - 1).bit_length()
     E = 0 if args.map == "rows" else (args.lane_entries or {8: 2, 16: 4, 32: 0}.get(M, 1))
     mfma = args.map == "auto" and not args.lane_entries and M == 8
-    # m = 1: rows staged through LDS (chains of up to 5 or 17 blocks)
+    # m = 1: rows staged through LDS (chains of up to 5, 9, 13 or 17 blocks)
     trik = args.map == "auto" and M == 1
     nint0 = levels[0][1] - (levels[0][2] - 1)
-    km = 5 if -(-nint0 // levels[0][2]) <= 5 else 17
+    km = next(k for k in (5, 9, 13, 17, 10 ** 9) if -(-nint0 // levels[0][2]) <= k)
     names = {"factor": ("k_btri_mfma<false>" if mfma else
                         f"k_tri_factor<{km}, false, false>" if trik else
                         f"k_btri_seg<{M}, {E}, double, false, false>" if E else
@@ -254,7 +255,7 @@ def run_bvp(args):
              "factor+forward": ("k_btri_mfma<true>" if mfma else
                                 f"k_tri_factor<{km}, false, true>" if trik else
                                 f"k_btri_seg<{M}, {E}, double, false, true>"),
-             "forward": f"k_fwd<0, {M}, 1, double, false>",
+             "forward": f"k_tri_fwd<{km}, false>" if trik else f"k_fwd<0, {M}, 1, double, false>",
              "backward": f"k_tri_bwd<{km}>" if trik else f"k_bwd<0, {M}, 1, double>"}
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6

@@ -495,8 +495,9 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
     for (size_t l = 0; l < L; ++l) {
         const Level &lv = F->lv[l];
         HIPCHK(prof_launch(F, false, 1, (int)l, s, [&] {
-            return lv.kind == PF_BTRI ? launch_btri_fwd(M, lv.f32, args[l], s)
-                                      : launch_babd_fwd(M, lv.f32, args[l], s);
+            return lv.kind != PF_BTRI ? launch_babd_fwd(M, lv.f32, args[l], s)
+                   : (lv.seg == kMapTri && args[l].nrhs == 1) ? launch_tri_fwd(args[l], s)
+                                                              : launch_btri_fwd(M, lv.f32, args[l], s);
         }));
     }
     for (size_t l = L; l-- > 0;) {

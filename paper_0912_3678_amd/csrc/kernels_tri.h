@@ -27,6 +27,10 @@ bool tri_fits(int64_t nb, int64_t p);
 // sv->Fadd) select the two-addend form of the reduced levels.
 hipError_t launch_tri_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
 
+// forward sweep of a block tridiagonal level with m = 1 (stored factors), one
+// right-hand side, FP64 factors; sv.Fadd selects the two-addend form
+hipError_t launch_tri_fwd(const SolveArgs &a, hipStream_t s);
+
 // back substitution of a block tridiagonal level with m = 1, one right-hand
 // side, FP64 factors
 hipError_t launch_tri_bwd(const SolveArgs &a, hipStream_t s);

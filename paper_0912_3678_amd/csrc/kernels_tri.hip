@@ -28,21 +28,57 @@ struct Chunk {
     int len0;        // length of partition 0 when the chunk holds it, else 0
 };
 
-__device__ __forceinline__ Chunk tri_chunk(int64_t nb, int64_t p, int64_t blk)
+// The balanced partition rule (partition i: q + [i < rem] blocks, then its
+// right separator) from one division per workgroup.
+struct Split {
+    int64_t q, rem;
+    __device__ __forceinline__ int64_t start(int64_t i) const { return i * (q + 1) + (i < rem ? i : rem); }
+    __device__ __forceinline__ int len(int64_t i) const { return (int)(q + (i < rem ? 1 : 0)); }
+};
+
+__device__ __forceinline__ Split tri_split(int64_t nb, int64_t p)
+{
+    const int64_t nint = nb - (p - 1);
+    Split s;
+    if (nint <= 0x7FFFFFFF && p <= 0x7FFFFFFF) s.q = (int64_t)((uint32_t)nint / (uint32_t)p);
+    else s.q = nint / p;
+    s.rem = nint - s.q * p;
+    return s;
+}
+
+__device__ __forceinline__ Chunk tri_chunk(const Split &sp, int64_t p, int64_t blk)
 {
     Chunk c;
     c.part0 = blk * kTriWG;
     const int64_t last = (c.part0 + kTriWG < p ? c.part0 + kTriWG : p) - 1;
-    const Geo g0 = geometry<0>(nb, p, c.part0), gl = geometry<0>(nb, p, last);
-    c.c0 = g0.start;
-    c.nr = (int)(gl.start + gl.len + 1 - g0.start);
-    const int64_t nint = nb - (p - 1), rem = nint % p;
-    c.q = (int)(nint / p);
-    const int64_t a = rem - c.part0;
+    c.c0 = sp.start(c.part0);
+    c.nr = (int)(sp.start(last) + sp.len(last) + 1 - c.c0);
+    c.q = (int)sp.q;
+    const int64_t a = sp.rem - c.part0;
     const int64_t nparts = last - c.part0 + 1;
     c.nA = (int)(a < 0 ? 0 : (a > nparts ? nparts : a));
-    c.len0 = c.part0 == 0 ? g0.len : 0;
+    c.len0 = c.part0 == 0 ? sp.len(0) : 0;
     return c;
+}
+
+// the lane's partition: its first row relative to the chunk, its length
+// and whether it has a left / right separator
+struct Lane {
+    int64_t part;
+    int o, len;
+    bool valid, hasL, hasR;
+};
+
+__device__ __forceinline__ Lane tri_lane(const Split &sp, int64_t p, const Chunk &c, int lane)
+{
+    Lane l;
+    l.part = c.part0 + lane;
+    l.valid = l.part < p;
+    l.o = l.valid ? (int)(sp.start(l.part) - c.c0) : 0;
+    l.len = l.valid ? sp.len(l.part) : 0;
+    l.hasL = l.valid && l.part > 0;
+    l.hasR = l.valid && l.part < p - 1;
+    return l;
 }
 
 // whether local row i of the chunk is a separator
@@ -70,7 +106,8 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
     __shared__ double sF[RHS ? NR : 1];
     const int lane = threadIdx.x;
     const int64_t nb = a.nb, p = a.p;
-    const Chunk c = tri_chunk(nb, p, blockIdx.x);
+    const Split sp = tri_split(nb, p);
+    const Chunk c = tri_chunk(sp, p, blockIdx.x);
 
     // raw buffers based at the chunk's first row: rows past an array's end
     // read zero and take no stores
@@ -116,9 +153,9 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
     // the chain of partition `part`; the rows it reads and writes are its
     // own, apart from its right separator's D and f (read only) and its left
     // separator's couplings (read only, at local row o - 1)
-    const int64_t part = c.part0 + lane;
-    const Geo G = geometry<0>(nb, p, part);
-    const int o = G.valid ? (int)(G.start - c.c0) : 0;
+    const Lane G = tri_lane(sp, p, c, lane);
+    const int64_t part = G.part, g0 = c.c0 + G.o;
+    const int o = G.o;
     double d = 0.0, fp = 0.0, z = 0.0, rr = 0.0, a1 = 0.0, gl = 0.0;
     if (G.valid) {
         d = sD[o];
@@ -126,8 +163,8 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
     }
     if (G.hasL) {
         if (lane == 0) {   // the previous workgroup's separator
-            z = a.Lo[G.start - 1];
-            rr = a.Up[G.start - 1];
+            z = a.Lo[g0 - 1];
+            rr = a.Up[g0 - 1];
         } else {
             z = sL[o - 1];
             rr = sU[o - 1];
@@ -144,7 +181,7 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
             dn = sD[i + 2];
             if constexpr (RHS) fn = sF[i + 2];
         }
-        const unsigned long long code = status_code(a.level, G.start + k);
+        const unsigned long long code = status_code(a.level, g0 + k);
         bad = (d == 0.0 && code < bad) ? code : bad;
         const double e = recip(d);             // E_k = D'_k^{-1}
         const double x = prod(e, cu);          // X_k = E_k A(g,g+1)
@@ -197,6 +234,67 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
     }
 }
 
+// Forward sweep of one level (one right-hand side) with stored factors:
+// t_k = E_k f'_k, f'_{k+1} = f_{g+1} - A(g+1,g) t_k, g_sL -= R_k t_k.
+template <int KM, bool ADD>
+__global__ __launch_bounds__(kTriWG) void k_tri_fwd(SolveArgs a)
+{
+    constexpr int NR = kTriWG * (KM + 1);
+    __shared__ double sE[NR], sR[NR], sL[NR], sF[NR];
+    const int lane = threadIdx.x;
+    const int64_t nb = a.nb, p = a.p;
+    const Split sp = tri_split(nb, p);
+    const Chunk c = tri_chunk(sp, p, blockIdx.x);
+    const uint64_t n0 = (uint64_t)(nb - c.c0) * 8;
+    const uint64_t n1 = nb - 1 > c.c0 ? (uint64_t)(nb - 1 - c.c0) * 8 : 0;
+    const auto rE = buf_rsrc((const double *)a.E + c.c0, n0);
+    const auto rR = buf_rsrc((const double *)a.R + c.c0, n0);
+    const auto rL = buf_rsrc(a.Lo + c.c0, n1);
+    const auto rF = buf_rsrc(a.F + c.c0, n0);
+    const auto rFa = buf_rsrc(ADD ? a.Fadd + c.c0 : a.F, ADD ? n0 : 0);
+    for (int i0 = 0; i0 < c.nr; i0 += kStage * kTriWG) {
+        double e[kStage], r[kStage], l[kStage], f[kStage];
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const uint32_t o = (uint32_t)(i0 + k * kTriWG + lane) * 8u;
+            e[k] = buf_ld(rE, o);
+            r[k] = buf_ld(rR, o);
+            l[k] = buf_ld(rL, o);
+            f[k] = buf_ld(rF, o);
+            if constexpr (ADD) f[k] += buf_ld(rFa, o);
+        }
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int i = i0 + k * kTriWG + lane;
+            if (i < c.nr) {
+                sE[i] = e[k];
+                sR[i] = r[k];
+                sL[i] = l[k];
+                sF[i] = f[k];
+            }
+        }
+    }
+    wave_sync();
+    const Lane G = tri_lane(sp, p, c, lane);
+    const int o = G.o;
+    double fp = G.valid ? sF[o] : 0.0, gl = 0.0;
+    for (int k = 0; k < G.len; ++k) {
+        const int i = o + k;
+        const double t = prod(sE[i], fp);      // t_k
+        const double rr = G.hasL ? sR[i] : 0.0;   // partition 0 stores no R
+        const double fn = sF[i + 1];
+        sF[i] = t;
+        fp = fn - prod(sL[i], t);
+        gl -= prod(rr, t);
+    }
+    if (G.hasR) a.nF[G.part] = fp;
+    if (G.hasL) a.nFadd[G.part - 1] = gl;
+    wave_sync();
+    const auto rY = buf_rsrc(a.Y + c.c0, n0);
+    for (int i = lane; i < c.nr; i += kTriWG)
+        if (!tri_sep(c, i)) buf_st(rY, (uint32_t)i * 8u, sF[i]);
+}
+
 // Back substitution of one level (one right-hand side):
 // x_k = t_k - Zh_k x_sL - X_k x_{k+1}, from the partition's last row up.
 template <int KM>
@@ -206,7 +304,8 @@ __global__ __launch_bounds__(kTriWG) void k_tri_bwd(SolveArgs a)
     __shared__ double sZ[NR], sX[NR], sT[NR];
     const int lane = threadIdx.x;
     const int64_t nb = a.nb, p = a.p;
-    const Chunk c = tri_chunk(nb, p, blockIdx.x);
+    const Split sp = tri_split(nb, p);
+    const Chunk c = tri_chunk(sp, p, blockIdx.x);
     const uint64_t n0 = (uint64_t)(nb - c.c0) * 8;
     const auto rZ = buf_rsrc((const double *)a.Z + c.c0, n0);
     const auto rX = buf_rsrc((const double *)a.X + c.c0, n0);
@@ -230,9 +329,9 @@ __global__ __launch_bounds__(kTriWG) void k_tri_bwd(SolveArgs a)
             }
         }
     }
-    const int64_t part = c.part0 + lane;
-    const Geo G = geometry<0>(nb, p, part);
-    const int o = G.valid ? (int)(G.start - c.c0) : 0;
+    const Lane G = tri_lane(sp, p, c, lane);
+    const int64_t part = G.part;
+    const int o = G.o;
     const double xl = G.hasL ? a.Xsep[part - 1] : 0.0;
     const double xr = G.hasR ? a.Xsep[part] : 0.0;
     wave_sync();
@@ -254,6 +353,18 @@ int tri_kmax(int64_t nb, int64_t p)
     return (int)(nint / p + (nint % p ? 1 : 0));
 }
 
+// LDS arrays sized for the level's longest chain (5, 9, 13 or 17 blocks):
+// the smaller they are, the more workgroups share a compute unit
+template <typename F>
+void dispatch_km(int64_t nb, int64_t p, F &&f)
+{
+    const int k = tri_kmax(nb, p);
+    if (k <= 5) f(std::integral_constant<int, 5>{});
+    else if (k <= 9) f(std::integral_constant<int, 9>{});
+    else if (k <= 13) f(std::integral_constant<int, 13>{});
+    else f(std::integral_constant<int, kTriMaxChain>{});
+}
+
 }  // namespace
 
 bool tri_fits(int64_t nb, int64_t p)
@@ -268,8 +379,8 @@ hipError_t launch_tri_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_
     const dim3 grid((unsigned)((a.p + kTriWG - 1) / kTriWG));
     const SolveArgs none{};
     const SolveArgs &v = sv ? *sv : none;
-    const bool add = a.Dadd != nullptr, small = tri_kmax(a.nb, a.p) <= 5;
-    auto go = [&](auto km) {
+    const bool add = a.Dadd != nullptr;
+    dispatch_km(a.nb, a.p, [&](auto km) {
         constexpr int K = decltype(km)::value;
         if (add) {
             if (sv) launch_k((k_tri_factor<K, true, true>), grid, dim3(kTriWG), s, a, v);
@@ -278,9 +389,19 @@ hipError_t launch_tri_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_
             if (sv) launch_k((k_tri_factor<K, false, true>), grid, dim3(kTriWG), s, a, v);
             else launch_k((k_tri_factor<K, false, false>), grid, dim3(kTriWG), s, a, v);
         }
-    };
-    if (small) go(std::integral_constant<int, 5>{});
-    else go(std::integral_constant<int, kTriMaxChain>{});
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_fwd(const SolveArgs &a, hipStream_t s)
+{
+    if (!tri_fits(a.nb, a.p) || a.nrhs != 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.p + kTriWG - 1) / kTriWG));
+    dispatch_km(a.nb, a.p, [&](auto km) {
+        constexpr int K = decltype(km)::value;
+        if (a.Fadd) launch_k((k_tri_fwd<K, true>), grid, dim3(kTriWG), s, a);
+        else launch_k((k_tri_fwd<K, false>), grid, dim3(kTriWG), s, a);
+    });
     return hipGetLastError();
 }
 
@@ -288,8 +409,9 @@ hipError_t launch_tri_bwd(const SolveArgs &a, hipStream_t s)
 {
     if (!tri_fits(a.nb, a.p) || a.nrhs != 1) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((a.p + kTriWG - 1) / kTriWG));
-    if (tri_kmax(a.nb, a.p) <= 5) launch_k((k_tri_bwd<5>), grid, dim3(kTriWG), s, a);
-    else launch_k((k_tri_bwd<kTriMaxChain>), grid, dim3(kTriWG), s, a);
+    dispatch_km(a.nb, a.p, [&](auto km) {
+        launch_k((k_tri_bwd<decltype(km)::value>), grid, dim3(kTriWG), s, a);
+    });
     return hipGetLastError();
 }
 
