@@ -90,6 +90,14 @@ __device__ __forceinline__ bool tri_sep(const Chunk &c, int i)
     return u < ea ? (u % wa == wa - 1u) : ((u - ea) % wb == wb - 1u);
 }
 
+// bytes of an array a staging load may read: the chunk's rows, within the
+// array's n bytes from the chunk's first row
+__device__ __forceinline__ uint64_t tri_span(uint64_t n, const Chunk &c)
+{
+    const uint64_t w = (uint64_t)c.nr * 8;
+    return n < w ? n : w;
+}
+
 __device__ __forceinline__ double prod(double u, double v)
 {
     const double a[1] = {u}, b[1] = {v};
@@ -110,15 +118,17 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
     const Chunk c = tri_chunk(sp, p, blockIdx.x);
 
     // raw buffers based at the chunk's first row: rows past an array's end
-    // read zero and take no stores
+    // take no stores, and loads past the chunk or the array read zero
+    // without touching memory
     const uint64_t n0 = (uint64_t)(nb - c.c0) * 8;
     const uint64_t n1 = nb - 1 > c.c0 ? (uint64_t)(nb - 1 - c.c0) * 8 : 0;
-    const auto rD = buf_rsrc(a.D + c.c0, n0);
-    const auto rDa = buf_rsrc(ADD ? a.Dadd + c.c0 : a.D, ADD ? n0 : 0);
-    const auto rL = buf_rsrc(a.Lo + c.c0, n1);
-    const auto rU = buf_rsrc(a.Up + c.c0, n1);
-    const auto rF = buf_rsrc(RHS ? sv.F + c.c0 : a.D, RHS ? n0 : 0);
-    const auto rFa = buf_rsrc((RHS && ADD) ? sv.Fadd + c.c0 : a.D, (RHS && ADD) ? n0 : 0);
+    const uint64_t m0 = tri_span(n0, c), m1 = tri_span(n1, c);
+    const auto rD = buf_rsrc(a.D + c.c0, m0);
+    const auto rDa = buf_rsrc(ADD ? a.Dadd + c.c0 : a.D, ADD ? m0 : 0);
+    const auto rL = buf_rsrc(a.Lo + c.c0, m1);
+    const auto rU = buf_rsrc(a.Up + c.c0, m1);
+    const auto rF = buf_rsrc(RHS ? sv.F + c.c0 : a.D, RHS ? m0 : 0);
+    const auto rFa = buf_rsrc((RHS && ADD) ? sv.Fadd + c.c0 : a.D, (RHS && ADD) ? m0 : 0);
 
     // stage D (+ Dadd), A(g+1,g), A(g,g+1) and f (+ Fadd): kStage rows in
     // flight per lane, each instruction reading 64 consecutive rows
@@ -247,11 +257,12 @@ __global__ __launch_bounds__(kTriWG) void k_tri_fwd(SolveArgs a)
     const Chunk c = tri_chunk(sp, p, blockIdx.x);
     const uint64_t n0 = (uint64_t)(nb - c.c0) * 8;
     const uint64_t n1 = nb - 1 > c.c0 ? (uint64_t)(nb - 1 - c.c0) * 8 : 0;
-    const auto rE = buf_rsrc((const double *)a.E + c.c0, n0);
-    const auto rR = buf_rsrc((const double *)a.R + c.c0, n0);
-    const auto rL = buf_rsrc(a.Lo + c.c0, n1);
-    const auto rF = buf_rsrc(a.F + c.c0, n0);
-    const auto rFa = buf_rsrc(ADD ? a.Fadd + c.c0 : a.F, ADD ? n0 : 0);
+    const uint64_t m0 = tri_span(n0, c), m1 = tri_span(n1, c);
+    const auto rE = buf_rsrc((const double *)a.E + c.c0, m0);
+    const auto rR = buf_rsrc((const double *)a.R + c.c0, m0);
+    const auto rL = buf_rsrc(a.Lo + c.c0, m1);
+    const auto rF = buf_rsrc(a.F + c.c0, m0);
+    const auto rFa = buf_rsrc(ADD ? a.Fadd + c.c0 : a.F, ADD ? m0 : 0);
     for (int i0 = 0; i0 < c.nr; i0 += kStage * kTriWG) {
         double e[kStage], r[kStage], l[kStage], f[kStage];
 #pragma unroll
@@ -306,9 +317,10 @@ __global__ __launch_bounds__(kTriWG) void k_tri_bwd(SolveArgs a)
     const int64_t nb = a.nb, p = a.p;
     const Split sp = tri_split(nb, p);
     const Chunk c = tri_chunk(sp, p, blockIdx.x);
-    const uint64_t n0 = (uint64_t)(nb - c.c0) * 8;
-    const auto rZ = buf_rsrc((const double *)a.Z + c.c0, n0);
-    const auto rX = buf_rsrc((const double *)a.X + c.c0, n0);
+    const uint64_t n0 = (uint64_t)(nb - c.c0) * 8, m0 = tri_span(n0, c);
+    const auto rZ = buf_rsrc((const double *)a.Z + c.c0, m0);
+    const auto rX = buf_rsrc((const double *)a.X + c.c0, m0);
+    const auto rT = buf_rsrc(a.Y + c.c0, m0);
     const auto rY = buf_rsrc(a.Y + c.c0, n0);
     for (int i0 = 0; i0 < c.nr; i0 += kStage * kTriWG) {
         double z[kStage], x[kStage], t[kStage];
@@ -317,7 +329,7 @@ __global__ __launch_bounds__(kTriWG) void k_tri_bwd(SolveArgs a)
             const uint32_t o = (uint32_t)(i0 + k * kTriWG + lane) * 8u;
             z[k] = buf_ld(rZ, o);
             x[k] = buf_ld(rX, o);
-            t[k] = buf_ld(rY, o);
+            t[k] = buf_ld(rT, o);
         }
 #pragma unroll
         for (int k = 0; k < kStage; ++k) {
