@@ -116,6 +116,10 @@ int target_rows(int kind, int M, bool f32, int level, const pf_opts &o)
     // as 4 there and leaves a reduced system a quarter the size (m = 16 BVP,
     // N = 2^18: 0.97 vs 1.08 ms per step).
     if (level == 0) return (M <= 8 || (kind == PF_BABD && M == 16 && !f32)) ? 16 : 4;
+    // scalar tridiagonal reduced levels run their chains out of LDS, where a
+    // block row costs little: 8 blocks per partition (8 levels instead of 11
+    // for n = 2^24, 0.696 vs 0.720 ms per step; n = 4096: 52 vs 59 us)
+    if (kind == PF_BTRI && M == 1) return 8;
     return 3;
 }
 

@@ -107,6 +107,18 @@ def test_plan_finest_chain_lengths():
     assert p0(pf.PF_BABD, 12, 262145) == (262145 - 1) // 17    # padded to 16
 
 
+def test_plan_reduced_chain_lengths():
+    """Reduced levels of block tridiagonal matrices: 3 blocks per partition,
+    8 for scalar tridiagonal matrices (their chains run out of LDS); the
+    last levels at most kTail = 6 blocks are one chain."""
+    for m, L in ((1, 8), (8, 3)):
+        plan = pf.pf_plan(_mat(pf.PF_BTRI, m, 1 << 20))
+        for k, n, p in plan[1:]:
+            want = 1 if n <= 6 else min(max((n + 1) // (L + 1), 2), (n + 1) // 2)
+            assert p == want, (m, n, p, want)
+    assert len(pf.pf_plan(_mat(pf.PF_BTRI, 1, 1 << 24))) == 8
+
+
 def test_plan_reduced_size_depends_only_on_p():
     """The block size of T_p depends only on p, not on n (eq. (redmatr))."""
     for nb in (1000, 5000, 65537):
