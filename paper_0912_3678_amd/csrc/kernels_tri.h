@@ -6,9 +6,10 @@
 // loads; each lane then runs its partition's chain (the recurrences of the
 // block factorization, Sec. 2, with 1 x 1 blocks) out of LDS, and the
 // workgroup writes the per-row factors back contiguously.  The stored factors
-// and the reduced system are those of the segment mapping with one entry per
-// lane, bit for bit, so the forward sweep and the batched kernels read them
-// unchanged.
+// of the partitions' rows and the reduced system are those of the segment
+// mapping with one entry per lane, bit for bit, so the forward sweep and the
+// batched kernels read them unchanged (the separators' rows of the factor
+// arrays, which no kernel reads, hold other values).
 #pragma once
 #include <hip/hip_runtime.h>
 

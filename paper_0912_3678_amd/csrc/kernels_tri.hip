@@ -5,8 +5,11 @@
 // instruction (one per partition); here the workgroup first copies its
 // partitions' rows into LDS with contiguous loads, runs the chains out of
 // LDS, and writes the per-row factors back with contiguous stores.  The
-// arithmetic is that of the segment mapping with one entry per lane, in the
-// same order, so both give the same bits.
+// stores cover every row of the workgroup's range, separators included
+// (nothing reads a separator's factor row): skipping them left a partly
+// written cache line every 17 rows, which cost about 40 % of the factor's
+// time.  The arithmetic is that of the segment mapping with one entry per
+// lane, in the same order, so both give the same bits.
 #include "kernels_common.h"
 #include "kernels_tri.h"
 
@@ -23,9 +26,6 @@ struct Chunk {
     int64_t c0;      // first row
     int nr;          // rows
     int64_t part0;   // first partition
-    int nA;          // leading partitions of length q + 1 (the rest have q)
-    int q;           // shorter partition length
-    int len0;        // length of partition 0 when the chunk holds it, else 0
 };
 
 // The balanced partition rule (partition i: q + [i < rem] blocks, then its
@@ -53,11 +53,6 @@ __device__ __forceinline__ Chunk tri_chunk(const Split &sp, int64_t p, int64_t b
     const int64_t last = (c.part0 + kTriWG < p ? c.part0 + kTriWG : p) - 1;
     c.c0 = sp.start(c.part0);
     c.nr = (int)(sp.start(last) + sp.len(last) + 1 - c.c0);
-    c.q = (int)sp.q;
-    const int64_t a = sp.rem - c.part0;
-    const int64_t nparts = last - c.part0 + 1;
-    c.nA = (int)(a < 0 ? 0 : (a > nparts ? nparts : a));
-    c.len0 = c.part0 == 0 ? sp.len(0) : 0;
     return c;
 }
 
@@ -79,15 +74,6 @@ __device__ __forceinline__ Lane tri_lane(const Split &sp, int64_t p, const Chunk
     l.hasL = l.valid && l.part > 0;
     l.hasR = l.valid && l.part < p - 1;
     return l;
-}
-
-// whether local row i of the chunk is a separator
-__device__ __forceinline__ bool tri_sep(const Chunk &c, int i)
-{
-    const unsigned wa = (unsigned)c.q + 2u, wb = (unsigned)c.q + 1u;
-    const unsigned ea = (unsigned)c.nA * wa;
-    const unsigned u = (unsigned)i;
-    return u < ea ? (u % wa == wa - 1u) : ((u - ea) % wb == wb - 1u);
 }
 
 // bytes of an array a staging load may read: the chunk's rows, within the
@@ -212,6 +198,7 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
         }
         rr = rn;
     }
+    if (G.valid) sR[o + G.len] = 0.0;   // the right separator's row (no factor)
     if (bad != ~0ull) atomicMin(a.status, bad);
     if (G.hasR) {
         a.nD[part] = d;                        // D[sR] + alpha_2
@@ -227,19 +214,20 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
     }
     wave_sync();
 
-    // factors of the partitions' rows (not of the separators), contiguous
+    // factors, contiguous.  The separators' rows are written too (with what
+    // LDS holds there; nothing reads them) so that stores cover whole cache
+    // lines; partition 0's R rows hold zero.
     const auto rE = buf_rsrc((double *)a.E + c.c0, n0);
     const auto rX = buf_rsrc((double *)a.X + c.c0, n0);
     const auto rZ = buf_rsrc((double *)a.Z + c.c0, n0);
     const auto rR = buf_rsrc((double *)a.R + c.c0, n0);
     const auto rY = buf_rsrc(RHS ? sv.Y + c.c0 : (double *)a.dump, RHS ? n0 : 0);
     for (int i = lane; i < c.nr; i += kTriWG) {
-        if (tri_sep(c, i)) continue;
         const uint32_t off = (uint32_t)i * 8u;
         buf_st(rE, off, sD[i]);
         buf_st(rX, off, sU[i]);
         buf_st(rZ, off, sL[i]);
-        if (i >= c.len0) buf_st(rR, off, sR[i]);   // partition 0 has no left separator
+        buf_st(rR, off, sR[i]);
         if constexpr (RHS) buf_st(rY, off, sF[i]);
     }
 }
@@ -303,7 +291,7 @@ __global__ __launch_bounds__(kTriWG) void k_tri_fwd(SolveArgs a)
     wave_sync();
     const auto rY = buf_rsrc(a.Y + c.c0, n0);
     for (int i = lane; i < c.nr; i += kTriWG)
-        if (!tri_sep(c, i)) buf_st(rY, (uint32_t)i * 8u, sF[i]);
+        buf_st(rY, (uint32_t)i * 8u, sF[i]);   // separators: their f, overwritten by x later
 }
 
 // Back substitution of one level (one right-hand side):
