@@ -124,6 +124,8 @@ int target_rows(int kind, int M, bool f32, int level, const pf_opts &o)
 }
 
 constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chain
+// (scalar tridiagonal reduced levels: up to kTriMaxChain blocks, one chain in
+// LDS)
 
 // Lane mapping of a level's factor kernel: segments of E entries per lane,
 // or rows (0).  One entry per lane (E = 1) spreads a chain row over M*M
@@ -191,7 +193,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
     while (true) {
         int64_t p;
         if (lvl == 0 && o.partitions > 0) p = o.partitions;
-        else if (cur <= kTail) p = 1;
+        else if (cur <= kTail || (M == 1 && lvl > 0 && cur <= kTriMaxChain)) p = 1;
         else {
             const int L = target_rows(kind, M, f32, lvl, o);
             p = (cur + 1) / (L + 1);

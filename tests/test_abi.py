@@ -109,14 +109,16 @@ def test_plan_finest_chain_lengths():
 
 def test_plan_reduced_chain_lengths():
     """Reduced levels of block tridiagonal matrices: 3 blocks per partition,
-    8 for scalar tridiagonal matrices (their chains run out of LDS); the
-    last levels at most kTail = 6 blocks are one chain."""
-    for m, L in ((1, 8), (8, 3)):
+    8 for scalar tridiagonal matrices (their chains run out of LDS); a
+    reduced level of at most 6 blocks (17 for scalar tridiagonal matrices)
+    is one chain."""
+    for m, L, tail in ((1, 8, 17), (8, 3, 6)):
         plan = pf.pf_plan(_mat(pf.PF_BTRI, m, 1 << 20))
         for k, n, p in plan[1:]:
-            want = 1 if n <= 6 else min(max((n + 1) // (L + 1), 2), (n + 1) // 2)
+            want = 1 if n <= tail else min(max((n + 1) // (L + 1), 2), (n + 1) // 2)
             assert p == want, (m, n, p, want)
-    assert len(pf.pf_plan(_mat(pf.PF_BTRI, 1, 1 << 24))) == 8
+        assert plan[-1][2] == 1
+    assert len(pf.pf_plan(_mat(pf.PF_BTRI, 1, 1 << 24))) == 7
 
 
 def test_plan_reduced_size_depends_only_on_p():
