@@ -341,3 +341,47 @@ def test_trapezoid_btri_regrouping_is_a_row_permutation(oracle):
     full = np.vstack(rows)
     key = lambda r: tuple(np.round(r, 12))
     assert sorted(map(key, A)) == sorted(map(key, full))
+
+
+def test_eta_hand_computed(oracle):
+    """The acceptance quantity eta = ||f - A x|| / (||A|| ||x|| + ||f||)
+    (infinity norms, per right-hand side) on a 2 x 2 block tridiagonal system
+    with m = 1 whose every value is worked out by hand:
+    A = [[2, -1], [1, 3]], ||A||_inf = max(2 + 1, 1 + 3) = 4.
+      column 0: x = (1, 2),      f = (1, 7):    A x = (0, 7),         r = (1, 0),
+                eta = 1 / (4*2 + 7) = 1/15 (both terms of the denominator count);
+      column 1: x = (0.5, -0.25), f = (100, 0): A x = (1.25, -0.25),  r = (98.75, 0.25),
+                eta = 98.75 / (4*0.5 + 100) = 98.75/102 (||f|| dominates);
+      column 2: x = (1000, 0),   f = (0, 1e-3): A x = (2000, 1000),   r = (-2000, -999.999),
+                eta = 2000 / (4*1000 + 1e-3) (||A|| ||x|| dominates).
+    A wrong axis, a missing norm or a one-norm in place of the max would
+    change at least one of the three."""
+    D = np.array([[[2.0]], [[3.0]]])
+    Lo = np.array([[[1.0]]])
+    Up = np.array([[[-1.0]]])
+    x = np.array([[1.0, 0.5, 1000.0], [2.0, -0.25, 0.0]])
+    f = np.array([[1.0, 100.0, 0.0], [7.0, 0.0, 1e-3]])
+    na = oracle.btri_norminf(D, Lo, Up)
+    assert na == 4.0
+    r = oracle.btri_residual(D, Lo, Up, f, x)
+    np.testing.assert_array_equal(r, np.array([[1.0, 98.75, -2000.0], [0.0, 0.25, 1e-3 - 1000.0]]))
+    e = oracle.eta(na, f, x, r)
+    expect = np.array([1.0 / 15.0, 98.75 / 102.0, 2000.0 / (4000.0 + 1e-3)])
+    np.testing.assert_allclose(e, expect, rtol=1e-15, atol=0)
+    # one right-hand side as a 1-D vector gives the same value
+    e1 = oracle.eta(na, f[:, 1], x[:, 1], r[:, 1])
+    assert np.shape(e1) == (1,)
+    assert abs(e1[0] - 98.75 / 102.0) <= 1e-15
+    # the bidiagonal-plus-corner form: A = [[2, 5], [1, 3]] (corner 5 in the
+    # top right), ||A||_inf = 7; x = (1, 1), f = (7, 5): r = (0, 1),
+    # eta = 1 / (7 + 7)
+    Db = np.array([[[2.0]], [[3.0]]])
+    Lb = np.array([[[1.0]]])
+    Cb = np.array([[5.0]])
+    nab = oracle.babd_norminf(Db, Lb, Cb)
+    assert nab == 7.0
+    xb = np.array([1.0, 1.0])
+    fb = np.array([7.0, 5.0])
+    rb = oracle.babd_residual(Db, Lb, Cb, fb, xb)
+    np.testing.assert_array_equal(rb, np.array([0.0, 1.0]))
+    assert abs(oracle.eta(nab, fb, xb, rb)[0] - 1.0 / 14.0) <= 1e-16
