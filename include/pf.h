@@ -62,8 +62,9 @@ enum {
     PF_OK = 0,
     PF_ESINGULAR = 1,   /* exactly zero pivot inside a pivot block            */
     PF_ENOCONV = 2,     /* refinement stagnated or hit max_refine            */
-    PF_ENOMEM = 3,      /* device allocation failed                          */
-    PF_EHIP = 4,        /* a HIP runtime call failed                         */
+    PF_ENOMEM = 3,      /* a device allocation ran out of memory             */
+    PF_EHIP = 4,        /* a HIP runtime call failed (any other error of an
+                           allocation included): pf_last_hip_error        */
     PF_EUNSUPPORTED = 5 /* block size beyond what the library instantiates   */
 };
 
@@ -129,6 +130,36 @@ typedef struct {
 } pf_info;
 
 typedef struct pf_factor_s *pf_factor_t;
+
+/* ---- device memory and HIP errors ----------------------------------------
+ * Ownership of factor memory (the factors, the reduced systems, the status
+ * words and the solve workspace of a handle; the one allocation of a batch):
+ * it is allocated through the allocator set here, and the handle or batch
+ * gives it back through the matching free when it is destroyed.  Default
+ * (and after pf_set_allocator(NULL, NULL, NULL)): stream-ordered
+ * hipMallocAsync / hipFreeAsync on the stream the handle was created on.
+ *   alloc(bytes, stream, ctx) returns device memory of at least `bytes`
+ *     bytes, 256-byte aligned, usable by work queued on `stream` (a
+ *     hipStream_t), or NULL when it has none (the call then fails with
+ *     PF_ENOMEM);
+ *   free(ptr, bytes, stream, ctx) takes back a block alloc returned; work
+ *     on `stream` that uses the block may still be queued, so the allocator
+ *     must order its reuse after that work (hipFreeAsync and PyTorch's
+ *     caching allocator both do).
+ * Each handle and batch keeps the allocator that was current when it was
+ * created (its blocks go back to that one).  Setting the allocator is not
+ * synchronized with other host threads creating handles.  Small argument
+ * tables of batches (a few bytes per partition block) and the plan of the IVP
+ * driver stay on hipMalloc / hipMallocAsync.  Returns 0, or -1 / -2 when only
+ * one of the two functions is given. */
+typedef void *(*pf_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*pf_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+int pf_set_allocator(pf_alloc_fn alloc, pf_free_fn free, void *ctx);
+
+/* The hipError_t of the most recent HIP call of the calling thread that made
+ * a library call fail with PF_EHIP (or PF_ENOMEM: hipErrorOutOfMemory);
+ * 0 if none has failed. */
+int pf_last_hip_error(void);
 
 /* Factor A (eqs. (parfact), (parblock) with the LU variant, applied
  * recursively to the reduced matrix (redmatr)/(redmatr1)).
@@ -227,8 +258,16 @@ int pf_batch_factor(pf_batch_t B, int32_t i, pf_factor_t *out);
 /* Release the batch (synchronizes its internal stream). */
 void pf_batch_destroy(pf_batch_t B);
 
-/* One-shot batch: create, run, optionally hand out every factor
- * (factors != NULL: factors[i] for the caller to destroy), destroy.
+/* One-shot batch: create, run, destroy.  factors (may be NULL) is in/out,
+ * one entry per system: an entry that is non-NULL on entry is the caller's
+ * existing factor of A[i] (same kind, m, nb and precision; from pf_factor, a
+ * batch or this call) and system i is solved with it, in the batch's grouped
+ * solve launches, without being factored again (the handle's solve
+ * workspace grows on its own stream if nrhs[i] needs it); an entry that is
+ * NULL on entry is factored by the batch and its new factor is handed out
+ * in it, for the caller to destroy.  An existing factor must not be used by
+ * other work while the call runs.  Argument errors as for pf_batch_create,
+ * and -10 for an existing factor that does not match A[i] or opts->prec.
  * Synchronizes `stream`. */
 int pf_solve_batch(int32_t nsys, const pf_matrix *A, const pf_opts *opts,
                    const int32_t *nrhs, const double *const *f, const int64_t *ldf,

@@ -37,23 +37,62 @@ struct PlanLevel {
 
 // One device allocation carved into the memory of many handles (a batch).
 // Shared by the batch and by the handles it hands out; freed by the last.
+// Device memory of handles and batches: the caller's allocator when one is
+// set (pf_set_allocator), else stream-ordered hipMallocAsync / hipFreeAsync.
+// Each handle and arena keeps the allocator it was created with, so that a
+// later pf_set_allocator does not pair a block with the wrong free.
+struct Allocator {
+    pf_alloc_fn alloc = nullptr;
+    pf_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+Allocator g_allocator;
+
+// the most recent failing HIP call of this thread (pf_last_hip_error)
+thread_local int g_last_hip = 0;
+
+// PF_ENOMEM for an allocation that ran out of memory, PF_EHIP (and the code
+// kept for pf_last_hip_error) for any other failure
+int alloc_status(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP;
+}
+
+hipError_t dev_alloc(const Allocator &a, void **p, size_t bytes, hipStream_t s)
+{
+    *p = nullptr;
+    if (a.alloc) {
+        *p = a.alloc(bytes, (void *)s, a.ctx);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMallocAsync(p, bytes, s);
+}
+
+void dev_free(const Allocator &a, void *p, size_t bytes, hipStream_t s)
+{
+    if (!p) return;
+    if (a.free) a.free(p, bytes, (void *)s, a.ctx);
+    else hipFreeAsync(p, s);
+}
+
+struct DevBlock {
+    void *p;
+    size_t bytes;
+};
+
 struct Arena {
     char *base = nullptr;
     size_t off = 0, cap = 0;
     bool counting = false;
-    bool stream_ordered = false;   // base from hipMallocAsync: freed the same way
+    Allocator al;   // what base came from (dev_alloc)
     int refs = 0;
 };
 
 void arena_release(Arena *ar, hipStream_t s)
 {
     if (--ar->refs > 0) return;
-    if (ar->stream_ordered) {
-        if (ar->base) hipFreeAsync(ar->base, s);
-    } else {
-        hipStreamSynchronize(s);
-        if (ar->base) hipFree(ar->base);
-    }
+    dev_free(ar->al, ar->base, ar->cap, s);
     delete ar;
 }
 
@@ -66,7 +105,8 @@ struct pf_factor_s {
     int64_t nb = 0;
     hipStream_t stream = nullptr;
     std::vector<Level> lv;
-    std::vector<void *> allocs;
+    Allocator al;                          // the allocator of its own blocks
+    std::vector<DevBlock> allocs;
     unsigned long long *d_status = nullptr;
     unsigned long long *d_norm = nullptr;  // ||A||_inf bits
     void *d_dump = nullptr;                // target of masked stores (kDumpBytes)
@@ -76,7 +116,7 @@ struct pf_factor_s {
     std::vector<double *> wsF, wsFadd, wsY;
     double *wsPadF = nullptr, *wsPadX = nullptr, *wsR = nullptr, *wsD = nullptr;
     unsigned long long *d_norms = nullptr;
-    std::vector<void *> ws_allocs;
+    std::vector<DevBlock> ws_allocs;
     // optional per-launch timing
     struct ProfSlot {
         int phase = 0, level = 0;
@@ -231,7 +271,7 @@ size_t plan_bytes(const std::vector<PlanLevel> &plan, int M, int m, const pf_opt
 // 256-byte aligned slices of a batch's arena.  A counting arena only adds up
 // sizes (the pointers it hands out are never dereferenced: no launch happens
 // while counting).
-hipError_t dalloc(pf_factor_s *F, void **p, size_t bytes, std::vector<void *> &list)
+hipError_t dalloc(pf_factor_s *F, void **p, size_t bytes, std::vector<DevBlock> &list)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 8;
@@ -243,15 +283,15 @@ hipError_t dalloc(pf_factor_s *F, void **p, size_t bytes, std::vector<void *> &l
         ar.off = off + bytes;
         return hipSuccess;
     }
-    hipError_t e = hipMallocAsync(p, bytes, F->stream);
+    hipError_t e = dev_alloc(F->al, p, bytes, F->stream);
     if (e != hipSuccess) { *p = nullptr; return e; }
-    list.push_back(*p);
+    list.push_back({*p, bytes});
     return hipSuccess;
 }
 
-void free_list(pf_factor_s *F, std::vector<void *> &list)
+void free_list(pf_factor_s *F, std::vector<DevBlock> &list)
 {
-    for (void *p : list) hipFreeAsync(p, F->stream);
+    for (const DevBlock &b : list) dev_free(F->al, b.p, b.bytes, F->stream);
     list.clear();
 }
 
@@ -292,7 +332,10 @@ int check_opts(const pf_matrix *A, const pf_opts &o)
 #define HIPCHK(x)                                   \
     do {                                            \
         hipError_t e_ = (x);                        \
-        if (e_ != hipSuccess) return PF_EHIP;       \
+        if (e_ != hipSuccess) {                     \
+            g_last_hip = (int)e_;                   \
+            return PF_EHIP;                         \
+        }                                           \
     } while (0)
 
 // Run one launch, bracketed by HIP events on its stream when profiling.
@@ -431,6 +474,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
 int ensure_workspace(pf_factor_s *F, int nrhs)
 {
     if (nrhs <= F->rhs_cap) return 0;
+    hipError_t e_;
     free_list(F, F->ws_allocs);
     // a handle carved from a batch arena grows its workspace in memory of
     // its own (the arena is sized for the batch's right-hand sides only)
@@ -449,32 +493,33 @@ int ensure_workspace(pf_factor_s *F, int nrhs)
     for (size_t l = 1; l < L; ++l) {
         const size_t bytes = (size_t)F->lv[l].nb * F->M * cap * sizeof(double);
         void *p;
-        if (dalloc(F, &p, bytes, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        if ((e_ = dalloc(F, &p, bytes, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
         F->wsF[l] = (double *)p;
         if (F->lv[l - 1].kind == PF_BTRI) {
-            if (dalloc(F, &p, bytes, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+            if ((e_ = dalloc(F, &p, bytes, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
             F->wsFadd[l] = (double *)p;
         }
-        if (dalloc(F, &p, bytes, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        if ((e_ = dalloc(F, &p, bytes, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
         F->wsY[l] = (double *)p;
     }
     const size_t nP = (size_t)F->nb * F->M * cap * sizeof(double);
     const size_t n = (size_t)F->nb * F->m * cap * sizeof(double);
     void *p;
     if (F->M != F->m) {
-        if (dalloc(F, &p, nP, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        if ((e_ = dalloc(F, &p, nP, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
         F->wsPadF = (double *)p;
-        if (dalloc(F, &p, nP, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        if ((e_ = dalloc(F, &p, nP, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
         F->wsPadX = (double *)p;
     }
     if (F->opts.prec == PF_FP32_IR) {   // residual and correction of the refinement
-        if (dalloc(F, &p, n, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        if ((e_ = dalloc(F, &p, n, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
         F->wsR = (double *)p;
-        if (dalloc(F, &p, n, F->ws_allocs) != hipSuccess) return PF_ENOMEM;
+        if ((e_ = dalloc(F, &p, n, F->ws_allocs)) != hipSuccess) return alloc_status(e_);
         F->wsD = (double *)p;
     }
-    if (dalloc(F, &p, 3 * (size_t)cap * sizeof(unsigned long long), F->ws_allocs) != hipSuccess)
-        return PF_ENOMEM;
+    if ((e_ = dalloc(F, &p, 3 * (size_t)cap * sizeof(unsigned long long), F->ws_allocs)) !=
+        hipSuccess)
+        return alloc_status(e_);
     F->d_norms = (unsigned long long *)p;
     F->rhs_cap = cap;
     return 0;
@@ -645,6 +690,15 @@ const char *pf_strerror(int code)
     }
 }
 
+int pf_set_allocator(pf_alloc_fn alloc, pf_free_fn free_fn, void *ctx)
+{
+    if ((alloc == nullptr) != (free_fn == nullptr)) return alloc ? -2 : -1;
+    g_allocator = Allocator{alloc, free_fn, alloc ? ctx : nullptr};
+    return 0;
+}
+
+int pf_last_hip_error(void) { return g_last_hip; }
+
 size_t pf_factor_bytes(const pf_matrix *A, const pf_opts *opts)
 {
     if (check_matrix(A) != 0) return 0;
@@ -681,6 +735,7 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
                  void *shared_scratch, pf_factor_s **out)
 {
     pf_factor_s *F = new pf_factor_s();
+    F->al = g_allocator;
     F->A = *A;
     F->opts = o;
     F->m = A->m;
@@ -697,31 +752,32 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         return code;
     };
     void *p;
-    if (dalloc(F, &p, 2 * sizeof(unsigned long long), F->allocs) != hipSuccess)
-        return fail(PF_ENOMEM);
+    hipError_t e_;
+    if ((e_ = dalloc(F, &p, 2 * sizeof(unsigned long long), F->allocs)) != hipSuccess)
+        return fail(alloc_status(e_));
     F->d_status = (unsigned long long *)p;
     F->d_norm = F->d_status + 1;
     if (shared_scratch) F->d_dump = shared_scratch;
-    else if (dalloc(F, &F->d_dump, kDumpBytes + kZeroBytes, F->allocs) != hipSuccess)
-        return fail(PF_ENOMEM);
+    else if ((e_ = dalloc(F, &F->d_dump, kDumpBytes + kZeroBytes, F->allocs)) != hipSuccess)
+        return fail(alloc_status(e_));
     F->d_zero = (const double *)((char *)F->d_dump + kDumpBytes);
 
     // level-0 matrix (padded to an instantiated block size if needed; the
     // padding itself runs in launch_factor_levels so refactor redoes it)
     const double *D0 = A->D, *Lo0 = A->Lo, *Up0 = A->Up, *C0 = A->C;
     if (M != A->m) {
-        if (dalloc(F, &p, A->nb * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+        if ((e_ = dalloc(F, &p, A->nb * bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
         F->padD = (double *)p;
-        if (dalloc(F, &p, (A->nb - 1) * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+        if ((e_ = dalloc(F, &p, (A->nb - 1) * bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
         F->padLo = (double *)p;
         D0 = F->padD;
         Lo0 = F->padLo;
         if (A->kind == PF_BTRI) {
-            if (dalloc(F, &p, (A->nb - 1) * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+            if ((e_ = dalloc(F, &p, (A->nb - 1) * bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
             F->padUp = (double *)p;
             Up0 = F->padUp;
         } else {
-            if (dalloc(F, &p, bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+            if ((e_ = dalloc(F, &p, bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
             F->padC = (double *)p;
             C0 = F->padC;
         }
@@ -752,28 +808,28 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
             else L.Up = P.nC;
         }
         const size_t fb = (size_t)L.nb * blk_bytes(M, L.f32);
-        if (dalloc(F, &L.E, fb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-        if (dalloc(F, &L.Z, fb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+        if ((e_ = dalloc(F, &L.E, fb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
+        if ((e_ = dalloc(F, &L.Z, fb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
         if (L.kind == PF_BTRI) {
-            if (dalloc(F, &L.R, fb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
-            if (dalloc(F, &L.X, fb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+            if ((e_ = dalloc(F, &L.R, fb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
+            if ((e_ = dalloc(F, &L.X, fb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
             if (L.p > 1) {
                 const size_t rb = (size_t)(L.p - 1) * bd;
-                if (dalloc(F, &p, rb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+                if ((e_ = dalloc(F, &p, rb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
                 L.nD = (double *)p;
-                if (dalloc(F, &p, rb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+                if ((e_ = dalloc(F, &p, rb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
                 L.nDadd = (double *)p;
-                if (dalloc(F, &p, rb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+                if ((e_ = dalloc(F, &p, rb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
                 L.nLo = (double *)p;
-                if (dalloc(F, &p, rb, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+                if ((e_ = dalloc(F, &p, rb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
                 L.nUp = (double *)p;
             }
         } else {
-            if (dalloc(F, &p, (size_t)(L.p + 1) * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+            if ((e_ = dalloc(F, &p, (size_t)(L.p + 1) * bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
             L.nD = (double *)p;
-            if (dalloc(F, &p, (size_t)L.p * bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+            if ((e_ = dalloc(F, &p, (size_t)L.p * bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
             L.nLo = (double *)p;
-            if (dalloc(F, &p, bd, F->allocs) != hipSuccess) return fail(PF_ENOMEM);
+            if ((e_ = dalloc(F, &p, bd, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
             L.nC = (double *)p;
         }
     }
@@ -800,10 +856,11 @@ int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, in
     Arena *ar = new Arena();
     ar->cap = count.off + 256;
     ar->refs = 1;
-    ar->stream_ordered = true;
-    if (hipMallocAsync((void **)&ar->base, ar->cap, s) != hipSuccess) {
+    ar->al = g_allocator;
+    const hipError_t e = dev_alloc(ar->al, (void **)&ar->base, ar->cap, s);
+    if (e != hipSuccess) {
         delete ar;
-        return PF_ENOMEM;
+        return alloc_status(e);
     }
     pf_factor_s *F = nullptr;
     if ((rc = factor_setup(A, o, s, ar, nullptr, &F)) || (rc = ensure_workspace(F, nrhs))) {
@@ -811,7 +868,7 @@ int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, in
             F->arena = nullptr;
             delete F;
         }
-        hipFreeAsync(ar->base, s);
+        dev_free(ar->al, ar->base, ar->cap, s);
         delete ar;
         return rc;
     }
@@ -1185,12 +1242,13 @@ int pf_ivp_create(int32_t m, int64_t p, int64_t N, const pf_opts *opts, void *st
     const int64_t steps = p * N, nb = steps + 1;
     const size_t mm = (size_t)m * m * sizeof(double);
     hipStream_t s = I->stream;
-    if (hipMallocAsync((void **)&I->D, nb * mm, s) != hipSuccess ||
-        hipMallocAsync((void **)&I->Lo, steps * mm, s) != hipSuccess ||
-        hipMallocAsync((void **)&I->C, mm, s) != hipSuccess ||
-        hipMallocAsync((void **)&I->f, (size_t)nb * m * sizeof(double), s) != hipSuccess) {
+    hipError_t e = hipMallocAsync((void **)&I->D, nb * mm, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&I->Lo, steps * mm, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&I->C, mm, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&I->f, (size_t)nb * m * sizeof(double), s);
+    if (e != hipSuccess) {
         pf_ivp_destroy(I);
-        return PF_ENOMEM;
+        return alloc_status(e);
     }
     // the coarse mesh is the partition: sub-interval i is partition i
     pf_opts o = resolve_opts(opts);
@@ -1310,8 +1368,10 @@ struct pf_batch_s {
     hipStream_t cap = nullptr;          // internal stream the graph is recorded on
     hipEvent_t ev = nullptr;
     Arena *arena = nullptr;
-    std::vector<pf_factor_s *> F;       // per system (null once handed out)
+    std::vector<pf_factor_s *> F;       // per system (null once handed out, or the caller's)
     std::vector<pf_factor_s *> all;     // per system, for the recorded work
+    std::vector<char> ext;              // 1: the caller's existing factor, solve only
+    std::vector<unsigned long long *> norms;   // per system: residual norm words
     std::vector<int32_t> nrhs;
     std::vector<const double *> f;
     std::vector<double *> x;
@@ -1347,7 +1407,7 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
         std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
         for (int i = 0; i < B->nsys; ++i) {
             const pf_factor_s *F = B->all[i];
-            if (l >= F->lv.size()) continue;
+            if (l >= F->lv.size() || B->ext[i]) continue;
             const Level &L = F->lv[l];
             groups[{L.kind, F->M, L.f32 ? 1 : 0, (L.kind == PF_BTRI && L.Dadd) ? 1 : 0,
                     L.seg}].push_back(i);
@@ -1424,8 +1484,9 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
 {
     hipError_t e = launch_fill_u64(B->d_words, B->nsys, ~0ull, s);
     if (e == hipSuccess) e = launch_fill_u64(B->d_words + B->nsys, B->nsys, 0ull, s);
-    for (auto *F : B->all)
-        if (e == hipSuccess && F->M != F->m) e = launch_pad_matrix(F, s);
+    for (int i = 0; i < B->nsys; ++i)
+        if (e == hipSuccess && !B->ext[i] && B->all[i]->M != B->all[i]->m)
+            e = launch_pad_matrix(B->all[i], s);
     for (const auto &bl : B->flaunch)
         if (e == hipSuccess)
             e = bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
@@ -1440,10 +1501,10 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
                                                B->d_lwork + bl.work, bl.nwg, s);
     if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
-        for (auto *F : B->all) {
-            const pf_matrix &A = F->A;
+        for (int i = 0; i < B->nsys; ++i) {
+            const pf_matrix &A = B->all[i]->A;
             if (e == hipSuccess)
-                e = launch_norminf(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, F->d_norm, s);
+                e = launch_norminf(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, B->d_words + B->nsys + i, s);
         }
     return e;
 }
@@ -1521,9 +1582,9 @@ int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::ve
             const pf_matrix &A = F->A;
             const int64_t n = A.nb * A.m;
             if (done[i] || B->nrhs[i] == 0) continue;
-            HIPCHK(launch_fill_u64(F->d_norms, 3 * B->nrhs[i], 0ull, s));
+            HIPCHK(launch_fill_u64(B->norms[i], 3 * B->nrhs[i], 0ull, s));
             HIPCHK(launch_residual(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, B->nrhs[i], B->f[i],
-                                   B->ldf[i], B->x[i], B->ldx[i], F->wsR, n, F->d_norms, s));
+                                   B->ldf[i], B->x[i], B->ldx[i], F->wsR, n, B->norms[i], s));
         }
         HIPCHK(hipMemcpyAsync(h.data(), B->d_words, h.size() * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s));
@@ -1566,15 +1627,13 @@ int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::ve
     return 0;
 }
 
-}  // namespace
-
-extern "C" {
-
-int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const int32_t *nrhs,
-                    const double *const *f, const int64_t *ldf, double *const *x,
-                    const int64_t *ldx, void *stream, pf_batch_t *out)
+// A batch; existing (may be NULL): per system the caller's factor of A[i]
+// (solved with, not factored) or NULL (factored by the batch).  Argument
+// errors are numbered as pf_solve_batch numbers them (existing = 10).
+int batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const int32_t *nrhs,
+                 const double *const *f, const int64_t *ldf, double *const *x,
+                 const int64_t *ldx, void *stream, pf_factor_s *const *existing, pf_batch_t *out)
 {
-    if (!out) return -10;
     *out = nullptr;
     if (nsys < 1) return -1;
     if (!A) return -2;
@@ -1586,12 +1645,17 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
         if ((rc = check_opts(&A[i], o))) return -3;
         const int64_t n = A[i].nb * A[i].m;
         if (nrhs[i] < 0 || (nrhs[i] > 0 && (!f[i] || !x[i])) || ldf[i] < n || ldx[i] < n) return -4;
+        const pf_factor_s *E = existing ? existing[i] : nullptr;
+        if (E && (E->A.kind != A[i].kind || E->m != A[i].m || E->nb != A[i].nb ||
+                  E->opts.prec != o.prec))
+            return -10;
     }
     hipStream_t us = (hipStream_t)stream;
     // per-system launch shapes (the autotuner's, when asked for)
     std::vector<pf_opts> os(nsys, o);
     if (o.flags & PF_FLAG_AUTOTUNE)
         for (int i = 0; i < nsys; ++i) {
+            if (existing && existing[i]) continue;
             pf_opts t{};
             const int rc = tuned_opts(&A[i], o, std::max(nrhs[i], 1), us, &t);
             if (rc) return rc;
@@ -1602,6 +1666,9 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
     B->opts = o;
     B->user = us;
     B->nrhs.assign(nrhs, nrhs + nsys);
+    B->ext.assign(nsys, 0);
+    if (existing)
+        for (int i = 0; i < nsys; ++i) B->ext[i] = existing[i] != nullptr;
     B->f.assign(f, f + nsys);
     B->x.assign(x, x + nsys);
     B->ldf.assign(ldf, ldf + nsys);
@@ -1621,6 +1688,7 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
     const size_t words = (2 * (size_t)nsys + 3 * total_rhs) * sizeof(unsigned long long);
     void *fake = (void *)(uintptr_t)4096;
     for (int i = 0; i < nsys; ++i) {
+        if (B->ext[i]) continue;
         pf_factor_s *F = nullptr;
         if (factor_setup(&A[i], os[i], us, &count, fake, &F)) return fail(PF_ENOMEM);
         ensure_workspace(F, std::max(nrhs[i], 1));
@@ -1629,7 +1697,11 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
     B->arena = new Arena();
     B->arena->refs = 1;
     B->arena->cap = count.off + words + kDumpBytes + kZeroBytes + 4096;
-    if (hipMalloc((void **)&B->arena->base, B->arena->cap) != hipSuccess) return fail(PF_ENOMEM);
+    B->arena->al = g_allocator;
+    {
+        const hipError_t e = dev_alloc(B->arena->al, (void **)&B->arena->base, B->arena->cap, us);
+        if (e != hipSuccess) return fail(alloc_status(e));
+    }
     Arena &ar = *B->arena;
     B->d_words = (unsigned long long *)ar.base;
     ar.off = words;
@@ -1637,23 +1709,36 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
     ar.off = ((ar.off + 255) & ~(size_t)255) + kDumpBytes + kZeroBytes;
     unsigned long long *norms = B->d_words + 2 * nsys;
     B->F.assign(nsys, nullptr);
+    B->all.assign(nsys, nullptr);
+    B->norms.assign(nsys, nullptr);
     for (int i = 0; i < nsys; ++i) {
+        B->norms[i] = norms;
+        norms += 3 * (size_t)std::max(nrhs[i], 1);
+        if (B->ext[i]) {
+            // the caller's handle: its own memory, its workspace grown if needed
+            pf_factor_s *F = existing[i];
+            const int rc = ensure_workspace(F, std::max(nrhs[i], 1));
+            if (rc) return fail(rc);
+            if (F->stream != us && hipStreamSynchronize(F->stream) != hipSuccess) return fail(PF_EHIP);
+            B->all[i] = F;
+            continue;
+        }
         pf_factor_s *F = nullptr;
-        if (factor_setup(&A[i], os[i], us, B->arena, scratch, &F)) return fail(PF_ENOMEM);
+        int rc = factor_setup(&A[i], os[i], us, B->arena, scratch, &F);
+        if (rc) return fail(rc);
         ++ar.refs;
         B->F[i] = F;
         // grouped launches run the segment kernels (same arithmetic)
         for (Level &L : F->lv)
             if (L.seg == kMapTri) L.seg = 1;
-        if (ensure_workspace(F, std::max(nrhs[i], 1))) return fail(PF_ENOMEM);
+        if ((rc = ensure_workspace(F, std::max(nrhs[i], 1)))) return fail(rc);
         // status, ||A|| and per-column norm words of all systems are
         // contiguous: one fill, one read-back per refinement sweep
         F->d_status = B->d_words + i;
         F->d_norm = B->d_words + nsys + i;
-        F->d_norms = norms;
-        norms += 3 * (size_t)std::max(nrhs[i], 1);
+        F->d_norms = B->norms[i];
+        B->all[i] = F;
     }
-    B->all = B->F;
     if (launch_fill_u64((unsigned long long *)((char *)scratch + kDumpBytes), kZeroBytes / 8, 0ull,
                         us) != hipSuccess)
         return fail(PF_EHIP);
@@ -1696,6 +1781,18 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const
         return fail(PF_EHIP);
     *out = B;
     return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const int32_t *nrhs,
+                    const double *const *f, const int64_t *ldf, double *const *x,
+                    const int64_t *ldx, void *stream, pf_batch_t *out)
+{
+    if (!out) return -10;
+    return batch_create(nsys, A, opts, nrhs, f, ldf, x, ldx, stream, nullptr, out);
 }
 
 int pf_batch_run(pf_batch_t B, void *stream, pf_info *info)
@@ -1764,12 +1861,13 @@ int pf_solve_batch(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const 
     if (nsys < 0) return -1;
     if (nsys == 0) return 0;
     pf_batch_t B = nullptr;
-    int rc = pf_batch_create(nsys, A, opts, nrhs, f, ldf, x, ldx, stream, &B);
+    int rc = batch_create(nsys, A, opts, nrhs, f, ldf, x, ldx, stream, factors, &B);
     if (rc) return rc;
     std::vector<pf_info> tmp(nsys);
     rc = pf_batch_run(B, stream, info ? info : tmp.data());
     if (factors)
-        for (int i = 0; i < nsys; ++i) pf_batch_factor(B, i, &factors[i]);
+        for (int i = 0; i < nsys; ++i)
+            if (!B->ext[i]) pf_batch_factor(B, i, &factors[i]);
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && !rc) rc = PF_EHIP;
     pf_batch_destroy(B);
     return rc;

@@ -29,6 +29,7 @@ EXPORTED = [
     "pf_autotune", "pf_autotune_clear",
     "pf_server_create", "pf_server_submit", "pf_server_poll", "pf_server_wait", "pf_server_times",
     "pf_server_release", "pf_server_stats", "pf_server_destroy",
+    "pf_set_allocator", "pf_last_hip_error",
 ]
 
 
@@ -55,6 +56,11 @@ class pf_info(ctypes.Structure):
 
 
 _lib = None
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                           ctypes.c_void_p)
+_allocator = None   # the callbacks the library holds (kept alive here)
 
 
 def load(path: str = LIB_PATH):
@@ -104,6 +110,8 @@ def load(path: str = LIB_PATH):
         "pf_autotune": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, vp, P(pf_opts),
                                        P(ctypes.c_float)]),
         "pf_autotune_clear": (None, []),
+        "pf_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, vp]),
+        "pf_last_hip_error": (ctypes.c_int, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -111,6 +119,54 @@ def load(path: str = LIB_PATH):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def pf_set_allocator(alloc=None, free=None):
+    """Route the library's factor memory through Python callables:
+    alloc(bytes, stream_ptr) -> device address (int, 0 when out of memory),
+    free(ptr, bytes, stream_ptr).  No arguments: back to the default
+    (stream-ordered hipMallocAsync)."""
+    global _allocator
+    lib = load()
+    if alloc is None and free is None:
+        rc = lib.pf_set_allocator(ALLOC_FN(), FREE_FN(), None)
+        _allocator = None
+    else:
+        a = ALLOC_FN(lambda n, st, ctx: alloc(int(n), st or 0) or None)
+        f = FREE_FN(lambda p, n, st, ctx: free(int(p), int(n), st or 0))
+        rc = lib.pf_set_allocator(a, f, None)
+        if rc == 0:
+            _allocator = (a, f)
+    if rc != 0:
+        raise PFError(rc, "pf_set_allocator")
+
+
+def use_torch_allocator(device=None):
+    """Back the library's factor memory with PyTorch's caching allocator (on
+    the stream each handle works on).  Returns the dict of live blocks
+    {ptr: bytes} for inspection."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+    live = {}
+
+    def alloc(n, st):
+        try:
+            p = torch.cuda.caching_allocator_alloc(n, dev, int(st))
+        except RuntimeError:
+            return 0
+        live[p] = n
+        return p
+
+    def free(p, n, st):
+        live.pop(p, None)
+        torch.cuda.caching_allocator_delete(p)
+
+    pf_set_allocator(alloc, free)
+    return live
+
+
+def pf_last_hip_error() -> int:
+    return int(load().pf_last_hip_error())
 
 
 class PFError(RuntimeError):
@@ -332,18 +388,30 @@ def pf_ivp_destroy(plan):
     load().pf_ivp_destroy(plan)
 
 
-def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False):
-    """mats: list of pf_matrix; fs/xs: lists of device tensors (nrhs_i, n_i)."""
+def pf_solve_batch(mats, opts, nrhs, fs, xs, stream=None, keep_factors=False, factors=None):
+    """mats: list of pf_matrix; fs/xs: lists of device tensors (nrhs_i, n_i).
+    factors: optional list of existing handles (or None) per system: those
+    systems are solved with their handle instead of being factored.  With
+    keep_factors (or factors) the returned list holds every system's handle
+    (the existing ones as given, the new ones for the caller to destroy)."""
     lib = load()
     ns = len(mats)
     A, nr, fp, lf, xp, lx = _batch_arrays(mats, nrhs, fs, xs)
-    fac = (ctypes.c_void_p * ns)() if keep_factors else None
+    fac = None
+    if keep_factors or factors is not None:
+        fac = (ctypes.c_void_p * ns)()
+        if factors is not None:
+            for i, h in enumerate(factors):
+                fac[i] = None if h is None else (h.value if isinstance(h, ctypes.c_void_p) else h)
     infos = (pf_info * ns)()
     rc = lib.pf_solve_batch(ns, A, ctypes.byref(opts) if opts is not None else None, nr, fp, lf,
                             xp, lx, _stream(stream), fac, infos)
     if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
         raise PFError(rc, "pf_solve_batch")
-    return list(infos), (list(fac) if keep_factors else None)
+    out = None
+    if fac is not None:
+        out = [None if v is None else ctypes.c_void_p(v) for v in fac]
+    return list(infos), out
 
 
 def _batch_arrays(mats, nrhs, fs, xs):

@@ -144,3 +144,52 @@ def test_factor_bytes_grow_with_size_and_precision():
     assert b64 > 4 * 65537 * 64 * 8 * 0.99
     assert b32 < b64
     assert pf.pf_factor_bytes(_mat(nb=1000)) < b64
+
+
+def test_allocator_callback_and_hip_errors():
+    """Factor memory goes through the caller's allocator: a NULL from it is
+    PF_ENOMEM (no device work is queued: the sizes come from a host-side
+    counting pass, at least pf_factor_bytes).  Setting only one of the two
+    functions is an argument error; NULL, NULL restores the default."""
+    lib = pf.load()
+    A = _mat(m=8, nb=1000)
+    h = ctypes.c_void_p()
+    asked = []
+    try:
+        pf.pf_set_allocator(lambda n, st: (asked.append(n), 0)[1], lambda p, n, st: None)
+        assert lib.pf_factor(ctypes.byref(A), None, None, ctypes.byref(h)) == pf.PF_ENOMEM
+        assert len(asked) == 1 and asked[0] >= pf.pf_factor_bytes(A)
+        assert pf.pf_last_hip_error() == 2          # hipErrorOutOfMemory
+    finally:
+        pf.pf_set_allocator()
+    only_alloc = pf.ALLOC_FN(lambda n, s, c: None)
+    only_free = pf.FREE_FN(lambda p, n, s, c: None)
+    assert lib.pf_set_allocator(only_alloc, pf.FREE_FN(), None) == -2
+    assert lib.pf_set_allocator(pf.ALLOC_FN(), only_free, None) == -1
+    assert lib.pf_set_allocator(pf.ALLOC_FN(), pf.FREE_FN(), None) == 0
+
+
+def test_hip_error_is_reported_not_enomem():
+    """A device allocation that fails for a reason other than memory (here:
+    no HIP device in the process) returns PF_EHIP, and pf_last_hip_error
+    gives the HIP code (hipErrorNoDevice = 100)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("needs a process without a HIP device")
+    lib = pf.load()
+    A = _mat(m=8, nb=1000)
+    h = ctypes.c_void_p()
+    assert lib.pf_factor(ctypes.byref(A), None, None, ctypes.byref(h)) == pf.PF_EHIP
+    assert pf.pf_last_hip_error() == 100
+
+
+def test_solve_batch_existing_factor_checked():
+    """pf_solve_batch takes existing factors in: argument checks run first
+    (a bad matrix is still -2 with a factors array present)."""
+    lib = pf.load()
+    bad = (pf.pf_matrix * 1)(_mat(nb=1))
+    nr = (ctypes.c_int32 * 1)(1)
+    vp = (ctypes.c_void_p * 1)(256)
+    ld = (ctypes.c_int64 * 1)(8)
+    fac = (ctypes.c_void_p * 1)()
+    assert lib.pf_solve_batch(1, bad, None, nr, vp, ld, vp, ld, None, fac, None) == -2
