@@ -65,7 +65,9 @@ enum {
     PF_ENOMEM = 3,      /* a device allocation ran out of memory             */
     PF_EHIP = 4,        /* a HIP runtime call failed (any other error of an
                            allocation included): pf_last_hip_error        */
-    PF_EUNSUPPORTED = 5 /* block size beyond what the library instantiates   */
+    PF_EUNSUPPORTED = 5,/* block size beyond what the library instantiates   */
+    PF_ETOOBIG = 6      /* pf_factor_solve_static: the system's factor memory
+                           exceeds the static workspace (256 MiB)           */
 };
 
 enum {
@@ -205,6 +207,27 @@ int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *
  * refactors.  Arguments, errors and synchronization as for pf_solve. */
 int pf_factor_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
                     int64_t ldx, void *stream, pf_info *info);
+
+/* Factor-and-solve that allocates no device memory, for callers that cannot
+ * call hipMalloc (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same plan and kernels as pf_factor
+ * followed by pf_factor_solve (results equal bit for bit), with every device
+ * byte of the factorization -- factors, reduced systems, status words and
+ * solve workspace -- carved from one static device array of 256 MiB that
+ * each GPU the library runs on holds until the process ends.  No handle is
+ * returned: the factors live in that array until the next call on the same
+ * GPU overwrites them.  Calls that overlap on one GPU (other streams, other
+ * host threads, before an earlier call's work has finished) share the array
+ * and race: order them on one stream or synchronize between them.  The
+ * stream must belong to the current device.  A, opts, f, ldf, x, ldx and
+ * info as for pf_factor and pf_factor_solve (nrhs = 0 only factors);
+ * PF_FLAG_AUTOTUNE is refused (argument 2: tuning allocates).  With info ==
+ * NULL and PF_FP64 the call is asynchronous and issues kernels only (it can
+ * be captured into a graph); otherwise it synchronizes `stream`.  Returns 0,
+ * -k for invalid argument k, PF_ETOOBIG when the system needs more than the
+ * array holds, PF_EHIP, or the numeric status. */
+int pf_factor_solve_static(const pf_matrix *A, const pf_opts *opts, int32_t nrhs, const double *f,
+                           int64_t ldf, double *x, int64_t ldx, void *stream, pf_info *info);
 
 /* Autotuner: time pf_factor_solve of A (nrhs right-hand sides, f = 1) on
  * `stream` for candidate launch shapes -- finest-level chain length

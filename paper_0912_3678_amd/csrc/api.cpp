@@ -686,6 +686,7 @@ const char *pf_strerror(int code)
     case PF_ENOMEM: return "device allocation failed";
     case PF_EHIP: return "HIP runtime error";
     case PF_EUNSUPPORTED: return "block size not supported";
+    case PF_ETOOBIG: return "system does not fit the library's static workspace";
     default: return "unknown error";
     }
 }
@@ -1107,6 +1108,73 @@ int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int
     }
     *out = F;
     return 0;
+}
+
+void note_hip_error(hipError_t e) { g_last_hip = (int)e; }
+
+// Factor-and-solve (pf_factor followed by pf_factor_solve, and the same
+// kernels) with every device byte of the handle -- factors, reduced systems,
+// status words, masked-store and zero areas, solve workspace -- carved from
+// [base, base + cap): nothing is allocated on the device.  The handle itself
+// is host bookkeeping, dropped before returning; the device work stays
+// queued on s.  PF_ETOOBIG when the memory the plan needs exceeds cap.
+int factor_solve_in(const pf_matrix *A, const pf_opts *opts, char *base, size_t cap, int nrhs,
+                    const double *f, int64_t ldf, double *x, int64_t ldx, hipStream_t s,
+                    pf_info *info)
+{
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    const pf_opts o = resolve_opts(opts);
+    if ((rc = check_opts(A, o))) return rc;
+    if (o.flags & PF_FLAG_AUTOTUNE) return -2;   // tuning allocates
+    if (nrhs < 0) return -3;
+    const int64_t n = A->nb * A->m;
+    if (nrhs > 0 && !f) return -4;
+    if (ldf < n) return -5;
+    if (nrhs > 0 && !x) return -6;
+    if (ldx < n) return -7;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->eta = -1.0;
+        info->bad_block = -1;
+    }
+    // the memory the plan needs: a counting pass through the same set-up
+    Arena count;
+    count.counting = true;
+    pf_factor_s *T = nullptr;
+    if ((rc = factor_setup(A, o, s, &count, nullptr, &T))) return rc;
+    rc = ensure_workspace(T, std::max(nrhs, 1));
+    delete T;
+    if (rc) return rc;
+    if (count.off + 256 > cap) return PF_ETOOBIG;
+    Arena ar;
+    ar.base = base;
+    ar.cap = cap;
+    ar.refs = 1;   // never released: the memory is not the library's to free
+    pf_factor_s *F = nullptr;
+    if ((rc = factor_setup(A, o, s, &ar, nullptr, &F))) return rc;
+    struct Drop {
+        pf_factor_s *F;
+        ~Drop()
+        {
+            F->arena = nullptr;   // carved blocks: nothing to give back
+            delete F;
+        }
+    } drop{F};
+    if ((rc = ensure_workspace(F, std::max(nrhs, 1)))) return rc;
+    HIPCHK(launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s));
+    if (nrhs == 0) {
+        HIPCHK(launch_factor_levels(F, s));
+        if (!info) return 0;
+        HIPCHK(hipStreamSynchronize(s));
+        read_status(F, info);
+        return info->status;
+    }
+    return solve_call(F, nrhs, f, ldf, x, ldx, (void *)s, info, [&](hipStream_t st) {
+        if (fused_ok(F, nrhs)) return run_factor_solve(F, nrhs, f, ldf, x, ldx, st);
+        if (launch_factor_levels(F, st) != hipSuccess) return (int)PF_EHIP;
+        return run_solve(F, nrhs, f, ldf, x, ldx, st);
+    });
 }
 
 // Device status word of a handle whose work has completed (no stream wait).

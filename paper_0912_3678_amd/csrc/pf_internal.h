@@ -177,6 +177,12 @@ LaunchTiming &launch_timing();
 int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int nrhs,
                      const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out);
 void destroy_async(pf_factor_s *F);
+// Factor-and-solve with all device memory carved from [base, base + cap)
+// (pf_factor_solve_static); and the HIP error kept for pf_last_hip_error.
+int factor_solve_in(const pf_matrix *A, const pf_opts *opts, char *base, size_t cap, int nrhs,
+                    const double *f, int64_t ldf, double *x, int64_t ldx, hipStream_t s,
+                    pf_info *info);
+void note_hip_error(hipError_t e);
 int status_nosync(pf_factor_s *F, pf_info *info);
 
 // Options of a PF_FLAG_AUTOTUNE factorization (tune.cpp): the cached choice

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpf.so")
 PF_BTRI, PF_BABD = 0, 1
 PF_FP64, PF_FP32_IR = 0, 1
 PF_OK, PF_ESINGULAR, PF_ENOCONV, PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED = 0, 1, 2, 3, 4, 5
+PF_ETOOBIG = 6
 PF_FLAG_ETA = 1
 PF_FLAG_MAP_ROWS, PF_FLAG_MAP_TILES, PF_FLAG_AUTOTUNE, PF_FLAG_MAP_SEGMENTS = 2, 4, 8, 16
 
@@ -29,7 +30,7 @@ EXPORTED = [
     "pf_autotune", "pf_autotune_clear",
     "pf_server_create", "pf_server_submit", "pf_server_poll", "pf_server_wait", "pf_server_times",
     "pf_server_release", "pf_server_stats", "pf_server_destroy",
-    "pf_set_allocator", "pf_last_hip_error",
+    "pf_set_allocator", "pf_last_hip_error", "pf_factor_solve_static",
 ]
 
 
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH):
         "pf_autotune_clear": (None, []),
         "pf_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, vp]),
         "pf_last_hip_error": (ctypes.c_int, []),
+        "pf_factor_solve_static": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, vp, i64, vp,
+                                                  i64, vp, P(pf_info)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -239,6 +242,24 @@ def pf_factor_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_in
     one call; arguments as pf_solve."""
     return _solve(load().pf_factor_solve, "pf_factor_solve", F, f, x, nrhs, ldf, ldx, stream,
                   want_info)
+
+
+def pf_factor_solve_static(A: pf_matrix, f, x, opts: pf_opts | None = None, nrhs=None,
+                           ldf=None, ldx=None, stream=None, want_info=True):
+    """Factor-and-solve with no device allocation (the library's static
+    workspace); returns pf_info (synchronizing) or None."""
+    if nrhs is None:
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+    n = f.shape[-1]
+    info = pf_info() if want_info else None
+    rc = load().pf_factor_solve_static(ctypes.byref(A),
+                                       ctypes.byref(opts) if opts is not None else None, nrhs,
+                                       _ptr(f), n if ldf is None else ldf, _ptr(x),
+                                       n if ldx is None else ldx, _stream(stream),
+                                       ctypes.byref(info) if info is not None else None)
+    if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED, PF_ETOOBIG):
+        raise PFError(rc, "pf_factor_solve_static")
+    return info
 
 
 def pf_refactor(F, stream=None):
