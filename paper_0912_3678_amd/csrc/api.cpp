@@ -195,10 +195,10 @@ constexpr int kMapTri = -5;
 int seg_width(int M, int level, int kind, bool f32, const pf_opts &o)
 {
     if (o.flags & PF_FLAG_MAP_ROWS) return 0;
-    if (M == 32 && kind == PF_BTRI && !f32) return kMapMfma32;
+    if (M == 32 && kind == PF_BTRI) return kMapMfma32;
     if (level == 0 && o.lane_entries > 0) return seg_ok(M, o.lane_entries) ? o.lane_entries : 0;
     if (M == 1 && kind == PF_BTRI && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS)) return kMapTri;
-    if (M == 16 && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS))
+    if (M == 16 && !(o.flags & PF_FLAG_MAP_SEGMENTS))
         return kind == PF_BABD ? kMapMfmaB16 : kMapMfma16;
     if (level == 0 && !(o.flags & PF_FLAG_MAP_SEGMENTS) && mfma_ok(kind, M, f32, false)) return kMapMfma;
     if (level == 0 && M == 8) return 2;   // 0.153 vs 0.156 ms per step with one entry
@@ -458,9 +458,9 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         const LevelArgs a = level_args(F, l);
         e = prof_launch(F, true, 0, (int)l, s, [&] {
             if (L.seg == kMapMfma) return launch_mfma_factor(a, nullptr, s);
-            if (L.seg == kMapMfma32) return launch_mfma32_factor(a, s);
-            if (L.seg == kMapMfma16) return launch_mfma16_factor(a, nullptr, s);
-            if (L.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, nullptr, s);
+            if (L.seg == kMapMfma32) return launch_mfma32_factor(a, L.f32, s);
+            if (L.seg == kMapMfma16) return launch_mfma16_factor(a, nullptr, L.f32, s);
+            if (L.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, nullptr, L.f32, s);
             if (L.seg == kMapTri) return launch_tri_factor(a, nullptr, s);
             if (L.seg) return launch_seg_factor(L.kind, F->M, L.seg, L.f32, a, nullptr, s);
             return (L.kind == PF_BTRI) ? launch_btri_factor(F->M, L.f32, a, s)
@@ -601,8 +601,8 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
         const LevelArgs a = level_args(F, l);
         HIPCHK(prof_launch(F, true, 3, (int)l, s, [&] {
             if (lv.seg == kMapMfma) return launch_mfma_factor(a, &args[l], s);
-            if (lv.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, &args[l], s);
-            if (lv.seg == kMapMfma16) return launch_mfma16_factor(a, &args[l], s);
+            if (lv.seg == kMapMfmaB16) return launch_mfma_babd16_factor(a, &args[l], lv.f32, s);
+            if (lv.seg == kMapMfma16) return launch_mfma16_factor(a, &args[l], lv.f32, s);
             if (lv.seg == kMapTri) return launch_tri_factor(a, &args[l], s);
             return launch_seg_factor(lv.kind, M, lv.seg, lv.f32, a, &args[l], s);
         }));
@@ -1559,11 +1559,11 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
         if (e == hipSuccess)
             e = bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfma32
-                    ? launch_mfma32_factor_batch(bl.add, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+                    ? launch_mfma32_factor_batch(bl.add, bl.f32, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfmaB16
-                    ? launch_mfma_babd16_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+                    ? launch_mfma_babd16_factor_batch(bl.f32, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfma16
-                    ? launch_mfma16_factor_batch(bl.add, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+                    ? launch_mfma16_factor_batch(bl.add, bl.f32, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
                                                    B->d_lwork + bl.work, bl.nwg, s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,

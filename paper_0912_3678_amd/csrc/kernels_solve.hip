@@ -42,7 +42,7 @@ int rhs_chunk(int nrhs) { return nrhs == 1 ? 1 : 4; }
 template <int KIND, bool FWD>
 static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t s)
 {
-    if (solve_tiled(M, f32)) return launch_solvet(M, KIND, FWD, KIND == 0 && a.Fadd, a, s);
+    if (solve_tiled(M, f32)) return launch_solvet(M, KIND, FWD, KIND == 0 && a.Fadd, f32, a, s);
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
         return dispatch_KC(rhs_chunk(a.nrhs), [&](auto kcc) {
@@ -114,7 +114,7 @@ hipError_t launch_solve_batch(int kind, bool fwd, int M, bool f32, bool add, int
                               const SolveArgs *tab, const int4 *work, int nwg, hipStream_t s)
 {
     if (nwg <= 0) return hipSuccess;
-    if (solve_tiled(M, f32)) return launch_solvet_batch(M, kind, fwd, add, KC, tab, work, nwg, s);
+    if (solve_tiled(M, f32)) return launch_solvet_batch(M, kind, fwd, add, f32, KC, tab, work, nwg, s);
     return kind == 0 ? launch_solve_batch_k<0>(fwd, M, f32, add, KC, tab, work, nwg, s)
                      : launch_solve_batch_k<1>(fwd, M, f32, add, KC, tab, work, nwg, s);
 }

@@ -80,29 +80,47 @@ bool mfma_ok(int kind, int M, bool f32, bool add);
 int mfma_partitions_per_wg();
 hipError_t launch_mfma_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
 hipError_t launch_mfma_factor_batch(const LevelArgs *tab, const int4 *work, int nwg, hipStream_t s);
-// matrix-core factor kernel for FP64 block tridiagonal levels with M = 32 (any
-// level; one partition per workgroup)
+// matrix-core factor kernel for block tridiagonal levels with M = 32 (any
+// level; one partition per workgroup; f32: FP32 arithmetic and factors on the
+// FP32 matrix-core instruction, else FP64)
+hipError_t launch_mfma32_factor(const LevelArgs &a, bool f32, hipStream_t s);
+hipError_t launch_mfma32_factor_batch(bool add, bool f32, const LevelArgs *tab, const int4 *work,
+                                      int nwg, hipStream_t s);
+// the same for M = 16 (sv: also sweep 1..16 right-hand sides forward)
+hipError_t launch_mfma16_factor(const LevelArgs &a, const SolveArgs *sv, bool f32, hipStream_t s);
+hipError_t launch_mfma16_factor_batch(bool add, bool f32, const LevelArgs *tab, const int4 *work,
+                                      int nwg, hipStream_t s);
+// matrix-core factor kernel for bidiagonal-plus-corner levels with M = 16
+// (any level; one partition per workgroup; sv: also sweep 1..16 right-hand
+// sides forward)
+hipError_t launch_mfma_babd16_factor(const LevelArgs &a, const SolveArgs *sv, bool f32,
+                                     hipStream_t s);
+hipError_t launch_mfma_babd16_factor_batch(bool f32, const LevelArgs *tab, const int4 *work,
+                                           int nwg, hipStream_t s);
+// matrix-core forward sweep / back substitution for M = 16, 32 (FP64 or FP32
+// factors): one partition per workgroup, solve32_cols(nrhs) right-hand sides
+// each
+int solve32_cols(int nrhs);
+hipError_t launch_solvet(int M, int kind, bool fwd, bool add, bool f32, const SolveArgs &a,
+                         hipStream_t s);
+hipError_t launch_solvet_batch(int M, int kind, bool fwd, bool add, bool f32, int cols,
+                               const SolveArgs *tab, const int4 *work, int nwg, hipStream_t s);
+inline bool solve_tiled(int M, bool) { return M == 16 || M == 32; }
+// the FP32 instantiations behind those launchers (kernels_mfma_tiles32.hip)
+namespace fp32 {
 hipError_t launch_mfma32_factor(const LevelArgs &a, hipStream_t s);
 hipError_t launch_mfma32_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
                                       hipStream_t s);
-// the same for M = 16 (sv: also sweep 1..16 right-hand sides forward)
 hipError_t launch_mfma16_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
 hipError_t launch_mfma16_factor_batch(bool add, const LevelArgs *tab, const int4 *work, int nwg,
                                       hipStream_t s);
-// matrix-core factor kernel for FP64 bidiagonal-plus-corner levels with M = 16
-// (any level; one partition per workgroup; sv: also sweep 1..16 right-hand
-// sides forward)
 hipError_t launch_mfma_babd16_factor(const LevelArgs &a, const SolveArgs *sv, hipStream_t s);
 hipError_t launch_mfma_babd16_factor_batch(const LevelArgs *tab, const int4 *work, int nwg,
                                            hipStream_t s);
-// matrix-core forward sweep / back substitution for M = 16, 32 and FP64
-// factors: one partition per workgroup, solve32_cols(nrhs) right-hand sides
-// each
-int solve32_cols(int nrhs);
 hipError_t launch_solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s);
 hipError_t launch_solvet_batch(int M, int kind, bool fwd, bool add, int cols, const SolveArgs *tab,
                                const int4 *work, int nwg, hipStream_t s);
-inline bool solve_tiled(int M, bool f32) { return (M == 16 || M == 32) && !f32; }
+}  // namespace fp32
 int seg_partitions_per_wg(int M, int E);
 hipError_t launch_seg_factor(int kind, int M, int E, bool f32, const LevelArgs &a,
                              const SolveArgs *sv, hipStream_t s);
