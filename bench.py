@@ -1,33 +1,39 @@
 #!/usr/bin/env python3
 """Throughput of the partition-method factor-and-solve on one MI355X.
 
-Default workload (--workload bvp): the block tridiagonal system of the
-trapezoidal discretization of y' = M(t) y + q(t) on [0,1], N = 65536 steps,
-block size m = 8, separated boundary conditions (4 components at each end),
-FP64: n = 524296 unknowns.  One step = pf_factor_solve: a numeric
-factorization in the handle's memory with the forward sweep fused into it,
-the recursive reduced solve and the back substitution -- every phase of the
-method.  Prints one JSON line: unknowns solved per second (whole job, inputs
-resident in HBM), the roofline fraction of the dominant kernel (the
-finest-level factor kernel, timed with HIP events on its stream), and the
-CPU oracle's rate on the same system.
+Default workload (--workload batch): 512 independent block tridiagonal
+systems drawn by the batched workload's law -- block size m uniform on
+{4, 8, 16, 32}, N log-uniform in [2^8, 2^16], diagonal blocks 4I + N(0,1/m),
+off-diagonal blocks N(0,1/m), 1..64 right-hand sides each -- factored and
+solved as one batch (grouped launches replayed from a HIP graph), in FP64
+(the line's value) and with FP32 factors + FP64 refinement (beside it).
+One step = one pf_batch_run: every phase of the method for every system.
+Prints one JSON line: unknowns x right-hand sides solved per second (whole
+job, inputs resident in HBM, only if every result meets eta <= 1e-12), the
+roofline of the dominant grouped launch (timed by events its dispatch
+stamps on its stream) and of the whole step, the CPU oracle on a bounded
+sample of the same law (one core and all cores), and p50 / p99 latency of
+the serving law under load (Poisson arrivals at 0.8 x saturation).
 
 Other workloads (one JSON line each, same fields where they apply):
+  bvp      the block tridiagonal system of the trapezoidal discretization of
+           y' = M(t) y + q(t) on [0,1], N = 65536 steps, m = 8, separated
+           boundary conditions, FP64; one step = pf_factor_solve
+           (--partitions 256 for the literal top-level p; cold-cache timing
+           beside the warm one);
   babd     BABD from the trapezoid rule with non-separated boundary
            conditions, m = 16, N = 262144 steps, FP32 factors + FP64
            refinement to eta <= 1e-12 (--prec fp64 for plain FP64);
-  batch    512 independent block tridiagonal systems, m in {4,8,16,32},
-           N log-uniform in [2^8, 2^16], 1..64 right-hand sides, one batch
-           (grouped launches replayed from a HIP graph);
   serving  Poisson arrivals of factor-and-solve requests (m in {8,16,32},
-           N lognormal with median 2^14, 30 % repeat right-hand sides on
-           kept factors) through the request scheduler: p50 / p99 latency
-           and throughput at fractions of the saturation rate;
+           N lognormal with median 2^14 clamped to 2^20, 30 % repeat
+           right-hand sides on kept factors) through the request scheduler:
+           p50 / p99 latency and throughput at fractions of the saturation
+           rate;
   ivp      the trapezoid rule for an initial value problem, solved in
            parallel over sub-intervals (Sec. 3);
   tridiag  a scalar tridiagonal system (m = 1; sub/super diagonals
            U[-1,1], diagonal 4+U[0,1]) of --n-tri unknowns, FP64, timed
-           like the default workload.
+           like bvp.
 """
 from __future__ import annotations
 
@@ -47,18 +53,25 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["bvp", "babd", "batch", "serving", "ivp", "tridiag"],
-                    default="bvp")
+    ap.add_argument("--workload", choices=["batch", "bvp", "babd", "serving", "ivp", "tridiag"],
+                    default="batch")
     ap.add_argument("--prec", choices=["fp64", "fp32ir"], default=None,
-                    help="babd / batch: precision (babd default fp32ir, batch default fp64)")
+                    help="babd: precision (default fp32ir); batch: run only this precision "
+                         "(default: both, FP64 is the line's value)")
+    ap.add_argument("--ir-steps", type=int, default=3,
+                    help="batch: timed steps of the FP32 + refinement run")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="batch: skip the serving-latency leg")
+    ap.add_argument("--serve-count", type=int, default=160,
+                    help="batch: requests of the serving-latency leg")
     ap.add_argument("--count", type=int, default=0,
                     help="batch: systems (default 512); serving: requests (default 240)")
     ap.add_argument("--n-hi", type=int, default=0,
-                    help="batch / serving: largest block count (default 2^16 / 2^18)")
+                    help="batch / serving: largest block count (default 2^16 / 2^20)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: memory budget")
     ap.add_argument("--autotune", action="store_true", help="batch: PF_FLAG_AUTOTUNE")
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (batch 20, others 50)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (batch 2, others 5)")
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--m", type=int, default=8)
     ap.add_argument("--n-tri", type=int, default=1 << 24, help="tridiag: unknowns")
@@ -75,6 +88,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="fold two rocprofv3 --pmc csv outputs into profiles/traffic.json (host only)")
+    ap.add_argument("--traffic-note", default="", help="--record-traffic: the workload and commands")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM counters)")
     return ap.parse_args()
@@ -114,9 +130,13 @@ KERNEL_SOURCES = {
     "k_tri_factor": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
     "k_tri_bwd": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
     "k_tri_fwd": _COMMON + ("kernels_tri.h", "kernels_tri.hip"),
+    "kb_btri_mfma32": _COMMON + ("kernels_gj.h", "kernels_mfma_tiles.h", "kernels_mfma_tiles.hip"),
+    "kb_btri_mfma16": _COMMON + ("kernels_gj.h", "kernels_mfma_tiles.h", "kernels_mfma_tiles.hip"),
+    "kb_fwdt": _COMMON + ("kernels_gj.h", "kernels_mfma_tiles.h", "kernels_mfma_tiles.hip"),
+    "kb_bwdt": _COMMON + ("kernels_gj.h", "kernels_mfma_tiles.h", "kernels_mfma_tiles.hip"),
 }
 _ALL_SOURCES = _COMMON + ("kernels_gj.h", "kernels_seg.h", "kernels_seg.hip", "kernels_mfma.hip",
-                          "kernels_mfma_tiles.hip", "kernels_rows.hip", "kernels_solve.h",
+                          "kernels_mfma_tiles.h", "kernels_mfma_tiles.hip", "kernels_mfma_tiles32.hip", "kernels_rows.hip", "kernels_solve.h",
                           "kernels_solve.hip", "kernels_tri.h", "kernels_tri.hip")
 
 
@@ -145,8 +165,64 @@ def load_traffic(kernel_name):
     return ent
 
 
+def record_traffic(fetch_dir, write_dir, note):
+    """Fold two rocprofv3 counter runs (--pmc FETCH_SIZE, --pmc WRITE_SIZE,
+    csv output, each of a bench.py run with --copy-probe) into
+    profiles/traffic.json: per library kernel, the HBM bytes of its largest
+    dispatch (the finest level), each counter scaled by what it reads for
+    the 256 MiB copy of the probe, keyed with the hash of the kernel's
+    sources.  Runs on the host; no device is touched."""
+    import csv
+    import re
+
+    def load(d, counter):
+        path = os.path.join(d, "run_counter_collection.csv")
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        copies = [float(r["Counter_Value"]) for r in rows
+                  if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 131072]
+        if not copies:
+            raise SystemExit(f"{path}: no 256 MiB copy-probe dispatch")
+        scale = 262144.0 / sorted(copies)[len(copies) // 2]   # KiB the copy moved / KiB read
+        best = {}
+        for r in rows:
+            m = re.search(r"pf::\(anonymous namespace\)::([^(]+)\(", r["Kernel_Name"])
+            if not m:
+                continue
+            name, grid = m.group(1), int(r["Grid_Size"])
+            if name not in best or grid > best[name][0]:
+                best[name] = (grid, float(r["Counter_Value"]) * 1024 * scale)
+        return best, scale
+
+    fetch, sf = load(fetch_dir, "FETCH_SIZE")
+    write, sw = load(write_dir, "WRITE_SIZE")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        rec = {"kernels": {}}
+    rec.setdefault("runs", []).append({"note": note, "fetch_scale": round(sf, 4),
+                                       "write_scale": round(sw, 4)})
+    for name, (grid, fb) in fetch.items():
+        if name not in write:
+            continue
+        wb = write[name][1]
+        rec["kernels"][name] = {"grid": grid, "fetch_bytes": int(fb), "write_bytes": int(wb),
+                                "total_bytes": int(fb + wb), "source_hash": source_hash(name),
+                                "run": note}
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"recorded {len(fetch)} kernels into {path} (FETCH x {sf:.3f}, WRITE x {sw:.3f})")
+
+
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(args.record_traffic[0], args.record_traffic[1], args.traffic_note)
+        return
+    if args.steps is None:
+        args.steps = 20 if args.workload == "batch" else 50
+    if args.warmup is None:
+        args.warmup = 2 if args.workload == "batch" else 5
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the method's multi-GPU "
               "sharding is described in DESIGN.md but not built.", file=sys.stderr)
@@ -154,6 +230,15 @@ def main():
     run = {"bvp": run_bvp, "babd": run_babd, "batch": run_batch, "serving": run_serving,
            "ivp": run_ivp, "tridiag": run_bvp}
     out = run[args.workload](args)
+    if args.copy_probe:
+        # a plain 256 MiB device copy: what the HBM counters read for known bytes
+        import torch
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 8
     print(json.dumps(out), flush=True)
 
 
@@ -208,6 +293,20 @@ def run_bvp(args):
     split_ms, _ = timed(step_split)
     step = step_split if args.split else step_fused
     ms_per_step, per = timed(step)
+
+    # cold steps: the 256 MB last-level cache (MALL) is flushed before each
+    # by writing a 1 GiB buffer; each step timed alone with events
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cold = []
+    for _ in range(max(3, min(args.steps, 20))):
+        flush.fill_(1.0)
+        a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_ev.record()
+        step()
+        b_ev.record()
+        torch.cuda.synchronize()
+        cold.append(a_ev.elapsed_time(b_ev))
+    del flush
 
     # acceptance of the result: FP64 residual with torch block products
     # (independent of the library's kernels)
@@ -291,6 +390,8 @@ def run_bvp(args):
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                        "mean_events": float(per.mean())},
         "split_ms_per_step": split_ms,
+        "cold_ms_per_step": float(np.median(cold)),
+        "warm_ms_per_step_events": float(np.median(per)),
         "step_alg_GBps": round(total_alg / (per.mean() * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": dom_name, "level": dom["level"],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -305,13 +406,6 @@ def run_bvp(args):
 
     pf.pf_destroy(F)
 
-    if args.copy_probe:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = src.numel() * 8
 
     if not args.no_cpu_baseline:
         import oracle
@@ -573,19 +667,84 @@ def _device_btri(m, nb, k, seed, dev):
     return D, Lo, Up, f
 
 
-def run_batch(args):
-    """Batched workload: one pf_batch of independent systems replayed from a
-    HIP graph; throughput counts m*nb unknowns per system per right-hand side."""
-    import numpy as np
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32
+RIDGE_FP64 = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)   # flop per byte
+
+
+def cpu_model():
+    """The host CPU's model name and the cores this process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return name, cores
+
+
+def batch_kernel_name(L):
+    """The kernel a grouped batch launch runs (pf_launch_info as a dict)."""
+    M, f32, lvl = L["m"], L["f32"], L["level"]
+    V = "float" if f32 else "double"
+    add = "true" if (lvl > 0 and L["kind"] == 0) else "false"
+    if L["phase"] == 0:
+        mp = L["mapping"]
+        if mp == -1:
+            return "kb_btri_mfma"
+        if mp == -2:
+            return f"kb_btri_mfma32<{add}, {V}>"
+        if mp == -3:
+            return f"kb_babd_mfma16<{V}>"
+        if mp == -4:
+            return f"kb_btri_mfma16<{add}, {V}>"
+        if mp > 0:
+            return f"kb_{'btri' if L['kind'] == 0 else 'babd'}_seg<{M}, {mp}, {V}, {add}>"
+        return f"kb_{'btri' if L['kind'] == 0 else 'babd'}_factor<{M}, {V}, {add}>"
+    tiled = M in (16, 32)
+    fwd = L["phase"] == 1
+    if tiled:
+        return (f"kb_fwdt<{M}, {L['kind']}, *, {add}, {V}>" if fwd
+                else f"kb_bwdt<{M}, {L['kind']}, *, {V}>")
+    return f"kb_fwd<{L['kind']}, {M}, *, {V}, {add}>" if fwd else f"kb_bwd<{L['kind']}, {M}, *, {V}>"
+
+
+def batch_launch_roofline(L, m_true):
+    """Algorithmic work of a grouped launch by the per-unit figures of the
+    method (8-byte words), and the roofline that bounds it.
+    Factor: the partition elimination reads the input blocks D, Lo, Up once
+    (3 m^2 words per block row) and does 12.7 m^3 flops per block row (the
+    partition method's count for block tridiagonal matrices).  Forward
+    sweep: reads the right-hand sides (m words per block row and column),
+    6 m^2 flops per block row and column (t, the next f', the separator
+    row).  Back substitution: writes the solution (m words per block row and
+    column), 4 m^2 flops per block row and column.  Factor stores and their
+    re-reads are not algorithmic here: the batch step factors and solves in
+    one call.  Returns (bytes, flops, bound)."""
+    m = m_true
+    if L["phase"] == 0:
+        byt = 3 * m * m * 8 * L["rows"]
+        fl = 12.7 * m ** 3 * L["rows"]
+    elif L["phase"] == 1:
+        byt = m * 8 * L["rhs_rows"]
+        fl = 6 * m * m * L["rhs_rows"]
+    else:
+        byt = m * 8 * L["rhs_rows"]
+        fl = 4 * m * m * L["rhs_rows"]
+    bound = "mfma" if fl / max(byt, 1) > RIDGE_FP64 else "hbm"
+    return byt, fl, bound
+
+
+def _batch_device_systems(specs, dev):
     import torch
-
     from paper_0912_3678_amd import pf
-    from paper_0912_3678_amd import workloads as wl
-
-    prec = args.prec or "fp64"
-    dev = torch.device("cuda", 0)
-    count = args.count or 512
-    specs = wl.batch_specs(count=count, n_hi=args.n_hi or 2 ** 16)
     mats, keep, fs, xs = [], [], [], []
     unknowns = 0
     for (m, nb, k, seed) in specs:
@@ -596,53 +755,233 @@ def run_batch(args):
         xs.append(torch.empty_like(f))
         unknowns += m * nb * k
     torch.cuda.synchronize()
-    flags = pf.PF_FLAG_AUTOTUNE if args.autotune else 0
-    opts = pf.make_opts(prec=pf.PF_FP32_IR if prec == "fp32ir" else pf.PF_FP64, flags=flags)
-    t_c = time.perf_counter()
-    B = pf.Batch(mats, opts, [k for _, _, k, _ in specs], fs, xs)
-    create_s = time.perf_counter() - t_c
-    want = prec == "fp32ir"
-    for _ in range(args.warmup):
-        B.run(want_info=want)
+    return mats, keep, fs, xs, unknowns
+
+
+def _time_batch(args, B, sync_each, steps, warmup):
+    """Warm-up, then `steps` replays between synchronizations; returns
+    (ms per step, per-step ms list, infos of the last run)."""
+    import torch
+    import numpy as np
+    infos = None
+    for _ in range(warmup):
+        infos = B.run(want_info=sync_each)
     torch.cuda.synchronize()
     per = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         t1 = time.perf_counter()
-        infos = B.run(want_info=want)
-        torch.cuda.synchronize()
-        per.append((time.perf_counter() - t1) * 1e3)
-    wall = (time.perf_counter() - t0) * 1e3 / args.steps
-    etas = [_eta_btri_torch(*keep[i], fs[i], xs[i], specs[i][0], specs[i][1])
-            for i in range(len(specs))]
-    infos = infos or B.run(want_info=True)
-    bad = sum(1 for i in infos if i.status != 0)
-    B.destroy()
-    ok = max(etas) <= 1e-12 and bad == 0
-    # algorithmic bytes of one pass: A once, f and x, factors written once
-    alg = sum(m * m * 8 * (3 * nb) + 2 * 8 * m * nb * k + (4 if prec == "fp64" else 2) * m * m * 8 * nb
-              for (m, nb, k, _) in specs)
+        infos = B.run(want_info=sync_each)
+        if sync_each:
+            per.append((time.perf_counter() - t1) * 1e3)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    if not per:
+        per = [wall]
+    return wall, np.array(per), infos
+
+
+def run_batch(args):
+    """Batched workload: 512 independent block tridiagonal systems (m in
+    {4, 8, 16, 32}, N log-uniform in [2^8, 2^16], 1..64 right-hand sides),
+    one pf_batch replayed from a HIP graph per step, in FP64 and with FP32
+    factors + FP64 refinement.  Throughput counts m*nb unknowns per system
+    per right-hand side, only if every result meets eta <= 1e-12."""
+    import numpy as np
+    import torch
+
+    from paper_0912_3678_amd import pf
+    from paper_0912_3678_amd import workloads as wl
+
+    dev = torch.device("cuda", 0)
+    count = args.count or 512
+    n_hi = args.n_hi or 2 ** 16
+    specs = wl.batch_specs(count=count, n_hi=n_hi)
+    mats, keep, fs, xs, unknowns = _batch_device_systems(specs, dev)
+    nrhs = [k for _, _, k, _ in specs]
+    flags = pf.PF_FLAG_AUTOTUNE if args.autotune else 0
+    precs = [args.prec] if args.prec else ["fp64", "fp32ir"]
+    res = {}
+    for prec in precs:
+        opts = pf.make_opts(prec=pf.PF_FP32_IR if prec == "fp32ir" else pf.PF_FP64, flags=flags)
+        t_c = time.perf_counter()
+        B = pf.Batch(mats, opts, nrhs, fs, xs)
+        create_s = time.perf_counter() - t_c
+        ir = prec == "fp32ir"
+        steps = args.steps if not ir else max(1, min(args.steps, args.ir_steps))
+        wall, per, infos = _time_batch(args, B, ir, steps, args.warmup if not ir else 1)
+        if infos is None:
+            infos = B.run(want_info=True)
+        etas = [_eta_btri_torch(*keep[i], fs[i], xs[i], specs[i][0], specs[i][1])
+                for i in range(len(specs))]
+        bad = sum(1 for i in infos if i.status != 0)
+        launches = B.profile()
+        B.destroy()
+        ok = max(etas) <= 1e-12 and bad == 0
+        r = {"ms_per_step": wall, "value": unknowns / (wall * 1e-3) if ok else 0.0,
+             "eta_max": max(etas), "bad_status": bad, "create_s": round(create_s, 2),
+             "steps": steps, "latency_ms": {"p50": float(np.percentile(per, 50)),
+                                             "p99": float(np.percentile(per, 99))},
+             "launches": launches}
+        if ir:
+            its = [i.refine_iters for i in infos]
+            r["refine_iters"] = {str(v): its.count(v) for v in sorted(set(its))}
+        res[prec] = r
+    main = res["fp64"] if "fp64" in res else res[precs[0]]
+    mprec = "fp64" if "fp64" in res else precs[0]
+    # dominant grouped launch of the main run, its roofline by the method's
+    # per-unit figures (m_true = the block size of the systems it covers)
+    dom = max(main["launches"], key=lambda L: L["ms"])
+    m_true = dom["m"]
+    byt, fl, bound = batch_launch_roofline(dom, m_true)
+    t = dom["ms"] * 1e-3
+    kname = batch_kernel_name(dom)
+    traffic = load_traffic(kname)
+    if bound == "mfma":
+        peak = FP32_PEAK_TFLOPS if dom["f32"] else FP64_PEAK_TFLOPS
+        roof = {"bound": "mfma", "achieved": round(fl / t / 1e12, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(fl / t / 1e12 / peak, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(byt / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(byt / t / 1e9 / HBM_PEAK_GBS, 4)}
+    roof.update({"kernel": kname, "level": dom["level"], "m": dom["m"],
+                 "alg_bytes_per_launch": int(byt), "alg_flops_per_launch": int(fl),
+                 "avg_launch_us": round(dom["ms"] * 1e3, 1),
+                 "traffic": traffic["total_bytes"] if traffic else None,
+                 "traffic_split": ({"fetch_bytes": traffic["fetch_bytes"],
+                                    "write_bytes": traffic["write_bytes"]} if traffic else None)})
+    # whole-step roofline: sum over systems of max(bytes / BW, flops / peak)
+    t_roof = 0.0
+    for (m, nb, k, _) in specs:
+        b_sys = 3 * m * m * 8 * nb + 2 * m * 8 * nb * k
+        f_sys = 12.7 * m ** 3 * nb + 10 * m * m * nb * k
+        t_roof += max(b_sys / (HBM_PEAK_GBS * 1e9), f_sys / (FP64_PEAK_TFLOPS * 1e12))
+    for r in res.values():
+        r["launches"] = sorted(
+            [{"kernel": batch_kernel_name(L), "phase": L["phase"], "level": L["level"],
+              "m": L["m"], "rows": L["rows"], "rhs_rows": L["rhs_rows"],
+              "us": round(L["ms"] * 1e3, 1)} for L in r["launches"]],
+            key=lambda d: -d["us"])[:12]
     out = {
-        "metric": "unknowns solved/sec (N*m per right-hand side) at residual<=1e-12",
-        "value": unknowns / (wall * 1e-3) if ok else 0.0,
-        "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 factors + f64 refinement" if prec == "fp32ir" else "f64",
+        "metric": "unknowns solved/sec (N*m per right-hand side) at residual<=1e-12; "
+                  "p50/p99 solve latency under load",
+        "value": main["value"],
+        "unit": "unknowns/s", "n_gpus": 1, "steps": main["steps"], "warmup": args.warmup,
+        "ms_per_step": main["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if mprec == "fp64" else "f32 factors + f64 refinement",
         "data": "synthetic",
-        "config": {"workload": "batched_btri", "systems": count, "unknowns_x_rhs": unknowns,
+        "config": {"workload": "batched_btri_512", "systems": count,
+                   "unknowns_x_rhs": unknowns, "n_range": [2 ** 8, n_hi],
                    "m_mix": {str(mm): sum(1 for s_ in specs if s_[0] == mm) for mm in (4, 8, 16, 32)},
-                   "autotune": bool(args.autotune), "step": "pf_batch_run (graph replay)"},
-        "eta_max": max(etas), "bad_status": bad, "create_s": round(create_s, 2),
-        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
-        "step_alg_GBps": round(alg / (wall * 1e-3) / 1e9, 1),
-        "roofline": {"bound": "hbm", "kernel": "whole batch step", "achieved": round(alg / (wall * 1e-3) / 1e9, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(alg / (wall * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+                   "matrix_GB": round(sum(3 * m * m * 8 * nb for m, nb, _, _ in specs) / 1e9, 2),
+                   "rhs_GB": round(sum(8 * m * nb * k for m, nb, k, _ in specs) / 1e9, 2),
+                   "autotune": bool(args.autotune),
+                   "step": "pf_batch_run: factor + solve of every system, grouped launches "
+                           "replayed from a HIP graph"},
+        "eta_max": main["eta_max"],
+        "latency_ms": main["latency_ms"],
+        "step_roofline": {"t_roof_ms": round(t_roof * 1e3, 2),
+                          "frac": round(t_roof * 1e3 / main["ms_per_step"], 4),
+                          "rule": "sum over systems of max(A + f + x bytes / 8 TB/s, "
+                                  "(12.7 m^3 + 10 m^2 k) flops per block row / 78.6 TFLOP/s)"},
+        "roofline": roof,
+        "precisions": {k: {kk: vv for kk, vv in v.items()} for k, v in res.items()},
+        "mall": "working set 63 GB >> 256 MB MALL: cold and warm steps coincide",
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(args, specs)
+    if not args.no_serving:
+        out["serving"] = serving_summary(args)
     return out
 
 
+def batch_cpu_baseline(args, specs):
+    """The oracle (band LU with partial pivoting, FP64) on a bounded sample
+    of the batched workload: systems in workload order whose estimated cost
+    is at most a few seconds each, until about --cpu-seconds of one core
+    are spent; then the same sample spread over all cores (one system per
+    thread).  Rates in unknowns x right-hand sides per second."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+    from paper_0912_3678_amd import workloads as wl
+
+    name, cores = cpu_model()
+    sample, est = [], 0.0
+    for (m, nb, k, seed) in specs:
+        cost = 16.0 * nb * m ** 3 + 12.0 * nb * m * m * k   # band LU flops + the k solves
+        if cost > 3e9:
+            continue
+        sample.append((m, nb, k, seed))
+        est += cost
+        if est > args.cpu_seconds * 1.2e9:
+            break
+
+    def system(sp):
+        m, nb, k, seed = sp
+        s = wl.random_btri(nb, m, seed=seed, manufactured=False)
+        f = np.random.default_rng(seed + 1).standard_normal((nb * m, k))
+        return s, f
+
+    data = [system(sp) for sp in sample]
+    t0 = time.perf_counter()
+    for s, f in data:
+        oracle.btri_solve(s.D, s.Lo, s.Up, f)
+    one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda sf: oracle.btri_solve(sf[0].D, sf[0].Lo, sf[0].Up, sf[1]), data))
+    allc = time.perf_counter() - t0
+    u = sum(m * nb * k for m, nb, k, _ in sample)
+    return {"value": u / one, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} systems of the batched workload's law in workload order "
+                      f"(those with m^3 nb below 3 GF of band LU work), {u} unknowns x "
+                      f"right-hand sides, band LU with partial pivoting, one pass",
+            "cpu": name, "all_cores": {"value": u / allc, "cores": cores,
+                                       "how": "one system per thread"}}
+
+
+def serving_summary(args):
+    """p50 / p99 latency under load for the batched line: the serving law
+    (block sizes 8, 16, 32; N lognormal, median 2^14, clamped to 2^20; 30 %
+    repeat right-hand sides on kept factors) through the request scheduler
+    under a 250 GB budget: saturation first, then Poisson arrivals at 0.8 x
+    that rate."""
+    out = _serving(args, count=args.serve_count, n_hi=2 ** 20, budget=250e9, pool_n=64,
+                   fracs=(0.8,))
+    load = out["load"][-1]
+    return {"workload": "serving_stream", "requests": args.serve_count, "n_max": 2 ** 20,
+            "budget_GB": 250, "pool_matrices": 64,
+            "saturation_req_s": round(out["saturation"]["throughput_req_s"], 1),
+            "saturation_unknowns_s": out["saturation"]["unknowns_per_s"],
+            "at_qps": round(load["qps"], 1), "p50_ms": load["p50_ms"], "p99_ms": load["p99_ms"],
+            "unknowns_per_s": load["unknowns_per_s"], "eta_max_sample":
+                max(out["saturation"]["eta_max_sample"], load["eta_max_sample"]),
+            "bad_status": out["saturation"]["bad_status"] + load["bad_status"]}
+
+
 def run_serving(args):
+    out = _serving(args, count=args.count or 240, n_hi=args.n_hi or 2 ** 20,
+                   budget=args.budget_gb * 1e9, pool_n=64, fracs=(0.5, 0.8))
+    sat, runs = out["saturation"], out["load"]
+    ok = all(r["bad_status"] == 0 and r["eta_max_sample"] <= 1e-12 for r in [sat] + runs)
+    return {
+        "metric": "p50/p99 solve latency under load; unknowns solved/sec at residual<=1e-12",
+        "value": runs[-1]["unknowns_per_s"] if ok else 0.0, "unit": "unknowns/s",
+        "n_gpus": 1, "steps": len(runs) and runs[-1]["requests"], "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_stream", "requests": args.count or 240,
+                   "pool": out["pool"], "n_max": args.n_hi or 2 ** 20,
+                   "budget_GB": args.budget_gb},
+        "saturation": sat, "load": runs,
+        "latency_ms": {"p50": runs[-1]["p50_ms"], "p99": runs[-1]["p99_ms"],
+                       "at_qps": runs[-1]["qps"]},
+    }
+
+
+def _serving(args, count, n_hi, budget, pool_n, fracs):
     """Request stream through the scheduler.  A pool of matrices drawn from
     the workload's law is generated on the device once; each new request
     factors one of them (the scheduler does not know they repeat), 30 % of
@@ -657,16 +996,14 @@ def run_serving(args):
     from paper_0912_3678_amd import workloads as wl
 
     dev = torch.device("cuda", 0)
-    count = args.count or 240
-    n_hi = args.n_hi or 2 ** 18
-    pool_specs = wl.serving_stream(32, 1.0, seed=wl.seed_for(5, 1), n_max=n_hi)
+    pool_specs = wl.serving_stream(pool_n, 1.0, seed=wl.seed_for(5, 1), n_max=n_hi)
     pool = []
     for i, r in enumerate(pool_specs):
         D, Lo, Up, _ = _device_btri(r["m"], r["nb"], 1, r["seed"], dev)
         pool.append((pf.make_matrix(pf.PF_BTRI, r["m"], r["nb"], D, Lo, Up), (D, Lo, Up),
                      r["m"], r["nb"]))
     torch.cuda.synchronize()
-    budget = int(args.budget_gb * 1e9)
+    budget = int(budget)
 
     def run_stream(qps):
         stream = wl.serving_stream(count, qps if qps else 1e9, n_max=n_hi)
@@ -728,20 +1065,8 @@ def run_serving(args):
 
     sat = run_stream(0)
     rate = sat["throughput_req_s"]
-    runs = [run_stream(frac * rate) for frac in (0.5, 0.8)]
-    ok = all(r["bad_status"] == 0 and r["eta_max_sample"] <= 1e-12 for r in [sat] + runs)
-    out = {
-        "metric": "p50/p99 solve latency under load; unknowns solved/sec at residual<=1e-12",
-        "value": runs[-1]["unknowns_per_s"] if ok else 0.0, "unit": "unknowns/s",
-        "n_gpus": 1, "steps": count, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "serving_stream", "requests": count, "pool": len(pool),
-                   "n_max": n_hi, "budget_GB": args.budget_gb},
-        "saturation": sat, "load": runs,
-        "latency_ms": {"p50": runs[-1]["p50_ms"], "p99": runs[-1]["p99_ms"],
-                       "at_qps": runs[-1]["qps"]},
-    }
-    return out
+    runs = [run_stream(frac * rate) for frac in fracs]
+    return {"saturation": sat, "load": runs, "pool": len(pool)}
 
 
 if __name__ == "__main__":

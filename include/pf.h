@@ -272,6 +272,27 @@ int pf_batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts,
  * status.  Runs of one batch must not overlap. */
 int pf_batch_run(pf_batch_t B, void *stream, pf_info *info);
 
+/* Per-launch timing of a batch: the batch's factor and solve launches are
+ * issued once more without the graph (the same work: the solutions are
+ * written as by pf_batch_run; PF_FP32_IR runs no refinement here), each
+ * grouped launch timed by HIP events that its dispatch stamps on the stream
+ * it runs on.  Fills up to max entries of out, sets *count to the number of
+ * grouped launches and returns 0 (or -k for invalid argument k, PF_EHIP);
+ * synchronizes.
+ * phase: 0 factor, 1 forward sweep, 2 back substitution; level: recursion
+ * level; m: the block size the kernel runs at (padded); mapping (factor
+ * launches): > 0 segment width, 0 rows, < 0 a matrix-core kernel; rows:
+ * block rows of all its systems; rhs_rows: block rows x right-hand sides
+ * (solve launches); ms: the launch's duration. */
+typedef struct {
+    int32_t phase, level, kind, m, f32, mapping;
+    int64_t rows, rhs_rows;
+    int32_t workgroups;
+    float ms;
+} pf_launch_info;
+int pf_batch_profile(pf_batch_t B, void *stream, int32_t max, pf_launch_info *out,
+                     int32_t *count);
+
 /* Hand out the factor of system i as a handle (pf_solve, pf_refactor,
  * pf_destroy work on it); each system can be handed out once.  The handle
  * shares the batch's allocation, which lives until the batch and every

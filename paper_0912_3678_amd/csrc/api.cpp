@@ -1416,7 +1416,38 @@ struct BatchLaunch {
     int seg;        // factor launches: segment width (0 = rows, kMapMfma = matrix cores)
     size_t work;    // first work item of this launch
     int nwg;
+    int level = 0;          // recursion level of its systems
+    int64_t rows = 0;       // block rows it covers (sum over its systems)
+    int64_t rhs_rows = 0;   // block rows x right-hand sides (solves)
 };
+
+// Per-launch timing of a batch (pf_batch_profile): events stamped by the
+// dispatches of the grouped launches.
+struct BatchTimes {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<const BatchLaunch *> which;
+};
+
+// Run one grouped launch, its dispatch timed when T != NULL.
+template <class Fn>
+hipError_t timed_launch(BatchTimes *T, const BatchLaunch &bl, Fn fn)
+{
+    if (!T) return fn();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return hipErrorOutOfMemory;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return hipErrorOutOfMemory;
+    }
+    T->ev.push_back({a, b});
+    T->which.push_back(&bl);
+    LaunchTiming &t = launch_timing();
+    t.start = a;
+    t.stop = b;
+    const hipError_t e = fn();
+    t.start = t.stop = nullptr;
+    return e;
+}
 
 // Device tables of one batched solve configuration (right-hand sides in,
 // solutions out): kernel arguments per (system, level) and one work item
@@ -1488,9 +1519,11 @@ void build_factor_tables(pf_batch_s *B, std::vector<LevelArgs> &tab, std::vector
                             : bl.seg == kMapMfma32 || bl.seg == kMapMfmaB16 || bl.seg == kMapMfma16 ? 1
                             : bl.seg             ? seg_partitions_per_wg(bl.M, bl.seg)
                                                  : groups_per_wg(bl.M);
+            bl.level = (int)l;
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(level_args(B->all[i], l));
+                bl.rows += B->all[i]->lv[l].nb;
                 const int64_t nblk = (B->all[i]->lv[l].p + gpw - 1) / gpw;
                 for (int64_t pb = 0; pb < nblk; ++pb) work.push_back(make_int4(entry, (int)pb, 0, 0));
             }
@@ -1531,9 +1564,12 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
                            std::get<4>(kv.first), std::get<2>(kv.first) != 0,
                            std::get<3>(kv.first) != 0, 0, work.size(), 0};
             const int gpw = solve_groups_per_wg(bl.M, bl.f32);
+            bl.level = (int)l;
             for (int i : kv.second) {
                 const int entry = (int)tab.size();
                 tab.push_back(args[i][l]);
+                bl.rows += B->all[i]->lv[l].nb;
+                bl.rhs_rows += B->all[i]->lv[l].nb * B->nrhs[i];
                 const int64_t nblk = (B->all[i]->lv[l].p + gpw - 1) / gpw;
                 const int ncb = (B->nrhs[i] + bl.KC - 1) / bl.KC;
                 for (int cb = 0; cb < ncb; ++cb)
@@ -1548,7 +1584,7 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
     for (size_t l = maxL; l-- > 0;) emit(2, l);
 }
 
-hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
+hipError_t issue_factor(pf_batch_s *B, hipStream_t s, BatchTimes *T = nullptr)
 {
     hipError_t e = launch_fill_u64(B->d_words, B->nsys, ~0ull, s);
     if (e == hipSuccess) e = launch_fill_u64(B->d_words + B->nsys, B->nsys, 0ull, s);
@@ -1557,7 +1593,8 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
             e = launch_pad_matrix(B->all[i], s);
     for (const auto &bl : B->flaunch)
         if (e == hipSuccess)
-            e = bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
+            e = timed_launch(T, bl, [&] { return
+              bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfma32
                     ? launch_mfma32_factor_batch(bl.add, bl.f32, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfmaB16
@@ -1567,7 +1604,7 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
                 : bl.seg ? launch_seg_factor_batch(bl.kind, bl.M, bl.seg, bl.f32, bl.add, B->d_lev,
                                                    B->d_lwork + bl.work, bl.nwg, s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
-                                               B->d_lwork + bl.work, bl.nwg, s);
+                                               B->d_lwork + bl.work, bl.nwg, s); });
     if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
         for (int i = 0; i < B->nsys; ++i) {
             const pf_matrix &A = B->all[i]->A;
@@ -1577,7 +1614,8 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s)
     return e;
 }
 
-hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t s)
+hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t s,
+                       BatchTimes *T = nullptr)
 {
     hipError_t e = hipSuccess;
     for (int i = 0; i < B->nsys && e == hipSuccess; ++i) {
@@ -1589,8 +1627,10 @@ hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t 
     }
     for (const auto &bl : S.launches)
         if (e == hipSuccess)
-            e = launch_solve_batch(bl.kind, bl.phase == 1, bl.M, bl.f32, bl.add, bl.KC, S.d_tab,
-                                   S.d_work + bl.work, bl.nwg, s);
+            e = timed_launch(T, bl, [&] {
+                return launch_solve_batch(bl.kind, bl.phase == 1, bl.M, bl.f32, bl.add, bl.KC,
+                                          S.d_tab, S.d_work + bl.work, bl.nwg, s);
+            });
     for (int i = 0; i < B->nsys && e == hipSuccess; ++i) {
         pf_factor_s *F = B->all[i];
         if (F->M == F->m || B->nrhs[i] == 0) continue;
@@ -1904,6 +1944,50 @@ int pf_batch_run(pf_batch_t B, void *stream, pf_info *info)
         }
     }
     return worst;
+}
+
+int pf_batch_profile(pf_batch_t B, void *stream, int32_t max, pf_launch_info *out,
+                     int32_t *count)
+{
+    if (!B) return -1;
+    if (max < 0 || (max > 0 && !out)) return -3;
+    if (!count) return -5;
+    *count = 0;
+    hipStream_t us = (hipStream_t)stream;
+    HIPCHK(hipEventRecord(B->ev, us));
+    HIPCHK(hipStreamWaitEvent(B->cap, B->ev, 0));
+    BatchTimes T;
+    hipError_t e = issue_factor(B, B->cap, &T);
+    if (e == hipSuccess) e = issue_solve(B, B->sol, false, B->cap, &T);
+    const hipError_t es = hipStreamSynchronize(B->cap);
+    int n = 0;
+    for (size_t i = 0; i < T.ev.size(); ++i, ++n) {
+        float ms = -1.f;
+        if (e == hipSuccess && es == hipSuccess &&
+            hipEventElapsedTime(&ms, T.ev[i].first, T.ev[i].second) != hipSuccess)
+            ms = -1.f;
+        hipEventDestroy(T.ev[i].first);
+        hipEventDestroy(T.ev[i].second);
+        if (n >= max) continue;
+        const BatchLaunch &bl = *T.which[i];
+        pf_launch_info &o = out[n];
+        o.phase = bl.phase;
+        o.level = bl.level;
+        o.kind = bl.kind;
+        o.m = bl.M;
+        o.f32 = bl.f32 ? 1 : 0;
+        o.mapping = bl.phase == 0 ? bl.seg : 0;
+        o.rows = bl.rows;
+        o.rhs_rows = bl.rhs_rows;
+        o.workgroups = bl.nwg;
+        o.ms = ms;
+    }
+    *count = n;
+    if (e != hipSuccess || es != hipSuccess) {
+        g_last_hip = (int)(e != hipSuccess ? e : es);
+        return PF_EHIP;
+    }
+    return 0;
 }
 
 int pf_batch_factor(pf_batch_t B, int32_t i, pf_factor_t *out)

@@ -4,6 +4,8 @@
 // the trapezoid discretization of a linear IVP (Sec. 3).
 #include "pf_internal.h"
 
+#include <type_traits>
+
 namespace pf {
 namespace {
 
@@ -37,60 +39,84 @@ __device__ __forceinline__ double block_max(double v, double *sh)
 }
 
 // Grid-stride loops over rows with a bounded grid, and one atomic per
-// workgroup and norm: the atomics to the few norm words stay few.
-// blockIdx.y = right-hand side.
-__global__ __launch_bounds__(256) void k_residual(int kind, int m, int64_t nb,
+// workgroup and norm: the atomics to the few norm words stay few.  A thread
+// owns one row and CH right-hand sides (blockIdx.y = the chunk of columns):
+// each entry of A is read once per CH columns, so many right-hand sides do
+// not multiply the reads of A.  Per column the sum runs in the same order
+// for every CH (f, then D, Lo, Up / C by column).
+template <int CH, int MT>
+__global__ __launch_bounds__(256) void k_residual(int kind, int m_rt, int64_t nb,
                                                   const double *__restrict__ D,
                                                   const double *__restrict__ Lo,
                                                   const double *__restrict__ Up,
-                                                  const double *__restrict__ C,
+                                                  const double *__restrict__ C, int nrhs,
                                                   const double *__restrict__ f, int64_t ldf,
                                                   const double *__restrict__ x, int64_t ldx,
                                                   double *__restrict__ r, int64_t ldr,
                                                   unsigned long long *norms)
 {
+    const int m = MT ? MT : m_rt;   // block size: compile-time where instantiated
     const int64_t n = (int64_t)m * nb;
     const int64_t mm = (int64_t)m * m;
-    const int c = blockIdx.y;
-    const double *xc = x + c * ldx;
-    double mr = 0.0, mx = 0.0, mf = 0.0;
+    const int c0 = blockIdx.y * CH;
+    const int nc = nrhs - c0 < CH ? nrhs - c0 : CH;
+    // columns of the chunk, clamped to existing ones (loads stay in bounds
+    // and branch-free; only the first nc are stored and reduced)
+    int64_t cx[CH], cf[CH], cr[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int64_t cc = c0 + (c < nc ? c : nc - 1);
+        cx[c] = cc * ldx;
+        cf[c] = cc * ldf;
+        cr[c] = cc * ldr;
+    }
+    double mr[CH], mx[CH], mf[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) mr[c] = mx[c] = mf[c] = 0.0;
     for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
          row += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = row / m;
         const int i = (int)(row - k * m);
-        const double fv = f[row + c * ldf];
-        double s = fv;
-        const double *dk = D + k * mm + i;
-        const double *xk = xc + k * m;
-        for (int j = 0; j < m; ++j) s = fma(-dk[(int64_t)j * m], xk[j], s);
-        if (k > 0) {
-            const double *lk = Lo + (k - 1) * mm + i;
-            const double *xp = xc + (k - 1) * m;
-            for (int j = 0; j < m; ++j) s = fma(-lk[(int64_t)j * m], xp[j], s);
+        double s[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            s[c] = f[row + cf[c]];
+            mf[c] = fmax(mf[c], fabs(s[c]));
         }
-        if (kind == 0 && k + 1 < nb) {
-            const double *uk = Up + k * mm + i;
-            const double *xn = xc + (k + 1) * m;
-            for (int j = 0; j < m; ++j) s = fma(-uk[(int64_t)j * m], xn[j], s);
+        // s -= blk(i, :) xb(:, c) for every column of the chunk
+        // (a partial unroll: loads of several columns in flight without
+        // spilling the CH accumulators)
+        constexpr int UF = CH >= 16 ? 4 : 8;
+        auto apply = [&](const double *blk, const double *xb) {
+#pragma unroll UF
+            for (int j = 0; j < (MT ? MT : m); ++j) {
+                const double a = blk[(int64_t)j * m];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) s[c] = fma(-a, xb[j + cx[c]], s[c]);
+            }
+        };
+        apply(D + k * mm + i, x + k * m);
+        if (k > 0) apply(Lo + (k - 1) * mm + i, x + (k - 1) * m);
+        if (kind == 0 && k + 1 < nb) apply(Up + k * mm + i, x + (k + 1) * m);
+        if (kind == 1 && k == 0) apply(C + i, x + (nb - 1) * m);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (r && c < nc) r[row + cr[c]] = s[c];
+            mr[c] = fmax(mr[c], fabs(s[c]));
+            mx[c] = fmax(mx[c], fabs(x[row + cx[c]]));
         }
-        if (kind == 1 && k == 0) {
-            const double *ck = C + i;
-            const double *xl = xc + (nb - 1) * m;
-            for (int j = 0; j < m; ++j) s = fma(-ck[(int64_t)j * m], xl[j], s);
-        }
-        if (r) r[row + c * ldr] = s;
-        mr = fmax(mr, fabs(s));
-        mx = fmax(mx, fabs(xc[row]));
-        mf = fmax(mf, fabs(fv));
     }
     __shared__ double sh[4];
-    mr = block_max(mr, sh);
-    mx = block_max(mx, sh);
-    mf = block_max(mf, sh);
-    if (threadIdx.x == 0) {
-        atomicMax(norms + 3 * c + 0, dbits(mr));
-        atomicMax(norms + 3 * c + 1, dbits(mx));
-        atomicMax(norms + 3 * c + 2, dbits(mf));
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const double a = block_max(mr[c], sh);
+        const double b = block_max(mx[c], sh);
+        const double d = block_max(mf[c], sh);
+        if (threadIdx.x == 0 && c < nc) {
+            atomicMax(norms + 3 * (c0 + c) + 0, dbits(a));
+            atomicMax(norms + 3 * (c0 + c) + 1, dbits(b));
+            atomicMax(norms + 3 * (c0 + c) + 2, dbits(d));
+        }
     }
 }
 
@@ -280,9 +306,28 @@ hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const d
                            unsigned long long *norms, hipStream_t s)
 {
     const int64_t n = (int64_t)m * nb;
-    hipLaunchKernelGGL(k_residual, dim3(grid_reduce(n, 256), nrhs), dim3(256), 0, s, kind, m, nb, D,
-                       Lo, Up, C, f, ldf, x, ldx, r, ldr, norms);
-    return hipGetLastError();
+    if (nrhs < 1) return hipSuccess;
+    // columns per thread: one, four, or eight (A read once per chunk); the
+    // block sizes of the workloads get a fully unrolled row loop
+    auto go = [&](auto ch, auto mt) {
+        constexpr int CH = decltype(ch)::value, MT = decltype(mt)::value;
+        hipLaunchKernelGGL((k_residual<CH, MT>), dim3(grid_reduce(n, 256), (nrhs + CH - 1) / CH),
+                           dim3(256), 0, s, kind, m, nb, D, Lo, Up, C, nrhs, f, ldf, x, ldx, r,
+                           ldr, norms);
+        return hipGetLastError();
+    };
+    auto by_m = [&](auto ch) {
+        switch (m) {
+        case 4: return go(ch, std::integral_constant<int, 4>{});
+        case 8: return go(ch, std::integral_constant<int, 8>{});
+        case 16: return go(ch, std::integral_constant<int, 16>{});
+        case 32: return go(ch, std::integral_constant<int, 32>{});
+        default: return go(ch, std::integral_constant<int, 0>{});
+        }
+    };
+    if (nrhs == 1) return by_m(std::integral_constant<int, 1>{});
+    if (nrhs <= 4) return by_m(std::integral_constant<int, 4>{});
+    return by_m(std::integral_constant<int, 8>{});
 }
 
 hipError_t launch_norminf(int kind, int m, int64_t nb, const double *D, const double *Lo,

@@ -30,7 +30,7 @@ EXPORTED = [
     "pf_autotune", "pf_autotune_clear",
     "pf_server_create", "pf_server_submit", "pf_server_poll", "pf_server_wait", "pf_server_times",
     "pf_server_release", "pf_server_stats", "pf_server_destroy",
-    "pf_set_allocator", "pf_last_hip_error", "pf_factor_solve_static",
+    "pf_set_allocator", "pf_last_hip_error", "pf_factor_solve_static", "pf_batch_profile",
 ]
 
 
@@ -45,6 +45,16 @@ class pf_opts(ctypes.Structure):
                 ("max_refine", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("coarse_rows", ctypes.c_int32),
                 ("lane_entries", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class pf_launch_info(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_int32), ("level", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("f32", ctypes.c_int32), ("mapping", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("rhs_rows", ctypes.c_int64),
+                ("workgroups", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class pf_info(ctypes.Structure):
@@ -107,6 +117,7 @@ def load(path: str = LIB_PATH):
                                            P(vp), P(i64), vp, P(vp)]),
         "pf_batch_run": (ctypes.c_int, [vp, vp, P(pf_info)]),
         "pf_batch_factor": (ctypes.c_int, [vp, i32, P(vp)]),
+        "pf_batch_profile": (ctypes.c_int, [vp, vp, i32, P(pf_launch_info), P(i32)]),
         "pf_batch_destroy": (None, [vp]),
         "pf_autotune": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, vp, P(pf_opts),
                                        P(ctypes.c_float)]),
@@ -471,6 +482,17 @@ class Batch:
         if rc < 0 or rc in (PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED):
             raise PFError(rc, "pf_batch_run")
         return list(infos) if want_info else None
+
+    def profile(self, stream=None):
+        """Per grouped launch: dicts of pf_launch_info (phase, level, kind, m,
+        f32, mapping, rows, rhs_rows, workgroups, ms)."""
+        n = 4096
+        buf = (pf_launch_info * n)()
+        cnt = ctypes.c_int32()
+        rc = load().pf_batch_profile(self.h, _stream(stream), n, buf, ctypes.byref(cnt))
+        if rc != 0:
+            raise PFError(rc, "pf_batch_profile")
+        return [buf[i].as_dict() for i in range(min(cnt.value, n))]
 
     def factor(self, i):
         out = ctypes.c_void_p()
