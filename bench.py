@@ -958,7 +958,8 @@ def serving_summary(args):
             "at_qps": round(load["qps"], 1), "p50_ms": load["p50_ms"], "p99_ms": load["p99_ms"],
             "unknowns_per_s": load["unknowns_per_s"], "eta_max_sample":
                 max(out["saturation"]["eta_max_sample"], load["eta_max_sample"]),
-            "bad_status": out["saturation"]["bad_status"] + load["bad_status"]}
+            "bad_status": out["saturation"]["bad_status"] + load["bad_status"],
+            "host_submit_max_ms": load["host_submit_max_ms"]}
 
 
 def run_serving(args):
@@ -1005,6 +1006,10 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
     torch.cuda.synchronize()
     budget = int(budget)
 
+    # one server for every stream of the run: its memory pool, grown by the
+    # first (saturation) stream, is reused by the later ones
+    S = pf.Server(budget, max_inflight=16, nstreams=4)
+
     def run_stream(qps):
         stream = wl.serving_stream(count, qps if qps else 1e9, n_max=n_hi)
         # a request's matrix: new requests cycle through the pool, repeats
@@ -1013,7 +1018,7 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
         g.manual_seed(wl.seed_for(5, 2))
         bufs = [None] * len(stream)
         torch.cuda.synchronize()
-        S = pf.Server(budget, max_inflight=16, nstreams=4)
+        st0 = S.stats()
         kept = []
         tickets = []
         host_submit = 0.0
@@ -1046,7 +1051,8 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
         wall = time.perf_counter() - t0
         times = [S.times(t) for t, _, _ in tickets]
         st = S.stats()
-        S.destroy()
+        for t, _ in kept:
+            S.release(t)
         lat = np.array([d - sub for sub, _, d in times])
         unknowns = sum(pool[pi][2] * pool[pi][3] for _, pi, _ in tickets)
         # acceptance on a sample of results
@@ -1058,7 +1064,10 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
                 "throughput_req_s": len(tickets) / wall, "unknowns_per_s": unknowns / wall,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "bad_status": sum(1 for i in infos if i.status != 0), "eta_max_sample": max(etas),
-                "evictions": st["evictions"], "repeats": sum(1 for _, _, fac in tickets if fac >= 0),
+                "evictions": st["evictions"] - st0["evictions"],
+                "repeats": sum(1 for _, _, fac in tickets if fac >= 0),
+                "host_setup_ms_max": round(st["setup_ms_max"], 2),
+                "host_launch_ms_max": round(st["launch_ms_max"], 2),
                 "host_submit_ms": round(host_submit * 1e3, 1),
                 "host_submit_max_ms": round(max(submit_ms), 2),
                 "host_submit_slowest": [int(i) for i in np.argsort(submit_ms)[-5:]]}
@@ -1066,6 +1075,7 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
     sat = run_stream(0)
     rate = sat["throughput_req_s"]
     runs = [run_stream(frac * rate) for frac in fracs]
+    S.destroy()
     return {"saturation": sat, "load": runs, "pool": len(pool)}
 
 

@@ -460,6 +460,10 @@ typedef struct {
 typedef struct {
     size_t budget, used;          /* bytes                                     */
     int64_t queued, inflight, resident, completed, evictions;
+    double setup_ms_max, setup_ms_total;    /* host time of new requests' handle
+                                               set-up and allocation           */
+    double launch_ms_max, launch_ms_total;  /* host time of requests' launches
+                                               (set-up included)              */
 } pf_server_info;
 
 /* budget_bytes: device memory the server may hold; max_inflight: running
@@ -478,6 +482,13 @@ int pf_server_wait(pf_server_t S, int64_t ticket, pf_info *info);
  * when the request is done. */
 int pf_server_times(pf_server_t S, int64_t ticket, double *submit_ms, double *start_ms,
                     double *done_ms);
+/* Map `bytes` (<= budget) of the server's memory pool ahead of the requests:
+ * factor memory comes from a pool of the server's own that keeps up to the
+ * budget mapped once used, so later allocations are pool lookups rather than
+ * fresh device mappings (which cost host time that lands in a request's
+ * latency).  Synchronizes one of the server's streams.  Returns 0, -k,
+ * PF_ENOMEM or PF_EHIP. */
+int pf_server_reserve(pf_server_t S, size_t bytes);
 /* Drop a kept factor (after the requests queued on it). */
 int pf_server_release(pf_server_t S, int64_t factor);
 int pf_server_stats(pf_server_t S, pf_server_info *st);

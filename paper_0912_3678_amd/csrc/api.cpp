@@ -7,6 +7,7 @@
 #include "kernels_tri.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,11 +42,6 @@ struct PlanLevel {
 // set (pf_set_allocator), else stream-ordered hipMallocAsync / hipFreeAsync.
 // Each handle and arena keeps the allocator it was created with, so that a
 // later pf_set_allocator does not pair a block with the wrong free.
-struct Allocator {
-    pf_alloc_fn alloc = nullptr;
-    pf_free_fn free = nullptr;
-    void *ctx = nullptr;
-};
 Allocator g_allocator;
 
 // the most recent failing HIP call of this thread (pf_last_hip_error)
@@ -844,7 +840,7 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
 // code.  One allocation instead of dozens keeps the host cost of a new
 // factorization low (a serving request pays it every time).
 int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, int nrhs,
-                         pf_factor_s **out)
+                         pf_factor_s **out, const Allocator *al = nullptr)
 {
     Arena count;
     count.counting = true;
@@ -857,7 +853,7 @@ int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, in
     Arena *ar = new Arena();
     ar->cap = count.off + 256;
     ar->refs = 1;
-    ar->al = g_allocator;
+    ar->al = al ? *al : g_allocator;
     const hipError_t e = dev_alloc(ar->al, (void **)&ar->base, ar->cap, s);
     if (e != hipSuccess) {
         delete ar;
@@ -1080,7 +1076,8 @@ void destroy_async(pf_factor_s *F)
 // A new handle for A, factored and its right-hand sides solved on stream s
 // in one pass per level where possible; nothing waits on the host.
 int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int nrhs,
-                     const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out)
+                     const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out,
+                     const Allocator *al, double *setup_ms)
 {
     *out = nullptr;
     int rc = check_matrix(A);
@@ -1088,7 +1085,12 @@ int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int
     const pf_opts o = resolve_opts(opts);
     if ((rc = check_opts(A, o))) return rc;
     pf_factor_s *F = nullptr;
-    if ((rc = factor_setup_private(A, o, s, std::max(nrhs, 1), &F))) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = factor_setup_private(A, o, s, std::max(nrhs, 1), &F, al);
+    if (setup_ms)
+        *setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                        .count();
+    if (rc) return rc;
     if ((rc = ensure_workspace(F, std::max(nrhs, 1)))) {
         destroy_async(F);
         return rc;

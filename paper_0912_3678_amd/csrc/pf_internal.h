@@ -192,8 +192,18 @@ LaunchTiming &launch_timing();
 // Handle helpers for the request scheduler (api.cpp): factor a new handle
 // and solve in one go on a stream, release without a host wait, and read the
 // status word of a handle whose work is complete.
+// Device memory of a handle: alloc / free callbacks (null: stream-ordered
+// hipMallocAsync / hipFreeAsync).
+struct Allocator {
+    pf_alloc_fn alloc = nullptr;
+    pf_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+// al: the allocator of the new handle (null: the one pf_set_allocator set);
+// setup_ms (may be null): host time of the handle's set-up and allocation
 int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int nrhs,
-                     const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out);
+                     const double *f, int64_t ldf, double *x, int64_t ldx, pf_factor_s **out,
+                     const Allocator *al = nullptr, double *setup_ms = nullptr);
 void destroy_async(pf_factor_s *F);
 // Factor-and-solve with all device memory carved from [base, base + cap)
 // (pf_factor_solve_static); and the HIP error kept for pf_last_hip_error.

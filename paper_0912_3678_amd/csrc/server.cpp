@@ -13,6 +13,11 @@
 // device.  All requests on one resident factor run on that factor's stream
 // (they share its workspace).  Nothing here waits on the host for device
 // work except pf_server_wait.
+//
+// Factor memory comes from a memory pool of the server's own whose release
+// threshold is the budget: what retired requests give back stays mapped for
+// the next ones, so a new request's allocation is a pool lookup instead of a
+// fresh mapping of device memory (pf_server_reserve maps it ahead).
 #include "pf.h"
 #include "pf_internal.h"
 
@@ -60,6 +65,10 @@ struct Resident {
 
 struct pf_server_s {
     size_t budget = 0, used = 0;
+    hipMemPool_t pool = nullptr;     // factor memory (release threshold = budget)
+    Allocator al;                    // hands the pool to new handles
+    double setup_ms_max = 0, setup_ms_total = 0;     // host: handle set-up + allocation
+    double launch_ms_max = 0, launch_ms_total = 0;   // host: a request's whole launch
     pf_opts opts{};
     int max_inflight = 8;
     std::vector<hipStream_t> streams;
@@ -75,6 +84,18 @@ struct pf_server_s {
 };
 
 namespace {
+
+void *pool_alloc(size_t bytes, void *stream, void *ctx)
+{
+    void *p = nullptr;
+    if (hipMallocFromPoolAsync(&p, bytes, (hipMemPool_t)ctx, (hipStream_t)stream) != hipSuccess)
+        return nullptr;
+    return p;
+}
+void pool_free(void *p, size_t, void *stream, void *)
+{
+    hipFreeAsync(p, (hipStream_t)stream);
+}
 
 size_t request_bytes(const pf_server_s *S, const pf_request &r)
 {
@@ -168,6 +189,7 @@ int launch(pf_server_s *S, int64_t id, Ticket &T)
         si = (int)(std::min_element(S->load.begin(), S->load.end()) - S->load.begin());
     }
     hipStream_t s = S->streams[si];
+    const double t0 = now_ms();
     if (T.ev_ready && hipStreamWaitEvent(s, T.ev_ready, 0) != hipSuccess) return PF_EHIP;
     hipEventRecord(T.ev_start, s);
     int rc;
@@ -175,9 +197,16 @@ int launch(pf_server_s *S, int64_t id, Ticket &T)
         T.F = S->resident[r.factor].F;
         rc = pf_solve(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s, nullptr);
     } else {
-        rc = factor_new_solve(&r.A, &S->opts, s, r.nrhs, r.f, r.ldf, r.x, r.ldx, &T.F);
+        double setup = 0;
+        rc = factor_new_solve(&r.A, &S->opts, s, r.nrhs, r.f, r.ldf, r.x, r.ldx, &T.F, &S->al,
+                              &setup);
+        S->setup_ms_max = std::max(S->setup_ms_max, setup);
+        S->setup_ms_total += setup;
     }
     if (rc) return rc;
+    const double dt = now_ms() - t0;
+    S->launch_ms_max = std::max(S->launch_ms_max, dt);
+    S->launch_ms_total += dt;
     hipEventRecord(T.ev_done, s);
     T.stream = si;
     T.state = 1;
@@ -282,6 +311,27 @@ int pf_server_create(size_t budget_bytes, const pf_opts *opts, int32_t max_infli
         return -2;
     }
     S->max_inflight = max_inflight ? max_inflight : 8;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) {
+            pf_server_destroy(S);
+            return PF_EHIP;
+        }
+        hipMemPoolProps pp{};
+        pp.allocType = hipMemAllocationTypePinned;
+        pp.handleTypes = hipMemHandleTypeNone;
+        pp.location.type = hipMemLocationTypeDevice;
+        pp.location.id = dev;
+        uint64_t keep = budget_bytes;
+        if (hipMemPoolCreate(&S->pool, &pp) != hipSuccess ||
+            hipMemPoolSetAttribute(S->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+            pf_server_destroy(S);
+            return PF_EHIP;
+        }
+        S->al.alloc = pool_alloc;
+        S->al.free = pool_free;
+        S->al.ctx = (void *)S->pool;
+    }
     const int ns = nstreams ? nstreams : 4;
     for (int i = 0; i < ns; ++i) {
         hipStream_t s = nullptr;
@@ -414,6 +464,23 @@ int pf_server_stats(pf_server_t S, pf_server_info *st)
     st->resident = (int64_t)S->resident.size();
     st->completed = S->completed;
     st->evictions = S->evictions;
+    st->setup_ms_max = S->setup_ms_max;
+    st->setup_ms_total = S->setup_ms_total;
+    st->launch_ms_max = S->launch_ms_max;
+    st->launch_ms_total = S->launch_ms_total;
+    return 0;
+}
+
+int pf_server_reserve(pf_server_t S, size_t bytes)
+{
+    if (!S) return -1;
+    if (bytes > S->budget) return -2;
+    if (bytes == 0) return 0;
+    hipStream_t s = S->streams[0];
+    void *p = nullptr;
+    const hipError_t e = hipMallocFromPoolAsync(&p, bytes, S->pool, s);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP;
+    if (hipFreeAsync(p, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return PF_EHIP;
     return 0;
 }
 
@@ -436,6 +503,7 @@ void pf_server_destroy(pf_server_t S)
         hipStreamDestroy(s);
     }
     if (S->epoch) hipEventDestroy(S->epoch);
+    if (S->pool) hipMemPoolDestroy(S->pool);
     delete S;
 }
 

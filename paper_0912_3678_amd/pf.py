@@ -31,6 +31,7 @@ EXPORTED = [
     "pf_server_create", "pf_server_submit", "pf_server_poll", "pf_server_wait", "pf_server_times",
     "pf_server_release", "pf_server_stats", "pf_server_destroy",
     "pf_set_allocator", "pf_last_hip_error", "pf_factor_solve_static", "pf_batch_profile",
+    "pf_server_reserve",
 ]
 
 
@@ -531,7 +532,9 @@ class pf_request(ctypes.Structure):
 class pf_server_info(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_size_t), ("used", ctypes.c_size_t), ("queued", ctypes.c_int64),
                 ("inflight", ctypes.c_int64), ("resident", ctypes.c_int64),
-                ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+                ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("setup_ms_max", ctypes.c_double), ("setup_ms_total", ctypes.c_double),
+                ("launch_ms_max", ctypes.c_double), ("launch_ms_total", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -547,6 +550,7 @@ def _server_sigs(lib):
         "pf_server_wait": (ctypes.c_int, [vp, i64, P(pf_info)]),
         "pf_server_times": (ctypes.c_int, [vp, i64, P(d), P(d), P(d)]),
         "pf_server_release": (ctypes.c_int, [vp, i64]),
+        "pf_server_reserve": (ctypes.c_int, [vp, ctypes.c_size_t]),
         "pf_server_stats": (ctypes.c_int, [vp, P(pf_server_info)]),
         "pf_server_destroy": (None, [vp]),
     }
@@ -603,6 +607,11 @@ class Server:
         s, a, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         load().pf_server_times(self.h, ticket, ctypes.byref(s), ctypes.byref(a), ctypes.byref(d))
         return s.value, a.value, d.value
+
+    def reserve(self, nbytes):
+        rc = load().pf_server_reserve(self.h, int(nbytes))
+        if rc != 0:
+            raise PFError(rc, "pf_server_reserve")
 
     def release(self, factor):
         rc = load().pf_server_release(self.h, factor)
