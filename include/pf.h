@@ -87,12 +87,34 @@ enum {
                               autotuner's cache for the system's shape class,
                               tuning on this matrix first when the class is new
                               (see pf_autotune)                                      */
-    PF_FLAG_MAP_SEGMENTS = 16 /* the finest level of an FP64 PF_BTRI matrix with
+    PF_FLAG_MAP_SEGMENTS = 16, /* the finest level of an FP64 PF_BTRI matrix with
                               m = 8 (after padding) runs its block products on the
                               matrix cores by default (v_mfma_f64_16x16x4f64,
                               two partitions per wave); this flag, or lane_entries
                               > 0, keeps it on the segment mapping.  The mappings
                               differ only in rounding.                               */
+    PF_FLAG_ENLARGE = 32   /* pf_factor, PF_BTRI: the enlarged reduced system of Sec. 2
+                              (the modified factorization after eq. (redmatr)).  Where a
+                              partition's elimination meets a pivot block that is
+                              singular (a zero pivot) or ill-conditioned (its
+                              smallest pivot below 2^-40 of its largest, 2^-20 for
+                              FP32 factors), the elimination stops before it and
+                              that block row joins the separators, so it enters the
+                              reduced system, where the neighbours' contributions
+                              are added to it; the level is planned again with the
+                              enlarged separator list (partitions may be empty) and
+                              factored again, up to 32 passes.  pf_factor then
+                              synchronizes `stream`; the handle keeps the separator
+                              lists (pf_factor_level reports the enlarged p), and
+                              pf_refactor / pf_factor_solve reuse them (a pivot block
+                              that fails there is reported as PF_ESINGULAR).
+                              pf_factor_bytes does not include the enlargement.
+                              The finest level of m = 8 then runs on the segment
+                              mapping.  PF_BABD: the reduced matrix of eq. (redmatr1)
+                              keeps each separator's own diagonal block, so moving a
+                              failing block there cannot cure it; pf_factor makes one
+                              pass, which also flags ill-conditioned pivot blocks
+                              (PF_ESINGULAR with the first one).                    */
 };
 
 typedef struct {

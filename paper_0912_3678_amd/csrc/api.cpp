@@ -19,6 +19,9 @@ using namespace pf;
 
 namespace {
 
+// PF_FLAG_ENLARGE: room for the codes of failing partitions per pass
+constexpr int kBadCap = 16384;
+
 struct Level {
     int kind = PF_BTRI;
     int64_t nb = 0, p = 1;
@@ -29,12 +32,18 @@ struct Level {
     const double *D = nullptr, *Dadd = nullptr, *Lo = nullptr, *Up = nullptr, *C = nullptr;
     void *E = nullptr, *R = nullptr, *Z = nullptr, *X = nullptr;
     double *nD = nullptr, *nDadd = nullptr, *nLo = nullptr, *nUp = nullptr, *nC = nullptr;
+    std::vector<int64_t> seps;   // explicit partition boundaries (empty: balanced)
+    int64_t *d_sep = nullptr;    // their device copy
 };
 
 struct PlanLevel {
     int kind;
     int64_t nb, p;
+    std::vector<int64_t> seps;   // explicit partition boundaries, p + 1 (empty: balanced)
 };
+
+// Explicit partition boundaries per level (enlarged reduced systems).
+using SepOverrides = std::map<int, std::vector<int64_t>>;
 
 // One device allocation carved into the memory of many handles (a batch).
 // Shared by the batch and by the handles it hands out; freed by the last.
@@ -125,6 +134,8 @@ struct pf_factor_s {
     double *padD = nullptr, *padLo = nullptr, *padUp = nullptr, *padC = nullptr;
     // set when the handle's memory is a slice of a batch's arena
     Arena *arena = nullptr;
+    // PF_FLAG_ENLARGE: failing partitions' codes (kBadCap) and their count
+    unsigned long long *d_badlist = nullptr;
 };
 
 namespace {
@@ -196,21 +207,35 @@ int seg_width(int M, int level, int kind, bool f32, const pf_opts &o)
     if (M == 1 && kind == PF_BTRI && !f32 && !(o.flags & PF_FLAG_MAP_SEGMENTS)) return kMapTri;
     if (M == 16 && !(o.flags & PF_FLAG_MAP_SEGMENTS))
         return kind == PF_BABD ? kMapMfmaB16 : kMapMfma16;
-    if (level == 0 && !(o.flags & PF_FLAG_MAP_SEGMENTS) && mfma_ok(kind, M, f32, false)) return kMapMfma;
+    if (level == 0 && !(o.flags & (PF_FLAG_MAP_SEGMENTS | PF_FLAG_ENLARGE)) && mfma_ok(kind, M, f32, false))
+        return kMapMfma;
     if (level == 0 && M == 8) return 2;   // 0.153 vs 0.156 ms per step with one entry
     for (int E = 1; E <= M; E <<= 1)
         if (seg_ok(M, E)) return E;
     return 0;
 }
 
-std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
+std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o,
+                                 const SepOverrides *ovr = nullptr)
 {
     std::vector<PlanLevel> out;
     const bool f32 = o.prec == PF_FP32_IR;
     int64_t cur = nb;
     int lvl = 0;
+    auto explicit_at = [&](int l) -> const std::vector<int64_t> * {
+        if (!ovr) return nullptr;
+        auto it = ovr->find(l);
+        return it == ovr->end() ? nullptr : &it->second;
+    };
     if (kind == PF_BABD) {
-        while (cur > 2) {
+        while (cur > 2 || explicit_at(lvl)) {
+            if (const auto *sp = explicit_at(lvl)) {
+                const int64_t p = (int64_t)sp->size() - 1;
+                out.push_back({PF_BABD, cur, p, *sp});
+                cur = p + 1;
+                ++lvl;
+                continue;
+            }
             int64_t p;
             if (lvl == 0 && o.partitions > 0) p = o.partitions;
             else {
@@ -219,14 +244,22 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
                 p = std::max<int64_t>(p, 1);
                 p = std::min<int64_t>(p, (cur - 1) / 2);
             }
-            out.push_back({PF_BABD, cur, p});
+            out.push_back({PF_BABD, cur, p, {}});
             cur = p + 1;
             ++lvl;
         }
-        out.push_back({PF_BTRI, cur, 1});
+        out.push_back({PF_BTRI, cur, 1, {}});
         return out;
     }
     while (true) {
+        if (const auto *sp = explicit_at(lvl)) {
+            const int64_t p = (int64_t)sp->size() - 1;
+            out.push_back({PF_BTRI, cur, p, *sp});
+            if (p == 1) break;
+            cur = p - 1;
+            ++lvl;
+            continue;
+        }
         int64_t p;
         if (lvl == 0 && o.partitions > 0) p = o.partitions;
         else if (cur <= kTail || (M == 1 && lvl > 0 && cur <= kTriMaxChain)) p = 1;
@@ -236,7 +269,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o)
             p = std::max<int64_t>(p, 2);
             p = std::min<int64_t>(p, (cur + 1) / 2);
         }
-        out.push_back({PF_BTRI, cur, p});
+        out.push_back({PF_BTRI, cur, p, {}});
         if (p == 1) break;
         cur = p - 1;
         ++lvl;
@@ -376,6 +409,13 @@ LevelArgs level_args(const pf_factor_s *F, size_t l)
     a.dump = F->d_dump;
     a.zero = F->d_zero;
     a.level = (int)l;
+    a.sep = L.d_sep;
+    if (F->d_badlist) {
+        a.tau = L.f32 ? 0x1p-20 : 0x1p-40;
+        a.badlist = F->d_badlist;
+        a.badcount = (unsigned *)(F->d_badlist + kBadCap);
+        a.badcap = kBadCap;
+    }
     return a;
 }
 
@@ -396,6 +436,7 @@ std::vector<SolveArgs> solve_args(const pf_factor_s *F, int nrhs, const double *
         a.dump = (double *)F->d_dump;
         a.zero = F->d_zero;
         a.p = lv.p;
+        a.sep = lv.d_sep;
         a.nrhs = nrhs;
         a.Lo = lv.Lo;
         a.E = lv.E; a.R = lv.R; a.Z = lv.Z; a.X = lv.X;
@@ -448,6 +489,9 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
     F->prof_fac_n = 0;
     hipError_t e = launch_fill_u64(F->d_status, 1, ~0ull, s);
     if (e != hipSuccess) return e;
+    if (F->d_badlist &&
+        (e = launch_fill_u64(F->d_badlist + kBadCap, 1, 0ull, s)) != hipSuccess)
+        return e;
     if (F->M != F->m && (e = pad_matrix(F, s)) != hipSuccess) return e;
     for (size_t l = 0; l < F->lv.size(); ++l) {
         const Level &L = F->lv[l];
@@ -580,6 +624,7 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
     F->prof_fac_n = 0;
     F->prof_sol_n = 0;
     HIPCHK(launch_fill_u64(F->d_status, 1, ~0ull, s));
+    if (F->d_badlist) HIPCHK(launch_fill_u64(F->d_badlist + kBadCap, 1, 0ull, s));
     const double *F0 = f;
     int64_t ld0f = ldf, ld0y = ldx;
     double *Y0 = x;
@@ -729,7 +774,7 @@ namespace {
 // arena the memory comes from it; with shared scratch (a batch) the handle
 // uses it for its dump and zero areas instead of its own.
 int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *arena,
-                 void *shared_scratch, pf_factor_s **out)
+                 void *shared_scratch, pf_factor_s **out, const SepOverrides *ovr = nullptr)
 {
     pf_factor_s *F = new pf_factor_s();
     F->al = g_allocator;
@@ -780,8 +825,14 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         }
     }
 
-    const auto plan = make_plan(A->kind, A->nb, M, o);
+    const auto plan = make_plan(A->kind, A->nb, M, o, ovr);
     F->lv.resize(plan.size());
+    const bool counting = arena && arena->counting;
+    if (o.flags & PF_FLAG_ENLARGE) {
+        if ((e_ = dalloc(F, &p, kBadCap * sizeof(unsigned long long) + 256, F->allocs)) != hipSuccess)
+            return fail(alloc_status(e_));
+        F->d_badlist = (unsigned long long *)p;
+    }
     for (size_t l = 0; l < plan.size(); ++l) {
         Level &L = F->lv[l];
         L.kind = plan[l].kind;
@@ -790,6 +841,19 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
         L.f32 = (l == 0 && o.prec == PF_FP32_IR);
         L.seg = seg_width(M, (int)l, L.kind, L.f32, o);
         if (L.seg == kMapTri && !tri_fits(L.nb, L.p)) L.seg = 1;
+        if (!plan[l].seps.empty()) {
+            // explicit boundaries: the kernels that follow them (not the
+            // LDS-staged scalar chains, whose staging assumes the balanced rule)
+            L.seps = plan[l].seps;
+            if (L.seg == kMapTri) L.seg = 1;
+            const size_t sb = L.seps.size() * sizeof(int64_t);
+            if ((e_ = dalloc(F, &p, sb, F->allocs)) != hipSuccess) return fail(alloc_status(e_));
+            L.d_sep = (int64_t *)p;
+            if (!counting &&
+                (e_ = hipMemcpyAsync(L.d_sep, L.seps.data(), sb, hipMemcpyHostToDevice, s)) !=
+                    hipSuccess)
+                return fail(alloc_status(e_));
+        }
         if (l == 0) {
             L.D = D0; L.Lo = Lo0;
             if (A->kind == PF_BTRI) L.Up = Up0;
@@ -840,12 +904,13 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
 // code.  One allocation instead of dozens keeps the host cost of a new
 // factorization low (a serving request pays it every time).
 int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, int nrhs,
-                         pf_factor_s **out, const Allocator *al = nullptr)
+                         pf_factor_s **out, const Allocator *al = nullptr,
+                         const SepOverrides *ovr = nullptr)
 {
     Arena count;
     count.counting = true;
     pf_factor_s *T = nullptr;
-    int rc = factor_setup(A, o, s, &count, nullptr, &T);
+    int rc = factor_setup(A, o, s, &count, nullptr, &T, ovr);
     if (rc) return rc;
     rc = ensure_workspace(T, nrhs);
     delete T;
@@ -860,7 +925,7 @@ int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, in
         return alloc_status(e);
     }
     pf_factor_s *F = nullptr;
-    if ((rc = factor_setup(A, o, s, ar, nullptr, &F)) || (rc = ensure_workspace(F, nrhs))) {
+    if ((rc = factor_setup(A, o, s, ar, nullptr, &F, ovr)) || (rc = ensure_workspace(F, nrhs))) {
         if (F) {
             F->arena = nullptr;
             delete F;
@@ -868,6 +933,73 @@ int factor_setup_private(const pf_matrix *A, const pf_opts &o, hipStream_t s, in
         dev_free(ar->al, ar->base, ar->cap, s);
         delete ar;
         return rc;
+    }
+    *out = F;
+    return 0;
+}
+
+// Partition boundaries of a level as a list (balanced rule, or explicit).
+std::vector<int64_t> level_bounds(const Level &L)
+{
+    if (!L.seps.empty()) return L.seps;
+    std::vector<int64_t> b(L.p + 1);
+    const bool btri = L.kind == PF_BTRI;
+    const int64_t nint = btri ? L.nb - (L.p - 1) : L.nb - (L.p + 1);
+    const int64_t q = nint / L.p, rem = nint % L.p;
+    b[0] = btri ? -1 : 0;
+    for (int64_t i = 0; i < L.p; ++i) b[i + 1] = b[i] + q + (i < rem ? 1 : 0) + 1;
+    return b;   // BTRI: b[p] = nb; BABD: b[p] = nb - 1
+}
+
+constexpr int kMaxEnlargePasses = 32;
+
+// Factorization with the reduced system enlarged where the local
+// eliminations fail (Sec. 2, the modified factorization after eq. (redmatr)):
+// a pass factors every level and lists, per failing partition, its first
+// pivot block that is singular or ill-conditioned; those block rows of the
+// lowest failing level become separators (the partition's elimination stops
+// before them and they enter the reduced system), that level is planned
+// again with the enlarged separator list and the levels above it anew, and
+// the next pass factors again, until no pivot block fails or the passes run
+// out (the status then reports the first failing block).  Synchronizes s.
+int factor_enlarged(const pf_matrix *A, const pf_opts &o, hipStream_t s, pf_factor_t *out)
+{
+    SepOverrides ovr;
+    pf_factor_s *F = nullptr;
+    for (int pass = 0;; ++pass) {
+        int rc = factor_setup_private(A, o, s, 1, &F, nullptr, &ovr);
+        if (rc) return rc;
+        hipError_t e = launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s);
+        if (e == hipSuccess) e = launch_factor_levels(F, s);
+        std::vector<unsigned long long> h(kBadCap + 1);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.data(), F->d_badlist, (kBadCap + 1) * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            pf_destroy(F);
+            return PF_EHIP;
+        }
+        const unsigned cnt = std::min<unsigned>((unsigned)h[kBadCap], (unsigned)kBadCap);
+        // In the bidiagonal-plus-corner form the reduced matrix (eq.
+        // (redmatr1)) keeps each separator's own diagonal block (no
+        // contribution is added to it), so a failing block would fail again
+        // on every reduced level: there the pass only detects and reports.
+        if (cnt == 0 || A->kind == PF_BABD || pass + 1 >= kMaxEnlargePasses) break;
+        std::vector<unsigned long long> codes(h.begin(), h.begin() + cnt);
+        std::sort(codes.begin(), codes.end());
+        codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
+        const int lvl = (int)(codes.front() >> 40);
+        std::vector<int64_t> b = level_bounds(F->lv[lvl]);
+        for (unsigned long long c : codes)
+            if ((int)(c >> 40) == lvl) b.push_back((int64_t)(c & ((1ull << 40) - 1)));
+        std::sort(b.begin(), b.end());
+        b.erase(std::unique(b.begin(), b.end()), b.end());
+        ovr[lvl] = b;
+        ovr.erase(ovr.upper_bound(lvl), ovr.end());
+        pf_destroy(F);
+        F = nullptr;
     }
     *out = F;
     return 0;
@@ -891,6 +1023,7 @@ int pf_factor(const pf_matrix *A, const pf_opts *opts, void *stream, pf_factor_t
         if ((rc = tuned_opts(A, o, 1, s, &t))) return rc;
         o = resolve_opts(&t);
     }
+    if (o.flags & PF_FLAG_ENLARGE) return factor_enlarged(A, o, s, out);
     pf_factor_s *F = nullptr;
     if ((rc = factor_setup_private(A, o, s, 1, &F))) return rc;
     hipError_t e = launch_fill_u64((unsigned long long *)F->d_zero, kZeroBytes / 8, 0ull, s);

@@ -39,7 +39,13 @@ __device__ __forceinline__ unsigned long long status_code(int level, int64_t blo
 
 // ---- partition geometry ---------------------------------------------------
 // Balanced rule: the non-separator blocks are spread as evenly as possible,
-// the first (count mod p) partitions getting one block more.
+// the first (count mod p) partitions getting one block more.  With an
+// explicit separator list sep (p + 1 entries: partition i covers the blocks
+// sep[i] + 1 .. sep[i + 1] - 1; for block tridiagonal levels sep[0] = -1 and
+// sep[p] = nb stand for the ends, for the bidiagonal-plus-corner form both
+// ends are real separators) the partitions are the ranges between them --
+// a level whose reduced system was enlarged by blocks the elimination could
+// not pivot on; a partition may then be empty.
 struct Geo {
     int64_t start;   // first block of the partition
     int len;         // blocks in the partition
@@ -48,16 +54,24 @@ struct Geo {
 };
 
 template <int KIND>
-__device__ __forceinline__ Geo geometry(int64_t nb, int64_t p, int64_t part)
+__device__ __forceinline__ Geo geometry(int64_t nb, int64_t p, int64_t part,
+                                        const int64_t *sep = nullptr)
 {
     Geo g;
-    const int64_t nint = (KIND == 0) ? nb - (p - 1) : nb - (p + 1);
-    const int64_t q = nint / p, rem = nint % p;
     g.valid = part < p;
-    const int64_t mn = part < rem ? part : rem;
-    g.start = (KIND == 0 ? 0 : 1) + part * (q + 1) + mn;
-    g.len = g.valid ? (int)(q + (part < rem ? 1 : 0)) : 0;
-    g.kmax = (int)(q + (rem > 0 ? 1 : 0));
+    if (sep) {
+        const int64_t pp = g.valid ? part : p - 1;
+        g.start = sep[pp] + 1;
+        g.len = g.valid ? (int)(sep[pp + 1] - sep[pp] - 1) : 0;
+        g.kmax = g.len;
+    } else {
+        const int64_t nint = (KIND == 0) ? nb - (p - 1) : nb - (p + 1);
+        const int64_t q = nint / p, rem = nint % p;
+        const int64_t mn = part < rem ? part : rem;
+        g.start = (KIND == 0 ? 0 : 1) + part * (q + 1) + mn;
+        g.len = g.valid ? (int)(q + (part < rem ? 1 : 0)) : 0;
+        g.kmax = (int)(q + (rem > 0 ? 1 : 0));
+    }
     if (KIND == 0) {
         g.hasL = g.valid && part > 0;
         g.hasR = g.valid && part < p - 1;
@@ -66,6 +80,22 @@ __device__ __forceinline__ Geo geometry(int64_t nb, int64_t p, int64_t part)
         g.hasR = g.valid;
     }
     return g;
+}
+
+// A partition's pivot-block failures: the first one (smallest level and
+// block) goes to the status word; with a list (enlarged reduced systems)
+// every failing partition also appends its first failing block, which the
+// host turns into a separator.  Called by every lane of the partition with
+// the same code (the host removes the repeats).
+template <class LA>
+__device__ __forceinline__ void report_bad(const LA &a, unsigned long long bad)
+{
+    if (bad == ~0ull) return;
+    atomicMin(a.status, bad);
+    if (a.badlist) {
+        const unsigned i = atomicAdd(a.badcount, 1u);
+        if (i < (unsigned)a.badcap) a.badlist[i] = bad;
+    }
 }
 
 // ---- register <-> memory helpers ------------------------------------------

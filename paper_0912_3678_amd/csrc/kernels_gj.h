@@ -56,13 +56,16 @@ __device__ __forceinline__ int seg_pivot(T bj, bool used, int r, int j)
 
 // In-place Gauss-Jordan of the tableau b = D'(r, c0 .. c0+E-1), c0 = gc E;
 // returns sigma(r) and p_c of the lane's columns through the references.
+// tau > 0: the block also fails (ill-conditioned) when its smallest pivot
+// is below tau times its largest (or a pivot is not finite).
 template <int M, int E, typename T>
 __device__ __forceinline__ void seg_invert(T (&b)[E], int r, int gc, T *S, int &sigma,
-                                           int (&pc)[E], bool &sing)
+                                           int (&pc)[E], bool &sing, T tau = T(0))
 {
     constexpr int RS = M + kPad<T>;
     const int c0 = gc * E;
     bool used = false;
+    T pmin = T(0), pmax = T(0);
     int pr = seg_pivot<M, E, T>(b[0], used, r, 0);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -83,6 +86,9 @@ __device__ __forceinline__ void seg_invert(T (&b)[E], int r, int gc, T *S, int &
             pv = S[__umul24(pr, RS) + j];
         }
         sing = sing || (pv == T(0));
+        const T apv = fabs(pv);
+        pmin = j == 0 ? apv : fmin(pmin, apv);
+        pmax = j == 0 ? apv : fmax(pmax, apv);
         const T inv = recip(pv);
         const bool isr = (r == pr);
         // exchange step as selects of computed values (no divergent code):
@@ -108,6 +114,7 @@ __device__ __forceinline__ void seg_invert(T (&b)[E], int r, int gc, T *S, int &
         wave_sync();
         if (j + 1 < M) pr = seg_pivot<M, E, T>(b[(j + 1) % E], used, r, j + 1);
     }
+    if (tau > T(0)) sing = sing || !(pmin > tau * pmax);
 }
 
 }  // namespace

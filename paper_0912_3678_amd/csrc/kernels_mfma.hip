@@ -81,8 +81,8 @@ __device__ __forceinline__ void btri_mfma_body(const LevelArgs &a, const SolveAr
     // The wave's partitions.  A partition past the last one shadows the first
     // (same rows, every output dropped), so both have lengths within one.
     const int64_t nb = a.nb;
-    const Geo G0 = geometry<0>(nb, a.p, pblock * PPW);
-    const Geo G1r = geometry<0>(nb, a.p, pblock * PPW + 1);
+    const Geo G0 = geometry<0>(nb, a.p, pblock * PPW, a.sep);
+    const Geo G1r = geometry<0>(nb, a.p, pblock * PPW + 1, a.sep);
     const bool sh1 = !G1r.valid;
     const Geo G1 = sh1 ? G0 : G1r;
     const Geo &Gg = gp ? G1 : G0, &Gm = mp ? G1 : G0;
@@ -240,7 +240,7 @@ __device__ __forceinline__ void btri_mfma_body(const LevelArgs &a, const SolveAr
     for (; k < kmin; ++k) row(std::integral_constant<bool, false>{}, k);
     if (k < kmax) row(std::integral_constant<bool, true>{}, k);
 
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     if (Gm.valid && outm) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {

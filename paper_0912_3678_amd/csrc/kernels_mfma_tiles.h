@@ -246,7 +246,7 @@ __device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveA
     V *SE = S0 + M * RS;      // E by logical rows; then D' handed over
 
     const int64_t nb = a.nb;
-    const Geo G = geometry<0>(nb, a.p, part);
+    const Geo G = geometry<0>(nb, a.p, part, a.sep);
     const int64_t gb = G.start > 0 ? G.start - 1 : 0;
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
@@ -287,6 +287,16 @@ __device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveA
         z = qload<false, T, V>(rL, (rel - 1) * BB, m, n);
         rT = qload<true, T, V>(rU, (rel - 1) * BB, m, n);
     }
+    if (G.len == 0) {   // an empty partition (enlarged reduced systems): D' of sR is D[sR]
+        dq = qload<false, T, V>(rD, rel * BB, m, n);
+        if constexpr (ADD) {
+            const Q da = qload<false, T, V>(rDa, rel * BB, m, n);
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J) dq.t[I][J] += da.t[I][J];
+        }
+    }
     unsigned long long bad = ~0ull;
 
     for (int k = 0; k < G.len; ++k) {
@@ -310,7 +320,7 @@ __device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveA
 #pragma unroll
         for (int e = 0; e < E; ++e) pc[e] = 0;
         bool sing = false;
-        seg_invert<M, E, V>(d, r, gc, S0, sigma, pc, sing);
+        seg_invert<M, E, V>(d, r, gc, S0, sigma, pc, sing, (V)a.tau);
         const unsigned long long code = status_code(a.level, G.start + k);
         bad = (sing && code < bad) ? code : bad;
 #pragma unroll
@@ -357,7 +367,7 @@ __device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveA
         lds_row<E, V>(d, SE + r * RS + c0);
         wave_sync();
     }
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     if (G.hasR) {
         qstore_gt<false, T>(a.nD + part * MM, dq, m, n);                      // D[sR] + alpha_2
         if (G.hasL) qstore_gt<false, T>(a.nLo + (part - 1) * MM, z, m, n);    // beta
@@ -421,7 +431,7 @@ __device__ __forceinline__ void fwdt_body(const SolveArgs &a, int64_t part, int 
     constexpr uint32_t BB = MM * 8, BF = MM * sizeof(V);
     const int m = lane >> 4, n = lane & 15;
     const int64_t nb = a.nb;
-    const Geo G = geometry<KIND>(nb, a.p, part);
+    const Geo G = geometry<KIND>(nb, a.p, part, a.sep);
     const int64_t gb = G.start > 0 ? G.start - 1 : 0;
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rE = buf_rsrc((const V *)a.E + gb * MM, nr * BF);
@@ -484,7 +494,7 @@ __device__ __forceinline__ void bwdt_body(const SolveArgs &a, int64_t part, int 
     constexpr uint32_t BF = MM * sizeof(V);
     const int m = lane >> 4, n = lane & 15;
     const int64_t nb = a.nb;
-    const Geo G = geometry<KIND>(nb, a.p, part);
+    const Geo G = geometry<KIND>(nb, a.p, part, a.sep);
     const int64_t gb = G.start > 0 ? G.start - 1 : 0;
     const uint64_t nr = (uint64_t)(nb - gb);
     const auto rZ = buf_rsrc((const V *)a.Z + gb * MM, nr * BF);
@@ -626,7 +636,7 @@ __device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const Solve
     V *SE = lds + (kBQ + q) * BSL;     // E_q by logical rows
 
     const int64_t nb = a.nb;
-    const Geo G = geometry<1>(nb, a.p, part);
+    const Geo G = geometry<1>(nb, a.p, part, a.sep);
     const int64_t gb = G.start - 1;         // the left separator (G.start >= 1)
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
@@ -671,7 +681,7 @@ __device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const Solve
 #pragma unroll
         for (int e = 0; e < E; ++e) pc[e] = 0;
         bool sing = false;
-        seg_invert<M, E, V>(d, r, 0, S0, sigma, pc, sing);
+        seg_invert<M, E, V>(d, r, 0, S0, sigma, pc, sing, (V)a.tau);
         const unsigned long long code = status_code(a.level, G.start + k0 + q);
         bad = (sing && vq && code < bad) ? code : bad;
 #pragma unroll
@@ -710,7 +720,7 @@ __device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const Solve
         }
         wave_sync();
     }
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     if (G.valid) {
         const int64_t sR = G.start + G.len;
         qstore_gt<false, 1>(a.nLo + part * MM, z, m, n);   // beta

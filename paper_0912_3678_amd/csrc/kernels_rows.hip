@@ -55,10 +55,14 @@ namespace {
 // eliminated from every other row.  Rows never move: the lane chosen at step
 // c ends with row c of D'^{-1} in e, and sigma (the return value) is c.
 // Only the columns > c of d are still needed after step c.
+// tau > 0: the block also fails (ill-conditioned) when its smallest pivot
+// is below tau times its largest (or a pivot is not finite).
 template <int M, typename T>
-__device__ __forceinline__ int gj_rows(T (&d)[M], T (&e)[M], int i, T *SP, bool &sing)
+__device__ __forceinline__ int gj_rows(T (&d)[M], T (&e)[M], int i, T *SP, bool &sing,
+                                       T tau = T(0))
 {
     constexpr int PR = 2 * M + kPad<T>;   // padded row stride of SP
+    T pmin = T(0), pmax = T(0);
 #pragma unroll
     for (int l = 0; l < M; ++l) e[l] = (l == i) ? T(1) : T(0);
     bool used = false;
@@ -80,6 +84,9 @@ __device__ __forceinline__ int gj_rows(T (&d)[M], T (&e)[M], int i, T *SP, bool 
         for (int l = 0; l < M; ++l) pe[l] = prow[M + l];
         const T pv = pd[c];
         sing = sing || (pv == T(0));
+        const T apv = fabs(pv);
+        pmin = c == 0 ? apv : fmin(pmin, apv);
+        pmax = c == 0 ? apv : fmax(pmax, apv);
         const T inv = recip(pv);
         const bool isp = (i == pr);
         const T f = isp ? -inv : d[c] * inv;
@@ -92,6 +99,7 @@ __device__ __forceinline__ int gj_rows(T (&d)[M], T (&e)[M], int i, T *SP, bool 
         sigma = isp ? c : sigma;
         wave_sync();
     }
+    if (tau > T(0)) sing = sing || !(pmin > tau * pmax);
     return sigma;
 }
 
@@ -122,7 +130,7 @@ __device__ __forceinline__ void btri_factor_body(const LevelArgs &a, int64_t pbl
 
     const int64_t nb = a.nb;
     const int64_t part = pblock * GPW + grp;
-    const Geo G = geometry<0>(nb, a.p, part);
+    const Geo G = geometry<0>(nb, a.p, part, a.sep);
     T *E = (T *)a.E, *R = (T *)a.R, *Zs = (T *)a.Z, *Xs = (T *)a.X;
     T *dump = (T *)a.dump + tid * M;
 
@@ -168,7 +176,7 @@ __device__ __forceinline__ void btri_factor_body(const LevelArgs &a, int64_t pbl
 
         T e[M];
         bool sing = false;
-        const int sig = gj_rows<M, T>(d, e, i, SP, sing);
+        const int sig = gj_rows<M, T>(d, e, i, SP, sing, (T)a.tau);
         const unsigned long long code = status_code(a.level, g);
         bad = (sing && code < bad) ? code : bad;
         st_fac<M, T>(E + g * MM + sig * M, e);             // row sig of E_k
@@ -225,7 +233,7 @@ __device__ __forceinline__ void btri_factor_body(const LevelArgs &a, int64_t pbl
         }
         wave_sync();
     }
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     // contributions to the reduced matrix (eq. (redmatr)); separator j sits
     // between partitions j and j+1
     if (G.hasR) {
@@ -256,7 +264,7 @@ __device__ __forceinline__ void babd_factor_body(const LevelArgs &a, int64_t pbl
     T *SZ = SP + M * PR;      // Z'^T, then the rows of Zh
 
     const int64_t part = pblock * GPW + grp;
-    const Geo G = geometry<1>(a.nb, a.p, part);
+    const Geo G = geometry<1>(a.nb, a.p, part, a.sep);
     T *E = (T *)a.E, *Zs = (T *)a.Z;
 
     T z[M];
@@ -281,7 +289,7 @@ __device__ __forceinline__ void babd_factor_body(const LevelArgs &a, int64_t pbl
         ld_row_d<M, T>(lc, more ? a.Lo + (g + 1) * MM : a.zero, i);
         T e[M];
         bool sing = false;
-        const int sig = gj_rows<M, T>(d, e, i, SP, sing);
+        const int sig = gj_rows<M, T>(d, e, i, SP, sing, (T)a.tau);
         const unsigned long long code = status_code(a.level, g);
         bad = (sing && code < bad) ? code : bad;
         st_fac<M, T>(E + g * MM + sig * M, e);
@@ -311,7 +319,7 @@ __device__ __forceinline__ void babd_factor_body(const LevelArgs &a, int64_t pbl
         for (int c = 0; c < M; ++c) z[c] = -zl[c];
         wave_sync();
     }
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     if (G.valid) {
         const int64_t sR = G.start + G.len;
         st_row_d<M, T>(a.nLo + part * MM, i, z);                     // beta

@@ -71,14 +71,14 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
 
     const int64_t nb = a.nb;
     const int64_t part = pblock * PPW + grp;
-    const Geo G = geometry<0>(nb, a.p, part);
+    const Geo G = geometry<0>(nb, a.p, part, a.sep);
     const int gc = t / M;   // segment column
 
     // Block arrays and factors through raw buffers based one block row before
     // the workgroup's first partition: every row a partition touches lies at
     // or past the base (its left separator's couplings included), and rows
     // past an array's end read zero, as a missing operand must.
-    const int64_t s0 = geometry<0>(nb, a.p, pblock * PPW).start;
+    const int64_t s0 = geometry<0>(nb, a.p, pblock * PPW, a.sep).start;
     const int64_t gb = s0 > 0 ? s0 - 1 : 0;
     constexpr uint32_t BB = MM * 8, BT = MM * sizeof(T);
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
 #pragma unroll
         for (int e = 0; e < E; ++e) { b[e] = d[e]; pc[e] = 0; }
         bool sing = false;
-        seg_invert<M, E, T>(b, r, gc, S0, sigma, pc, sing);
+        seg_invert<M, E, T>(b, r, gc, S0, sigma, pc, sing, (T)a.tau);
         const unsigned long long code = status_code(a.level, g);
         bad = (sing && code < bad) ? code : bad;
 
@@ -259,7 +259,7 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
         for (int d = 0; d < PD; ++d) buf[d] = buf[d + 1];
         wave_sync();
     }
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int cm = r + (c0 + e) * M;
@@ -302,12 +302,12 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
     constexpr int PD = seg_prefetch<E>();
 
     const int64_t part = pblock * PPW + grp;
-    const Geo G = geometry<1>(a.nb, a.p, part);
+    const Geo G = geometry<1>(a.nb, a.p, part, a.sep);
     const int gc = t / M;   // segment column
     // raw buffers based one block row before the workgroup's first partition
     // (its left separator); rows past an array's end read zero
     const int64_t nb = a.nb;
-    const int64_t gb = geometry<1>(nb, a.p, pblock * PPW).start - 1;
+    const int64_t gb = geometry<1>(nb, a.p, pblock * PPW, a.sep).start - 1;
     constexpr uint32_t BB = MM * 8, BT = MM * sizeof(T);
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
@@ -372,7 +372,7 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
 #pragma unroll
         for (int e = 0; e < E; ++e) { b[e] = (T)cur.dc[e]; lo[e] = (T)cur.lc[e]; pc[e] = 0; }
         bool sing = false;
-        seg_invert<M, E, T>(b, r, gc, S0, sigma, pc, sing);
+        seg_invert<M, E, T>(b, r, gc, S0, sigma, pc, sing, (T)a.tau);
         const unsigned long long code = status_code(a.level, g);
         bad = (sing && code < bad) ? code : bad;
 
@@ -427,7 +427,7 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
         for (int d = 0; d < PD; ++d) buf[d] = buf[d + 1];
         wave_sync();
     }
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     if (G.valid) {
         const int64_t sR = G.start + G.len;
 #pragma unroll

@@ -36,7 +36,7 @@ __device__ __forceinline__ void fwd_body(const SolveArgs &a, int64_t pblock, int
     constexpr int GS = group_stride<T>(KC * CS);
     T *SV = lds + grp * GS;                           // M x KC block vector, by columns
     const int64_t part = pblock * GPW + grp;
-    const Geo G = geometry<KIND>(a.nb, a.p, part);
+    const Geo G = geometry<KIND>(a.nb, a.p, part, a.sep);
     const int c0 = cblock * KC;
     const int kc = (a.nrhs - c0) < KC ? (a.nrhs - c0) : KC;
     const T *E = (const T *)a.E, *R = (const T *)a.R;
@@ -161,7 +161,7 @@ __device__ __forceinline__ void bwd_body(const SolveArgs &a, int64_t pblock, int
     T *SV = lds + grp * GS;                           // x of the row below (M x KC)
     T *SL = SV + KC * CS;                             // x at the left separator
     const int64_t part = pblock * GPW + grp;
-    const Geo G = geometry<KIND>(a.nb, a.p, part);
+    const Geo G = geometry<KIND>(a.nb, a.p, part, a.sep);
     const int c0 = cblock * KC;
     const int kc = (a.nrhs - c0) < KC ? (a.nrhs - c0) : KC;
     const T *Zs = (const T *)a.Z, *Xs = (const T *)a.X;

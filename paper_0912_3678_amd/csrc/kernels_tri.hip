@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kTriWG) void k_tri_factor(LevelArgs a, SolveArgs sv
         rr = rn;
     }
     if (G.valid) sR[o + G.len] = 0.0;   // the right separator's row (no factor)
-    if (bad != ~0ull) atomicMin(a.status, bad);
+    report_bad(a, bad);
     if (G.hasR) {
         a.nD[part] = d;                        // D[sR] + alpha_2
         if (G.hasL) a.nLo[part - 1] = z;       // beta

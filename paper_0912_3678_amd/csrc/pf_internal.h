@@ -35,6 +35,12 @@ struct LevelArgs {
     void *dump;            // kDumpBytes of scratch that masked stores write into
     const double *zero;    // kZeroBytes of zeros: the target of out-of-range loads
     int level;
+    const int64_t *sep;    // explicit partition boundaries (p + 1 entries), or null: balanced
+    double tau;            // > 0: a pivot block whose smallest pivot is below tau times its
+                           // largest counts as failing (ill-conditioned), besides zero pivots
+    unsigned long long *badlist;   // with a list: every failing partition appends its code
+    unsigned *badcount;
+    int badcap;
 };
 
 // Device scratch that receives the stores a lane must not make, and a block
@@ -61,6 +67,7 @@ struct SolveArgs {
     const double *Xsep;    // backward: next level's solution (ld ldn)
     double *dump;          // kDumpBytes of scratch for masked stores
     const double *zero;    // kZeroBytes of zeros
+    const int64_t *sep;    // explicit partition boundaries, or null (as LevelArgs)
 };
 
 // Factor launchers, two lane mappings.

@@ -19,6 +19,7 @@ PF_OK, PF_ESINGULAR, PF_ENOCONV, PF_ENOMEM, PF_EHIP, PF_EUNSUPPORTED = 0, 1, 2, 
 PF_ETOOBIG = 6
 PF_FLAG_ETA = 1
 PF_FLAG_MAP_ROWS, PF_FLAG_MAP_TILES, PF_FLAG_AUTOTUNE, PF_FLAG_MAP_SEGMENTS = 2, 4, 8, 16
+PF_FLAG_ENLARGE = 32
 
 EXPORTED = [
     "pf_factor", "pf_solve", "pf_solve_batch", "pf_factor_bytes", "pf_solve_bytes_per_rhs",

@@ -285,6 +285,64 @@ def random_babd(nb: int, m: int, seed: int, nrhs=None) -> System:
                   {"workload": "random_babd", "nb": nb, "m": m, "seed": seed})
 
 
+def _failing_block(rng, m, how):
+    """A diagonal block the local elimination cannot pivot on: all zeros
+    ("zero"), or U diag(1, .., 1, 1e-15) V^T with random orthogonal U, V
+    ("ill": condition 1e15)."""
+    if how == "zero":
+        return np.zeros((m, m))
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    sv = np.ones(m)
+    sv[-1] = 1e-15
+    return (U * sv) @ V.T
+
+
+def btri_failing_pivots(nb: int, m: int, seed: int, rows, how: str = "zero",
+                        nrhs=None) -> System:
+    """random_btri's law with the diagonal blocks of `rows` replaced by
+    failing blocks and the couplings into them from the row above removed
+    (A(k, k-1) = 0), so that a partition's elimination meets them as its
+    pivot blocks unchanged; the matrix as a whole stays regular (row k
+    reaches x_{k+1} through A(k, k+1)).  Manufactured solution."""
+    rng = np.random.default_rng(seed)
+    s = 1.0 / math.sqrt(m)
+    D = rng.standard_normal((nb, m, m)) * s + 4.0 * np.eye(m)[None]
+    Lo = rng.standard_normal((nb - 1, m, m)) * s
+    Up = rng.standard_normal((nb - 1, m, m)) * s
+    for k in rows:
+        D[k] = _failing_block(rng, m, how)
+        if k > 0:
+            Lo[k - 1] = 0.0
+    x = rng.standard_normal(_rhs_shape(nb * m, nrhs))
+    f = btri_apply(D, Lo, Up, x)
+    return System("btri", D, Lo, Up, None, f, x,
+                  {"workload": "btri_failing_pivots", "nb": nb, "m": m, "seed": seed,
+                   "rows": list(rows), "how": how})
+
+
+def babd_failing_pivots(nb: int, m: int, seed: int, rows, how: str = "zero",
+                        nrhs=None) -> System:
+    """random_babd's law with the diagonal blocks of `rows` (interior block
+    rows) replaced by failing blocks; in this form the pivot blocks are the
+    diagonal blocks themselves.  Manufactured solution."""
+    rng = np.random.default_rng(seed)
+    s = 0.3 / math.sqrt(m)
+    # transfer maps -D[k+1]^{-1} Lo[k] near the identity: a block row that
+    # cannot be pivoted on leaves a free block that the corner must still
+    # fix, which it can only while the chain neither grows nor decays much
+    D = rng.standard_normal((nb, m, m)) * s + 3.0 * np.eye(m)[None]
+    Lo = rng.standard_normal((nb - 1, m, m)) * s - 3.0 * np.eye(m)[None]
+    C = rng.standard_normal((m, m)) * s + np.eye(m)
+    for k in rows:
+        D[k] = _failing_block(rng, m, how)
+    x = rng.standard_normal(_rhs_shape(nb * m, nrhs))
+    f = babd_apply(D, Lo, C, x)
+    return System("babd", D, Lo, None, C, f, x,
+                  {"workload": "babd_failing_pivots", "nb": nb, "m": m, "seed": seed,
+                   "rows": list(rows), "how": how})
+
+
 def batch_specs(count: int = 512, seed: int = seed_for(4), m_choices=(4, 8, 16, 32),
                 n_lo: int = 2 ** 8, n_hi: int = 2 ** 16, max_rhs: int = 64):
     """Shapes of the batched workload: m uniform over m_choices, the block
