@@ -96,24 +96,28 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False):
-    """Algorithmic bytes one launch moves: the blocks it must read and the
-    factors / vectors it must write (8-byte words; 4 for FP32 factors)."""
+def kernel_bytes(kind, phase, level_nb, m, nrhs, f32=False, split=False, whole=False):
+    """Algorithmic bytes of one launch by the method's per-unit figures
+    (8-byte words; 4 for FP32 factors): one read of the input blocks, the
+    right-hand-side read and the solution write.  The factors' stores and
+    their re-reads count only when factor and solve are separate calls
+    (split: pf_refactor, then pf_solve); inside one factor-and-solve call
+    they are the method's intermediate state.  whole: one launch does the
+    level's factor, forward sweep and back substitution."""
     w = 4 if f32 else 8
     mm = m * m
-    if phase == "factor+forward":   # the factor's blocks plus f read and t written
-        return kernel_bytes(kind, "factor", level_nb, m, nrhs, f32) + level_nb * 2 * m * 8 * nrhs
-    if kind == 0:  # block tridiagonal
-        if phase == "factor":   # read D, Lo, Up; write E, R, Z, X
-            return level_nb * (3 * mm * 8 + 4 * mm * w)
-        if phase == "forward":  # read Lo, E, R, f; write t
-            return level_nb * (mm * 8 + 2 * mm * w + 2 * m * 8 * nrhs)
-        return level_nb * (2 * mm * w + 2 * m * 8 * nrhs)   # read Z, X, t; write x
-    if phase == "factor":       # read D, Lo; write E, Z
-        return level_nb * (2 * mm * 8 + 2 * mm * w)
-    if phase == "forward":      # read Lo, E, f; write t
-        return level_nb * (mm * 8 + mm * w + 2 * m * 8 * nrhs)
-    return level_nb * (mm * w + 2 * m * 8 * nrhs)           # read Z, t; write x
+    nblk = 3 if kind == 0 else 2            # D, Lo, Up (block tridiagonal) or D, Lo
+    nfac = 4 if kind == 0 else 2            # E, R, Z, X or E, Z
+    rhs = level_nb * m * 8 * nrhs
+    if whole:
+        return level_nb * nblk * mm * 8 + 2 * rhs
+    if phase == "factor+forward":           # A read, f read (t is intermediate)
+        return level_nb * nblk * mm * 8 + rhs
+    if phase == "factor":
+        return level_nb * (nblk * mm * 8 + (nfac * mm * w if split else 0))
+    if phase == "forward":                  # f read (+ Lo, E, R when split)
+        return rhs + (level_nb * (mm * 8 + (nfac // 2) * mm * w) if split else 0)
+    return rhs + (level_nb * (nfac // 2) * mm * w if split else 0)   # x write (+ Z, X)
 
 
 # Sources each profiled kernel is built from: its recorded counters stay valid
@@ -266,6 +270,8 @@ def run_bvp(args):
     F = pf.pf_factor(A, opts)
     levels = pf.pf_factor_levels(F)
     torch.cuda.synchronize()
+    # small scalar systems: pf_factor_solve is one launch of local cyclic reduction
+    cr = (tri and args.map == "auto" and not args.split and nb <= 4096 and levels[0][2] <= 64)
 
     def step_fused():
         pf.pf_factor_solve(F, f, x, want_info=False)
@@ -334,7 +340,8 @@ def run_bvp(args):
     total_alg = 0
     for (ph, lvl), v in sorted(acc.items(), key=lambda kv: (kv[0][1], kv[0][0])):
         kind, lnb, lp = levels[lvl]
-        b = kernel_bytes(kind, ph, lnb, m, 1)
+        whole = tri and cr and lvl == 0 and ph == "factor+forward"
+        b = kernel_bytes(kind, ph, lnb, m, 1, split=args.split, whole=whole)
         total_alg += b
         avg = float(np.mean(v))
         kernels.append({"phase": ph, "level": lvl, "nb": lnb, "p": lp, "avg_us": round(avg * 1e3, 2),
@@ -344,9 +351,10 @@ def run_bvp(args):
     E = 0 if args.map == "rows" else (args.lane_entries or {8: 2, 16: 4, 32: 0}.get(M, 1))
     mfma = args.map == "auto" and not args.lane_entries and M == 8
     # m = 1: rows staged through LDS (chains of up to 5, 9, 13 or 17 blocks)
-    trik = args.map == "auto" and M == 1
+    # (longer chains run on the segment kernel with one entry per lane)
     nint0 = levels[0][1] - (levels[0][2] - 1)
     km = next(k for k in (5, 9, 13, 17, 10 ** 9) if -(-nint0 // levels[0][2]) <= k)
+    trik = args.map == "auto" and M == 1 and km <= 17
     names = {"factor": ("k_btri_mfma<false>" if mfma else
                         f"k_tri_factor<{km}, false, false>" if trik else
                         f"k_btri_seg<{M}, {E}, double, false, false>" if E else
@@ -356,6 +364,8 @@ def run_bvp(args):
                                 f"k_btri_seg<{M}, {E}, double, false, true>"),
              "forward": f"k_tri_fwd<{km}, false>" if trik else f"k_fwd<0, {M}, 1, double, false>",
              "backward": f"k_tri_bwd<{km}>" if trik else f"k_bwd<0, {M}, 1, double>"}
+    if cr:
+        names["factor+forward"] = "k_tri_cr_whole"
     dom_name = names[dom["phase"]] if dom["level"] == 0 else f"{dom['phase']} level {dom['level']}"
     dom_bytes = dom["alg_MB"] * 1e6
     achieved = dom_bytes / (dom["avg_us"] * 1e-6) / 1e9

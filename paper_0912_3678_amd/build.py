@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_rows.hip", "kernels_seg.hip", "kernels_tri.hip", "kernels_mfma.hip", "kernels_mfma_tiles.hip", "kernels_mfma_tiles32.hip", "kernels_solve.hip", "kernels_util.hip", "api.cpp", "tune.cpp", "server.cpp", "noalloc.hip"]
+SOURCES = ["kernels_rows.hip", "kernels_seg.hip", "kernels_tri.hip", "kernels_tri_cr.hip", "kernels_mfma.hip", "kernels_mfma_tiles.hip", "kernels_mfma_tiles32.hip", "kernels_solve.hip", "kernels_util.hip", "api.cpp", "tune.cpp", "server.cpp", "noalloc.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -136,6 +136,11 @@ struct pf_factor_s {
     Arena *arena = nullptr;
     // PF_FLAG_ENLARGE: failing partitions' codes (kBadCap) and their count
     unsigned long long *d_badlist = nullptr;
+    // small scalar tridiagonal systems: pf_factor_solve with one right-hand
+    // side runs as one launch (local cyclic reduction, kernels_tri_cr.hip),
+    // which leaves the stored factors behind the matrix's values
+    bool tri_cr = false;
+    bool factors_stale = false;
 };
 
 namespace {
@@ -171,6 +176,22 @@ int target_rows(int kind, int M, bool f32, int level, const pf_opts &o)
 }
 
 constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chain
+
+// Scalar tridiagonal systems of at most kTriCrMaxRows rows in FP64 are
+// solved by pf_factor_solve (one right-hand side) in one launch with local
+// cyclic reduction; by default their finest level then has partitions of
+// about kTriCrRows rows (fewer reduction rounds), at most one wave's lanes of
+// them (the reduced system is solved across one wave).
+constexpr int64_t kTriCrRows = 64;
+int64_t tri_cr_parts(int64_t nb)
+{
+    return std::max<int64_t>(1, std::min<int64_t>(kTriCrMaxParts, (nb + 1) / (kTriCrRows + 1)));
+}
+bool tri_cr_default(int M, int64_t nb, const pf_opts &o)
+{
+    return M == 1 && o.prec == PF_FP64 && !(o.flags & (PF_FLAG_ENLARGE | PF_FLAG_MAP_ROWS)) &&
+           tri_cr_fits(nb, tri_cr_parts(nb));
+}
 // (scalar tridiagonal reduced levels: up to kTriMaxChain blocks, one chain in
 // LDS)
 
@@ -262,6 +283,7 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o,
         }
         int64_t p;
         if (lvl == 0 && o.partitions > 0) p = o.partitions;
+        else if (lvl == 0 && tri_cr_default(M, cur, o)) p = tri_cr_parts(cur);
         else if (cur <= kTail || (M == 1 && lvl > 0 && cur <= kTriMaxChain)) p = 1;
         else {
             const int L = target_rows(kind, M, f32, lvl, o);
@@ -608,6 +630,23 @@ int run_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x,
 // Factor-and-solve in one pass per level (every level on the segment mapping,
 // 1 <= nrhs <= M): the factor kernels also sweep the right-hand sides
 // forward, then the back substitution runs up the levels as in run_solve.
+// Factor-and-solve of a small scalar tridiagonal system (one right-hand
+// side) in one launch: the finest level's partitions by local cyclic
+// reduction, the reduced system across one wave, the back substitution.  The
+// launch sets the status word itself; the stored factors are left behind
+// (pf_solve refactors first).
+int run_tri_cr(pf_factor_s *F, const double *f, double *x, hipStream_t s)
+{
+    const pf_matrix &A = F->A;
+    F->prof_fac_n = 0;
+    F->prof_sol_n = 0;
+    HIPCHK(prof_launch(F, true, 3, 0, s, [&] {
+        return launch_tri_cr_whole(A.nb, F->lv[0].p, A.D, A.Lo, A.Up, f, x, F->d_status, s);
+    }));
+    F->factors_stale = true;
+    return 0;
+}
+
 bool fused_ok(const pf_factor_s *F, int nrhs)
 {
     if (nrhs < 1 || nrhs > F->M) return false;
@@ -827,6 +866,10 @@ int factor_setup(const pf_matrix *A, const pf_opts &o, hipStream_t s, Arena *are
 
     const auto plan = make_plan(A->kind, A->nb, M, o, ovr);
     F->lv.resize(plan.size());
+    F->tri_cr = A->kind == PF_BTRI && M == 1 && A->m == 1 && o.prec == PF_FP64 &&
+                !(o.flags & (PF_FLAG_ENLARGE | PF_FLAG_MAP_ROWS | PF_FLAG_ETA |
+                             PF_FLAG_MAP_SEGMENTS)) && !ovr &&
+                tri_cr_fits(A->nb, plan[0].p);
     const bool counting = arena && arena->counting;
     if (o.flags & PF_FLAG_ENLARGE) {
         if ((e_ = dalloc(F, &p, kBadCap * sizeof(unsigned long long) + 256, F->allocs)) != hipSuccess)
@@ -1040,7 +1083,9 @@ int pf_refactor(pf_factor_t F, void *stream)
 {
     if (!F) return -1;
     hipStream_t s = stream ? (hipStream_t)stream : F->stream;
-    return launch_factor_levels(F, s) == hipSuccess ? 0 : PF_EHIP;
+    if (launch_factor_levels(F, s) != hipSuccess) return PF_EHIP;
+    F->factors_stale = false;
+    return 0;
 }
 
 int pf_profile_enable(pf_factor_t F, int enable)
@@ -1155,8 +1200,13 @@ extern "C" {
 int pf_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x, int64_t ldx,
              void *stream, pf_info *info)
 {
-    return solve_call(F, nrhs, f, ldf, x, ldx, stream, info,
-                      [&](hipStream_t s) { return run_solve(F, nrhs, f, ldf, x, ldx, s); });
+    return solve_call(F, nrhs, f, ldf, x, ldx, stream, info, [&](hipStream_t s) {
+        if (F->factors_stale) {   // the last factor-and-solve left no factors behind
+            if (launch_factor_levels(F, s) != hipSuccess) return (int)PF_EHIP;
+            F->factors_stale = false;
+        }
+        return run_solve(F, nrhs, f, ldf, x, ldx, s);
+    });
 }
 
 int pf_factor_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, double *x,
@@ -1171,6 +1221,7 @@ int pf_factor_solve(pf_factor_t F, int32_t nrhs, const double *f, int64_t ldf, d
         return pf_refactor(F, stream);
     }
     return solve_call(F, nrhs, f, ldf, x, ldx, stream, info, [&](hipStream_t s) {
+        if (F->tri_cr && nrhs == 1) return run_tri_cr(F, f, x, s);
         if (fused_ok(F, nrhs)) return run_factor_solve(F, nrhs, f, ldf, x, ldx, s);
         if (launch_factor_levels(F, s) != hipSuccess) return (int)PF_EHIP;
         return run_solve(F, nrhs, f, ldf, x, ldx, s);
@@ -1306,6 +1357,7 @@ int factor_solve_in(const pf_matrix *A, const pf_opts *opts, char *base, size_t 
         return info->status;
     }
     return solve_call(F, nrhs, f, ldf, x, ldx, (void *)s, info, [&](hipStream_t st) {
+        if (F->tri_cr && nrhs == 1) return run_tri_cr(F, f, x, st);
         if (fused_ok(F, nrhs)) return run_factor_solve(F, nrhs, f, ldf, x, ldx, st);
         if (launch_factor_levels(F, st) != hipSuccess) return (int)PF_EHIP;
         return run_solve(F, nrhs, f, ldf, x, ldx, st);

@@ -36,4 +36,15 @@ hipError_t launch_tri_fwd(const SolveArgs &a, hipStream_t s);
 // side, FP64 factors
 hipError_t launch_tri_bwd(const SolveArgs &a, hipStream_t s);
 
+// A whole scalar tridiagonal system (nb rows, p partitions) in one launch of
+// one workgroup (kernels_tri_cr.hip): local cyclic reduction of the
+// partitions, parallel cyclic reduction of the reduced system across a
+// wave, back substitution; one right-hand side, FP64, no pivoting.
+constexpr int kTriCrMaxRows = 4096;   // rows in LDS (4 words each)
+constexpr int kTriCrMaxParts = 64;    // reduced system: one wave's lanes
+bool tri_cr_fits(int64_t nb, int64_t p);
+hipError_t launch_tri_cr_whole(int64_t nb, int64_t p, const double *D, const double *Lo,
+                               const double *Up, const double *f, double *x,
+                               unsigned long long *status, hipStream_t s);
+
 }  // namespace pf

@@ -23,6 +23,12 @@ def _say(*a):
     print(*a, flush=True)
 
 
+def cr_eligible(nb, p):
+    """Whether pf_factor_solve with one right-hand side takes the one-launch
+    local cyclic reduction (systems that fit one workgroup's LDS)."""
+    return 2 <= nb <= 4096 and 1 <= p <= 64 and p <= (nb + 1) // 2
+
+
 def _run(s, f, opts, split):
     import torch
     A, keep = G.to_device(s)
@@ -62,7 +68,11 @@ def test_tridiag_equals_segments(nb, p, br, split):
     assert levels == levs
     if p:
         assert levels[0][2] == p
-    assert np.array_equal(x, xs), np.abs(x - xs).max()
+    if not split and cr_eligible(nb, levels[0][2]):
+        # one launch of local cyclic reduction: another elimination order
+        assert np.abs(x - xs).max() <= 1e-13 * np.abs(xs).max()
+    else:
+        assert np.array_equal(x, xs), np.abs(x - xs).max()
     G.check(s, x[0], tag=f"tridiag nb={nb} p={p} br={br}")
 
 
