@@ -457,15 +457,20 @@ int pf_ivp_solve(int32_t m, const double *L, double t0, double T, int64_t p, int
  * ones that fit go ahead -- and run concurrently on the server's streams;
  * least recently used kept factors that no pending request needs are
  * evicted to make room.  Scheduling happens inside submit / poll / wait /
- * stats; only pf_server_wait blocks.  FP64 only (the refinement loop of
- * PF_FP32_IR synchronizes).  Not thread-safe: one host thread drives a
- * server. */
+ * stats; only pf_server_wait blocks.  PF_FP64 or PF_FP32_IR: a refined
+ * request queues its FP32 solve and first residual at admission, and each
+ * poll whose residual norms have arrived (pinned host words behind an event)
+ * queues the next correction or ends the request -- the same steps, tests
+ * and kernels as pf_solve's refinement, without a host wait.  Requests on
+ * one kept factor share its residual workspace, so a refined request on it
+ * runs only after the one before has finished refining.  Not thread-safe:
+ * one host thread drives a server. */
 typedef struct pf_server_s *pf_server_t;
 
 typedef struct {
-    pf_matrix A;        /* device arrays, valid until the request completes (and while
-                           a kept factor may be used: the refinement-free solve does
-                           not read A, but a factor kept with keep = 1 points to it) */
+    pf_matrix A;        /* device arrays, valid until the request completes, and while
+                           a factor kept with keep = 1 may be used (it points to
+                           them; PF_FP32_IR repeats read them for the residual) */
     int32_t nrhs;       /* >= 1                                                */
     int32_t keep;       /* 1: keep the factor resident for later requests     */
     const double *f;    /* device, n x nrhs, ld ldf                            */
@@ -490,7 +495,8 @@ typedef struct {
 
 /* budget_bytes: device memory the server may hold; max_inflight: running
  * requests at once (0 = 8); nstreams: concurrent streams (0 = 4, default
- * priority).  opts: as for pf_factor (prec must be PF_FP64). */
+ * priority).  opts: as for pf_factor (prec PF_FP64 or PF_FP32_IR; -2 for
+ * another). */
 int pf_server_create(size_t budget_bytes, const pf_opts *opts, int32_t max_inflight,
                      int32_t nstreams, pf_server_t *out);
 /* Queue a request; returns its ticket.  PF_ENOMEM if it can never fit. */

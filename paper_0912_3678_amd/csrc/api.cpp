@@ -710,19 +710,26 @@ double bits_to_double(unsigned long long b)
 }
 
 // eta per right-hand side from the norms buffer; returns the max over columns.
-int compute_eta(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const double *x,
-                int64_t ldx, double *r, int64_t ldr, hipStream_t s, double *eta_out)
+// The residual r = f - A x with its norms, and ||A||, queued on s into the
+// host words h (3 nrhs + 1: per column ||r||, ||x||, ||f||, then ||A||).
+int queue_residual_norms(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const double *x,
+                         int64_t ldx, double *r, int64_t ldr, hipStream_t s,
+                         unsigned long long *h)
 {
     const pf_matrix &A = F->A;
     HIPCHK(launch_fill_u64(F->d_norms, 3 * nrhs, 0ull, s));
     HIPCHK(launch_residual(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, nrhs, f, ldf, x, ldx, r, ldr,
                            F->d_norms, s));
-    std::vector<unsigned long long> h(3 * nrhs + 1);
-    HIPCHK(hipMemcpyAsync(h.data(), F->d_norms, 3 * nrhs * sizeof(unsigned long long),
+    HIPCHK(hipMemcpyAsync(h, F->d_norms, 3 * nrhs * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(h.data() + 3 * nrhs, F->d_norm, sizeof(unsigned long long),
+    HIPCHK(hipMemcpyAsync(h + 3 * nrhs, F->d_norm, sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    return 0;
+}
+
+// eta (max over columns) from the words queue_residual_norms filled
+double eta_of(const unsigned long long *h, int nrhs)
+{
     const double na = bits_to_double(h[3 * nrhs]);
     double worst = 0.0;
     for (int c = 0; c < nrhs; ++c) {
@@ -733,7 +740,17 @@ int compute_eta(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const do
         if (std::isnan(e)) e = INFINITY;
         worst = std::max(worst, e);
     }
-    *eta_out = worst;
+    return worst;
+}
+
+int compute_eta(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const double *x,
+                int64_t ldx, double *r, int64_t ldr, hipStream_t s, double *eta_out)
+{
+    std::vector<unsigned long long> h(3 * nrhs + 1);
+    const int rc = queue_residual_norms(F, nrhs, f, ldf, x, ldx, r, ldr, s, h.data());
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    *eta_out = eta_of(h.data(), nrhs);
     return 0;
 }
 
@@ -1297,6 +1314,37 @@ int factor_new_solve(const pf_matrix *A, const pf_opts *opts, hipStream_t s, int
 }
 
 void note_hip_error(hipError_t e) { g_last_hip = (int)e; }
+
+// Refinement steps for a caller that must not wait (the request scheduler):
+// the same kernels, in the same order, as the refinement loop of solve_call.
+int ir_queue_residual(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const double *x,
+                      int64_t ldx, hipStream_t s, unsigned long long *host)
+{
+    const int64_t n = F->nb * F->m;
+    return queue_residual_norms(F, nrhs, f, ldf, x, ldx, F->wsR, n, s, host);
+}
+int ir_queue_correction(pf_factor_s *F, int nrhs, double *x, int64_t ldx, hipStream_t s)
+{
+    const int64_t n = F->nb * F->m;
+    const int rc = run_solve(F, nrhs, F->wsR, n, F->wsD, n, s);
+    if (rc) return rc;
+    HIPCHK(launch_axpy(n, nrhs, F->wsD, n, x, ldx, s));
+    return 0;
+}
+double ir_eta(const unsigned long long *host, int nrhs) { return eta_of(host, nrhs); }
+const pf_opts &handle_opts(const pf_factor_s *F) { return F->opts; }
+// a solve with stored factors and no refinement, queued on s
+int solve_queued(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x, int64_t ldx,
+                 hipStream_t s)
+{
+    int rc = ensure_workspace(F, nrhs);
+    if (rc) return rc;
+    if (F->factors_stale) {
+        if (launch_factor_levels(F, s) != hipSuccess) return PF_EHIP;
+        F->factors_stale = false;
+    }
+    return run_solve(F, nrhs, f, ldf, x, ldx, s);
+}
 
 // Factor-and-solve (pf_factor followed by pf_factor_solve, and the same
 // kernels) with every device byte of the handle -- factors, reduced systems,

@@ -218,6 +218,17 @@ int factor_solve_in(const pf_matrix *A, const pf_opts *opts, char *base, size_t 
                     const double *f, int64_t ldf, double *x, int64_t ldx, hipStream_t s,
                     pf_info *info);
 void note_hip_error(hipError_t e);
+// Refinement (PF_FP32_IR) as separate queued steps for the request
+// scheduler, in the order of pf_solve's loop: the residual and its norms into
+// host words (3 nrhs + 1, pinned), eta from them, a correction solve with
+// x += d; and a solve with stored factors without refinement.
+int ir_queue_residual(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const double *x,
+                      int64_t ldx, hipStream_t s, unsigned long long *host);
+int ir_queue_correction(pf_factor_s *F, int nrhs, double *x, int64_t ldx, hipStream_t s);
+double ir_eta(const unsigned long long *host, int nrhs);
+const pf_opts &handle_opts(const pf_factor_s *F);
+int solve_queued(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, double *x, int64_t ldx,
+                 hipStream_t s);
 int status_nosync(pf_factor_s *F, pf_info *info);
 
 // Options of a PF_FLAG_AUTOTUNE factorization (tune.cpp): the cached choice

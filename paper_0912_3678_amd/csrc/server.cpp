@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -49,6 +50,14 @@ struct Ticket {
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
     hipEvent_t ev_ready = nullptr;   // inputs ready (recorded on req.after at submission)
     pf_factor_t F = nullptr;   // the factor this request ran on
+    // PF_FP32_IR: refinement driven from the scheduler's polling -- each
+    // step's residual norms arrive in pinned host words (ev_norms), and the
+    // next step is queued only when they say so; no host wait
+    bool ir = false;
+    int iters = 0, slow = 0;
+    double eta = INFINITY, prev = INFINITY;
+    unsigned long long *hnorms = nullptr;   // 3 nrhs + 1 pinned words
+    hipEvent_t ev_norms = nullptr;
 };
 
 struct Resident {
@@ -59,6 +68,8 @@ struct Resident {
     double last_use = 0;
     bool released = false;
     int failed = 0;            // status of a factoring request that could not start
+    bool refining = false;     // a request on it is between refinement steps: the
+                               // residual and correction workspace is taken
 };
 
 }  // namespace
@@ -129,16 +140,66 @@ bool make_room(pf_server_s *S, size_t need)
     return true;
 }
 
+// One refinement decision for a request whose residual norms have arrived:
+// done (ev_done recorded behind the work so far), or the next correction
+// and residual queued.  The same test and order as pf_solve's loop.
+void refine_step(pf_server_s *S, int64_t id, Ticket &T)
+{
+    hipStream_t s = S->streams[T.stream];
+    const pf_request &r = T.req;
+    const pf_opts &o = handle_opts(T.F);
+    T.eta = ir_eta(T.hnorms, r.nrhs);
+    int status = PF_OK;
+    bool done = true;
+    if (T.eta <= o.tol) {
+    } else if (T.iters >= o.max_refine) {
+        status = PF_ENOCONV;
+    } else {
+        T.slow = (T.eta > 0.5 * T.prev) ? T.slow + 1 : 0;
+        if (T.slow >= 2) status = PF_ENOCONV;
+        else done = false;
+    }
+    if (!done) {
+        T.prev = T.eta;
+        int rc = ir_queue_correction(T.F, r.nrhs, r.x, r.ldx, s);
+        if (!rc) rc = ir_queue_residual(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s, T.hnorms);
+        if (!rc && hipEventRecord(T.ev_norms, s) != hipSuccess) rc = PF_EHIP;
+        ++T.iters;
+        if (!rc) return;
+        status = rc;
+    }
+    T.ir = false;
+    T.info.status = status;   // kept; the device status word is read at retirement
+    hipEventRecord(T.ev_done, s);
+    const int64_t home = r.factor >= 0 ? r.factor : (r.keep ? id : -1);
+    if (home >= 0) S->resident[home].refining = false;
+}
+
 void retire(pf_server_s *S)
 {
     for (auto &kv : S->tickets) {
         Ticket &T = kv.second;
         if (T.state != 1) continue;
+        if (T.ir) {
+            if (hipEventQuery(T.ev_norms) != hipSuccess) continue;
+            refine_step(S, kv.first, T);
+            continue;   // retired once ev_done has fired, at a later poll
+        }
         if (hipEventQuery(T.ev_done) != hipSuccess) continue;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, S->epoch, T.ev_done) == hipSuccess) T.t_done = S->epoch_ms + ms;
         if (hipEventElapsedTime(&ms, S->epoch, T.ev_start) == hipSuccess) T.t_start = S->epoch_ms + ms;
-        status_nosync(T.F, &T.info);
+        {
+            const int ir_status = T.info.status;
+            status_nosync(T.F, &T.info);
+            if (T.hnorms) {   // a refined request: its iterations, eta and outcome
+                T.info.refine_iters = T.iters;
+                T.info.eta = T.eta;
+                if (T.info.status == PF_OK) T.info.status = ir_status;
+                hipHostFree(T.hnorms);
+                T.hnorms = nullptr;
+            }
+        }
         T.state = 2;
         --S->inflight;
         --S->load[T.stream];
@@ -172,8 +233,27 @@ void retire(pf_server_s *S)
         hipEventDestroy(T.ev_start);
         hipEventDestroy(T.ev_done);
         if (T.ev_ready) hipEventDestroy(T.ev_ready);
-        T.ev_start = T.ev_done = T.ev_ready = nullptr;
+        if (T.ev_norms) hipEventDestroy(T.ev_norms);
+        T.ev_start = T.ev_done = T.ev_ready = T.ev_norms = nullptr;
     }
+}
+
+// PF_FP32_IR: queue the first residual behind the FP32 solve; the
+// refinement continues from the polling (refine_step)
+int start_refinement(pf_server_s *S, int64_t id, Ticket &T, hipStream_t s)
+{
+    const pf_request &r = T.req;
+    if (hipHostMalloc((void **)&T.hnorms, (3 * (size_t)r.nrhs + 1) * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess)
+        return PF_EHIP;
+    if (hipEventCreateWithFlags(&T.ev_norms, hipEventDisableTiming) != hipSuccess) return PF_EHIP;
+    const int rc = ir_queue_residual(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s, T.hnorms);
+    if (rc) return rc;
+    if (hipEventRecord(T.ev_norms, s) != hipSuccess) return PF_EHIP;
+    T.ir = true;
+    if (r.factor >= 0) S->resident[r.factor].refining = true;
+    else if (r.keep) S->resident[id].refining = true;
+    return 0;
 }
 
 int launch(pf_server_s *S, int64_t id, Ticket &T)
@@ -195,7 +275,7 @@ int launch(pf_server_s *S, int64_t id, Ticket &T)
     int rc;
     if (r.factor >= 0) {
         T.F = S->resident[r.factor].F;
-        rc = pf_solve(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s, nullptr);
+        rc = solve_queued(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s);
     } else {
         double setup = 0;
         rc = factor_new_solve(&r.A, &S->opts, s, r.nrhs, r.f, r.ldf, r.x, r.ldx, &T.F, &S->al,
@@ -204,10 +284,17 @@ int launch(pf_server_s *S, int64_t id, Ticket &T)
         S->setup_ms_total += setup;
     }
     if (rc) return rc;
+    if (S->opts.prec == PF_FP32_IR && (rc = start_refinement(S, id, T, s))) {
+        if (r.factor < 0) {
+            destroy_async(T.F);
+            T.F = nullptr;
+        }
+        return rc;
+    }
     const double dt = now_ms() - t0;
     S->launch_ms_max = std::max(S->launch_ms_max, dt);
     S->launch_ms_total += dt;
-    hipEventRecord(T.ev_done, s);
+    if (!T.ir) hipEventRecord(T.ev_done, s);
     T.stream = si;
     T.state = 1;
     ++S->inflight;
@@ -237,7 +324,11 @@ void fail(pf_server_s *S, Ticket &T, int rc)
     if (T.ev_start) hipEventDestroy(T.ev_start);
     if (T.ev_done) hipEventDestroy(T.ev_done);
     if (T.ev_ready) hipEventDestroy(T.ev_ready);
-    T.ev_start = T.ev_done = T.ev_ready = nullptr;
+    if (T.ev_norms) hipEventDestroy(T.ev_norms);
+    if (T.hnorms) hipHostFree(T.hnorms);
+    T.ev_start = T.ev_done = T.ev_ready = T.ev_norms = nullptr;
+    T.hnorms = nullptr;
+    T.ir = false;
     (void)S;
 }
 
@@ -257,8 +348,8 @@ void admit(pf_server_s *S)
                 fail(S, T, R.failed);
                 continue;
             }
-            if (!R.F) {                      // its factor's request has not started
-                ++q;
+            if (!R.F || R.refining) {        // its factor's request has not started, or
+                ++q;                         // another request is refining on its workspace
                 continue;
             }
         }
@@ -306,7 +397,7 @@ int pf_server_create(size_t budget_bytes, const pf_opts *opts, int32_t max_infli
     S->budget = budget_bytes;
     if (opts) S->opts = *opts;
     S->opts.flags &= ~PF_FLAG_AUTOTUNE;
-    if (S->opts.prec != PF_FP64) {   // the refinement loop synchronizes: not in a server
+    if (S->opts.prec != PF_FP64 && S->opts.prec != PF_FP32_IR) {
         delete S;
         return -2;
     }
@@ -410,12 +501,15 @@ int pf_server_wait(pf_server_t S, int64_t ticket, pf_info *info)
         Ticket &T = it->second;
         if (T.state == 2) break;
         if (T.state == 1) {
-            if (hipEventSynchronize(T.ev_done) != hipSuccess) return PF_EHIP;
+            if (hipEventSynchronize(T.ir ? T.ev_norms : T.ev_done) != hipSuccess) return PF_EHIP;
         } else {
             // queued: wait for the oldest running request to make room
             hipEvent_t ev = nullptr;
             for (auto &kv : S->tickets)
-                if (kv.second.state == 1) { ev = kv.second.ev_done; break; }
+                if (kv.second.state == 1) {
+                    ev = kv.second.ir ? kv.second.ev_norms : kv.second.ev_done;
+                    break;
+                }
             if (!ev) return PF_ENOMEM;    // nothing running and still not admitted
             if (hipEventSynchronize(ev) != hipSuccess) return PF_EHIP;
         }
@@ -493,6 +587,8 @@ void pf_server_destroy(pf_server_t S)
         if (T.ev_start) hipEventDestroy(T.ev_start);
         if (T.ev_done) hipEventDestroy(T.ev_done);
         if (T.ev_ready) hipEventDestroy(T.ev_ready);
+        if (T.ev_norms) hipEventDestroy(T.ev_norms);
+        if (T.hnorms) hipHostFree(T.hnorms);
         if (T.state == 2 && T.req.factor < 0 && !T.req.keep) continue;   // freed at retire
         if (T.state == 1 && T.req.factor < 0 && !T.req.keep) destroy_async(T.F);
     }

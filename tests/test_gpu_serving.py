@@ -158,3 +158,68 @@ def test_autotune_choice_solves(kind, m, nb):
     assert levels2 == levels
     assert np.array_equal(x, x2)
     del keep
+
+
+def test_serving_fp32_refined_mix_equals_alone():
+    """PF_FP32_IR requests: the refinement runs from the scheduler's polling,
+    step for step what pf_solve's loop does, so each solution equals the
+    same refined solve made alone bit for bit, with its iteration count and
+    eta; repeats on one kept factor take turns on its residual workspace."""
+    import torch
+    opts = pf.make_opts(prec=pf.PF_FP32_IR)
+    specs = [(8, 3000, 1), (16, 500, 2), (4, 2000, 1), (3, 900, 1), (32, 60, 1), (8, 1500, 3)]
+    systems = []
+    for i, (m, nb, k) in enumerate(specs):
+        s = wl.random_btri(nb, m, seed=8100 + i)
+        A, keep = G.to_device(s)
+        systems.append((s, A, keep, k))
+    sizes = [pf.pf_factor_bytes(A, opts) + pf.pf_solve_bytes_per_rhs(A, opts) * k
+             for _, A, _, k in systems]
+    S = pf.Server(int(max(sizes) * 3), opts, max_inflight=4, nstreams=3)
+
+    def alone(A, fd, repeat):
+        x = torch.full_like(fd, np.nan)
+        F = pf.pf_factor(A, opts)
+        try:
+            info = (pf.pf_solve if repeat else pf.pf_factor_solve)(F, fd, x)
+        finally:
+            pf.pf_destroy(F)
+        return x.cpu().numpy(), info
+
+    try:
+        reqs = []
+        for i, (s, A, keep, k) in enumerate(systems):
+            f, fd = _rhs(s.n, k, 300 + i)
+            x = torch.full_like(fd, np.nan)
+            t = S.submit(A, fd, x, keep=(i % 2 == 0))
+            reqs.append((t, i, f, fd, x, False))
+        # three repeats on one kept factor, queued behind each other's
+        # refinement, and one on another
+        for j, i in enumerate([0, 0, 2, 0]):
+            s, A, keep, k = systems[i]
+            f, fd = _rhs(s.n, k, 700 + j)
+            x = torch.full_like(fd, np.nan)
+            t = S.submit(A, fd, x, factor=reqs[i][0])
+            reqs.append((t, i, f, fd, x, True))
+        infos = {}
+        for t, *_ in reqs:
+            info = S.wait(t)
+            assert info.status == 0, (t, info.as_dict())
+            infos[t] = info
+        st = S.stats()
+        _say("stats at end", st)
+        assert st["completed"] == len(reqs) and st["inflight"] == 0
+        for t, i, f, fd, x, repeat in reqs:
+            s, A, keep, k = systems[i]
+            xs = x.cpu().numpy()
+            xa, ia = alone(A, fd, repeat)
+            got = infos[t]
+            _say(f"ticket {t} m={s.m} nb={s.nb} repeat={repeat}: iters {got.refine_iters} "
+                 f"eta {got.eta:.3e} (alone {ia.refine_iters}, {ia.eta:.3e})")
+            assert got.refine_iters == ia.refine_iters and got.eta == ia.eta, t
+            assert got.refine_iters >= 1 and got.eta <= 1e-12
+            assert np.array_equal(xs, xa), f"ticket {t} (system {i}): mix != alone"
+            G.check(s, xs.T, f=f, tag=f"fp32 refined ticket {t} m={s.m} nb={s.nb}")
+    finally:
+        S.destroy()
+    torch.cuda.synchronize()
