@@ -837,6 +837,11 @@ def run_batch(args):
             its = [i.refine_iters for i in infos]
             r["refine_iters"] = {str(v): its.count(v) for v in sorted(set(its))}
         res[prec] = r
+    # give the batch's device memory back before the serving stream, whose
+    # server may hold up to its budget (250 GB) of the 288 GB
+    del mats, keep, fs, xs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     main = res["fp64"] if "fp64" in res else res[precs[0]]
     mprec = "fp64" if "fp64" in res else precs[0]
     # dominant grouped launch of the main run, its roofline by the method's

@@ -349,6 +349,20 @@ size_t pf_solve_bytes_per_rhs(const pf_matrix *A, const pf_opts *opts);
  * factorization (zero pivots). */
 int pf_sync_status(pf_factor_t F, pf_info *info);
 
+/* The FP64 residual of the refinement (PF_FP32_IR) and of PF_FLAG_ETA, and
+ * the norms of the normwise backward error eta = ||r|| / (||A|| ||x|| + ||f||)
+ * (infinity norms) those tests take: r = f - A x for nrhs columns, with A of
+ * eq. (syst)'s block forms as in pf_matrix (device arrays).  f, x: device,
+ * n x nrhs, ld ldf / ldx >= n = m nb; r: device, n x nrhs, ld ldr >= n, or
+ * NULL for the norms only.  norms: host, 3 nrhs + 1 doubles, filled on
+ * return: ||r_c||, ||x_c||, ||f_c|| for column c at 3c .. 3c+2, then ||A||.
+ * Queued on `stream` (NULL = the default stream) behind its work, with a
+ * small stream-ordered scratch of 3 nrhs + 1 words from the allocator;
+ * synchronizes `stream`.  Returns 0, -k for invalid argument k, PF_ENOMEM or
+ * PF_EHIP. */
+int pf_residual(const pf_matrix *A, int32_t nrhs, const double *f, int64_t ldf, const double *x,
+                int64_t ldx, double *r, int64_t ldr, void *stream, double *norms);
+
 /* Release the factor's device memory (synchronizes its stream first). */
 void pf_destroy(pf_factor_t F);
 

@@ -495,17 +495,6 @@ hipError_t pad_matrix(pf_factor_s *F, hipStream_t s)
     return e;
 }
 
-// ||A||_inf for the refinement loop and eta, when the options ask for them.
-hipError_t launch_norm(pf_factor_s *F, hipStream_t s)
-{
-    if (F->opts.prec != PF_FP32_IR && !(F->opts.flags & PF_FLAG_ETA)) return hipSuccess;
-    const pf_matrix *A = &F->A;
-    hipError_t e = launch_fill_u64(F->d_norm, 1, 0ull, s);
-    if (e == hipSuccess)
-        e = launch_norminf(A->kind, A->m, A->nb, A->D, A->Lo, A->Up, A->C, F->d_norm, s);
-    return e;
-}
-
 hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
 {
     F->prof_fac_n = 0;
@@ -530,7 +519,7 @@ hipError_t launch_factor_levels(pf_factor_s *F, hipStream_t s)
         });
         if (e != hipSuccess) return e;
     }
-    return launch_norm(F, s);
+    return hipSuccess;
 }
 
 int ensure_workspace(pf_factor_s *F, int nrhs)
@@ -687,7 +676,6 @@ int run_factor_solve(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, dou
             return launch_seg_factor(lv.kind, M, lv.seg, lv.f32, a, &args[l], s);
         }));
     }
-    HIPCHK(launch_norm(F, s));
     for (size_t l = L; l-- > 0;) {
         const Level &lv = F->lv[l];
         HIPCHK(prof_launch(F, false, 2, (int)l, s, [&] {
@@ -718,8 +706,9 @@ int queue_residual_norms(pf_factor_s *F, int nrhs, const double *f, int64_t ldf,
 {
     const pf_matrix &A = F->A;
     HIPCHK(launch_fill_u64(F->d_norms, 3 * nrhs, 0ull, s));
+    HIPCHK(launch_fill_u64(F->d_norm, 1, 0ull, s));
     HIPCHK(launch_residual(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, nrhs, f, ldf, x, ldx, r, ldr,
-                           F->d_norms, s));
+                           F->d_norms, F->d_norm, s));
     HIPCHK(hipMemcpyAsync(h, F->d_norms, 3 * nrhs * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(h + 3 * nrhs, F->d_norm, sizeof(unsigned long long),
@@ -1130,6 +1119,41 @@ int pf_profile_read(pf_factor_t F, int32_t max, int32_t *phase, int32_t *level, 
         }
     }
     return n;
+}
+
+int pf_residual(const pf_matrix *A, int32_t nrhs, const double *f, int64_t ldf, const double *x,
+                int64_t ldx, double *r, int64_t ldr, void *stream, double *norms)
+{
+    int rc = check_matrix(A);
+    if (rc) return rc < 0 ? -1 : rc;
+    const int64_t n = A->nb * A->m;
+    if (nrhs < 0) return -2;
+    if (nrhs > 0 && !f) return -3;
+    if (ldf < n) return -4;
+    if (nrhs > 0 && !x) return -5;
+    if (ldx < n) return -6;
+    if (r && ldr < n) return -8;
+    if (!norms) return -10;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t words = 3 * (size_t)nrhs + 1;
+    unsigned long long *d = nullptr;
+    hipError_t e = dev_alloc(g_allocator, (void **)&d, words * sizeof *d, s);
+    if (e != hipSuccess) return alloc_status(e);
+    std::vector<unsigned long long> h(words);
+    e = launch_fill_u64(d, (int64_t)words, 0ull, s);
+    if (e == hipSuccess)
+        e = launch_residual(A->kind, A->m, A->nb, A->D, A->Lo, A->Up, A->C, nrhs, f, ldf, x, ldx,
+                            r, r ? ldr : n, d, d + 3 * nrhs, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), d, words * sizeof *d, hipMemcpyDeviceToHost, s);
+    dev_free(g_allocator, d, words * sizeof *d, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return PF_EHIP;
+    }
+    for (size_t i = 0; i < words; ++i) norms[i] = bits_to_double(h[i]);
+    return 0;
 }
 
 int pf_sync_status(pf_factor_t F, pf_info *info)
@@ -1840,12 +1864,6 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s, BatchTimes *T = nullptr)
                                                    B->d_lwork + bl.work, bl.nwg, s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
                                                B->d_lwork + bl.work, bl.nwg, s); });
-    if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA))
-        for (int i = 0; i < B->nsys; ++i) {
-            const pf_matrix &A = B->all[i]->A;
-            if (e == hipSuccess)
-                e = launch_norminf(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, B->d_words + B->nsys + i, s);
-        }
     return e;
 }
 
@@ -1905,8 +1923,8 @@ void batch_free(pf_batch_s *B)
 // FP64 refinement of every system of the batch (PF_FP32_IR): residuals and
 // norms for all systems, one synchronization, then one batched correction
 // solve for all systems, until every eta <= tol or a system stagnates.
-int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::vector<int> &iters,
-                 std::vector<int> &status)
+int batch_refine(pf_batch_s *B, hipStream_t s, bool refine, std::vector<double> &eta,
+                 std::vector<int> &iters, std::vector<int> &status)
 {
     const int ns = B->nsys;
     eta.assign(ns, INFINITY);
@@ -1918,16 +1936,18 @@ int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::ve
     size_t slots = 0;
     for (int i = 0; i < ns; ++i) slots += 3 * (size_t)std::max(B->nrhs[i], 1);
     std::vector<unsigned long long> h(2 * (size_t)ns + slots);
-    HIPCHK(launch_fill_u64(B->d_words + 2 * ns, (int64_t)slots, 0ull, s));
-    for (;;) {
+    // ||A||_inf (zeroed with the status words when the graph starts) comes
+    // with the first residual of each system
+    for (bool first = true;; first = false) {
+        HIPCHK(launch_fill_u64(B->d_words + 2 * ns, (int64_t)slots, 0ull, s));
         for (int i = 0; i < ns; ++i) {
             pf_factor_s *F = B->all[i];
             const pf_matrix &A = F->A;
             const int64_t n = A.nb * A.m;
             if (done[i] || B->nrhs[i] == 0) continue;
-            HIPCHK(launch_fill_u64(B->norms[i], 3 * B->nrhs[i], 0ull, s));
             HIPCHK(launch_residual(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, B->nrhs[i], B->f[i],
-                                   B->ldf[i], B->x[i], B->ldx[i], F->wsR, n, B->norms[i], s));
+                                   B->ldf[i], B->x[i], B->ldx[i], refine ? F->wsR : nullptr, n,
+                                   B->norms[i], first ? B->d_words + ns + i : nullptr, s));
         }
         HIPCHK(hipMemcpyAsync(h.data(), B->d_words, h.size() * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s));
@@ -1950,6 +1970,7 @@ int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::ve
                 w = std::max(w, e);
             }
             eta[i] = w;
+            if (!refine) continue;   // eta only (FP64 with PF_FLAG_ETA)
             if (w <= B->opts.tol) { done[i] = 1; continue; }
             if (iters[i] >= B->opts.max_refine) { done[i] = 1; status[i] = PF_ENOCONV; continue; }
             slow[i] = (w > 0.5 * prev[i]) ? slow[i] + 1 : 0;
@@ -1957,7 +1978,7 @@ int batch_refine(pf_batch_s *B, hipStream_t s, std::vector<double> &eta, std::ve
             prev[i] = w;
             all = false;
         }
-        if (all) break;
+        if (all || !refine) break;
         HIPCHK(issue_solve(B, B->corr, true, s));
         for (int i = 0; i < ns; ++i) {
             if (done[i]) continue;
@@ -2148,8 +2169,8 @@ int pf_batch_run(pf_batch_t B, void *stream, pf_info *info)
     std::vector<double> eta;
     std::vector<int> iters, st;
     int worst = 0;
-    if (B->opts.prec == PF_FP32_IR) {
-        const int rc = batch_refine(B, B->cap, eta, iters, st);
+    if (B->opts.prec == PF_FP32_IR || (B->opts.flags & PF_FLAG_ETA)) {
+        const int rc = batch_refine(B, B->cap, B->opts.prec == PF_FP32_IR, eta, iters, st);
         if (rc) return rc;
     }
     if (hipEventRecord(B->ev, B->cap) != hipSuccess) return PF_EHIP;

@@ -162,16 +162,14 @@ hipError_t launch_pad_blocks(int m, int M, int64_t count, const double *src, dou
 hipError_t launch_pad_rhs(int m, int M, int64_t nb, int32_t nrhs, const double *src,
                           int64_t lds, double *dst, int64_t ldd, bool to_padded,
                           hipStream_t s);
-// r = f - A x (FP64) with the max-abs norms of r, x, f per right-hand side
-// accumulated into norms[3*c + {0,1,2}] (as ordered uint64 bit patterns).
+// r = f - A x (FP64; r may be null: norms only) with the max-abs norms of r,
+// x, f per right-hand side accumulated into norms[3*c + {0,1,2}], and, when
+// normA is not null, ||A||_inf into *normA (ordered uint64 bit patterns of
+// non-negative doubles; the caller zeroes them).
 hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const double *Lo,
                            const double *Up, const double *C, int32_t nrhs, const double *f,
                            int64_t ldf, const double *x, int64_t ldx, double *r, int64_t ldr,
-                           unsigned long long *norms, hipStream_t s);
-// ||A||_inf into *out (uint64 bit pattern of a non-negative double; caller zeroes).
-hipError_t launch_norminf(int kind, int m, int64_t nb, const double *D, const double *Lo,
-                          const double *Up, const double *C, unsigned long long *out,
-                          hipStream_t s);
+                           unsigned long long *norms, unsigned long long *normA, hipStream_t s);
 // x += d
 hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, double *x,
                        int64_t ldx, hipStream_t s);

@@ -32,7 +32,7 @@ EXPORTED = [
     "pf_server_create", "pf_server_submit", "pf_server_poll", "pf_server_wait", "pf_server_times",
     "pf_server_release", "pf_server_stats", "pf_server_destroy",
     "pf_set_allocator", "pf_last_hip_error", "pf_factor_solve_static", "pf_batch_profile",
-    "pf_server_reserve",
+    "pf_server_reserve", "pf_residual",
 ]
 
 
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
         "pf_last_hip_error": (ctypes.c_int, []),
         "pf_factor_solve_static": (ctypes.c_int, [P(pf_matrix), P(pf_opts), i32, vp, i64, vp,
                                                   i64, vp, P(pf_info)]),
+        "pf_residual": (ctypes.c_int, [P(pf_matrix), i32, vp, i64, vp, i64, vp, i64, vp,
+                                       P(ctypes.c_double)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -255,6 +257,26 @@ def pf_factor_solve(F, f, x, nrhs=None, ldf=None, ldx=None, stream=None, want_in
     one call; arguments as pf_solve."""
     return _solve(load().pf_factor_solve, "pf_factor_solve", F, f, x, nrhs, ldf, ldx, stream,
                   want_info)
+
+
+def pf_residual(A: pf_matrix, f, x, r=None, nrhs=None, ldf=None, ldx=None, ldr=None,
+                stream=None):
+    """r = f - A x (FP64) into r (a device tensor like f, or None) and the
+    norms of eta: returns (norms per column as an (nrhs, 3) array of
+    ||r||, ||x||, ||f||, ||A||)."""
+    import numpy as np
+    if nrhs is None:
+        nrhs = 1 if f.dim() == 1 else f.shape[0]
+    n = f.shape[-1]
+    out = (ctypes.c_double * (3 * nrhs + 1))()
+    rc = load().pf_residual(ctypes.byref(A), nrhs, _ptr(f), n if ldf is None else ldf, _ptr(x),
+                            n if ldx is None else ldx, _ptr(r),
+                            (n if ldr is None else ldr) if r is not None else n,
+                            _stream(stream), out)
+    if rc != 0:
+        raise PFError(rc, "pf_residual")
+    v = np.frombuffer(out, dtype=np.float64).copy()
+    return v[:3 * nrhs].reshape(nrhs, 3), float(v[3 * nrhs])
 
 
 def pf_factor_solve_static(A: pf_matrix, f, x, opts: pf_opts | None = None, nrhs=None,
