@@ -1739,6 +1739,16 @@ struct pf_batch_s {
     int4 *d_lwork = nullptr;
     std::vector<BatchLaunch> flaunch;
     SolveSet sol, corr;                  // f -> x, and residual -> correction
+    // residual passes (PF_FP32_IR, PF_FLAG_ETA): one grouped launch per
+    // block size with one (m in 4, 8, 16, 32), per-system launches otherwise
+    struct ResGroup {
+        int m = 0, nwg = 0;
+        int4 *d_work = nullptr;
+    };
+    ResidualArgs *d_rtab = nullptr;
+    std::vector<ResGroup> rgroups;
+    std::vector<int> rsingle;
+    unsigned char *d_live = nullptr, *h_live = nullptr;   // systems still refining (h: pinned)
     std::vector<void *> own;             // table allocations
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1914,6 +1924,7 @@ void batch_free(pf_batch_s *B)
     for (auto *F : B->F)
         if (F) pf_destroy(F);
     for (void *p : B->own) hipFree(p);
+    if (B->h_live) hipHostFree(B->h_live);
     if (B->arena) arena_release(B->arena, B->cap ? B->cap : B->user);
     if (B->ev) hipEventDestroy(B->ev);
     if (B->cap) hipStreamDestroy(B->cap);
@@ -1940,11 +1951,17 @@ int batch_refine(pf_batch_s *B, hipStream_t s, bool refine, std::vector<double> 
     // with the first residual of each system
     for (bool first = true;; first = false) {
         HIPCHK(launch_fill_u64(B->d_words + 2 * ns, (int64_t)slots, 0ull, s));
-        for (int i = 0; i < ns; ++i) {
+        for (int i = 0; i < ns; ++i) B->h_live[i] = (!done[i] && B->nrhs[i] > 0) ? 1 : 0;
+        // pinned source: queued, not waited on (the sweep's synchronization
+        // below comes before the next change of h_live)
+        HIPCHK(hipMemcpyAsync(B->d_live, B->h_live, ns, hipMemcpyHostToDevice, s));
+        for (const auto &G : B->rgroups)
+            HIPCHK(launch_residual_batch(G.m, B->d_rtab, G.d_work, G.nwg, B->d_live, first, refine, s));
+        for (int i : B->rsingle) {
             pf_factor_s *F = B->all[i];
             const pf_matrix &A = F->A;
             const int64_t n = A.nb * A.m;
-            if (done[i] || B->nrhs[i] == 0) continue;
+            if (!B->h_live[i]) continue;
             HIPCHK(launch_residual(A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, B->nrhs[i], B->f[i],
                                    B->ldf[i], B->x[i], B->ldx[i], refine ? F->wsR : nullptr, n,
                                    B->norms[i], first ? B->d_words + ns + i : nullptr, s));
@@ -2130,6 +2147,47 @@ int batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const in
     if (o.prec == PF_FP32_IR &&
         (upload(B, ctab, &B->corr.d_tab) || upload(B, cwork, &B->corr.d_work)))
         return fail(PF_EHIP);
+    if (o.prec == PF_FP32_IR || (o.flags & PF_FLAG_ETA)) {
+        // residual tables: per system its operands; per block size with a
+        // grouped launch, work units of a few runs of steps
+        std::vector<ResidualArgs> rtab(nsys);
+        std::map<int, std::vector<int4>> rwork;
+        for (int i = 0; i < nsys; ++i) {
+            pf_factor_s *F = B->all[i];
+            const pf_matrix &A = F->A;
+            const int64_t n = A.nb * A.m;
+            rtab[i] = ResidualArgs{A.kind, A.m, A.nb, A.D, A.Lo, A.Up, A.C, nrhs[i], B->f[i],
+                                   B->ldf[i], B->x[i], B->ldx[i], F->wsR, n, B->norms[i],
+                                   B->d_words + nsys + i};
+            if (!residual_batched(A.m)) {
+                B->rsingle.push_back(i);
+                continue;
+            }
+            const int64_t steps = (n + residual_step_rows(A.m) - 1) / residual_step_rows(A.m);
+            const int per = residual_item_steps();
+            if (steps > INT32_MAX - per) {
+                B->rsingle.push_back(i);
+                continue;
+            }
+            const int chunks = (nrhs[i] + 63) / 64;
+            auto &w = rwork[A.m];
+            for (int c = 0; c < chunks; ++c)
+                for (int64_t t = 0; t < steps; t += per)
+                    w.push_back(int4{i, (int)t, (int)std::min<int64_t>(t + per, steps), c});
+        }
+        if (upload(B, rtab, &B->d_rtab)) return fail(PF_EHIP);
+        for (auto &kv : rwork) {
+            pf_batch_s::ResGroup G;
+            G.m = kv.first;
+            G.nwg = (int)kv.second.size();
+            if (upload(B, kv.second, &G.d_work)) return fail(PF_EHIP);
+            B->rgroups.push_back(G);
+        }
+        std::vector<unsigned char> live(nsys, 1);
+        if (upload(B, live, &B->d_live)) return fail(PF_EHIP);
+        if (hipHostMalloc((void **)&B->h_live, nsys, hipHostMallocDefault) != hipSuccess)
+            return fail(PF_EHIP);
+    }
     if (hipStreamSynchronize(us) != hipSuccess) return fail(PF_EHIP);
 
     // record factor + solve once; pf_batch_run replays it

@@ -383,7 +383,7 @@ __device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveA
 }
 
 template <bool ADD, typename V>
-__global__ __launch_bounds__(WG) void k_btri_mfma32(LevelArgs a)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(V) == 4 ? 2 : 1))) void k_btri_mfma32(LevelArgs a)
 {
     __shared__ __align__(16) V lds[2 * kM * kRS<V>];
     btri_mfmat_body<2, ADD, false, V>(a, SolveArgs{}, blockIdx.x, threadIdx.x, lds);
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(WG) void k_btri_mfma16(LevelArgs a, SolveArgs sv)
 }
 // batched: workgroup w serves table entry work[w].x, partition work[w].y
 template <bool ADD, typename V>
-__global__ __launch_bounds__(WG) void kb_btri_mfma32(const LevelArgs *tab, const int4 *work)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(V) == 4 ? 2 : 1))) void kb_btri_mfma32(const LevelArgs *tab, const int4 *work)
 {
     __shared__ __align__(16) V lds[2 * kM * kRS<V>];
     const int4 w = work[blockIdx.x];
@@ -577,24 +577,24 @@ __device__ __forceinline__ void bwdt_body(const SolveArgs &a, int64_t part, int 
 }
 
 template <int M, int KIND, int CT, bool ADD, typename V>
-__global__ __launch_bounds__(WG) void k_fwdt(SolveArgs a)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_fwdt(SolveArgs a)
 {
     fwdt_body<M, KIND, CT, ADD, V>(a, blockIdx.x, blockIdx.y, threadIdx.x);
 }
 template <int M, int KIND, int CT, typename V>
-__global__ __launch_bounds__(WG) void k_bwdt(SolveArgs a)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_bwdt(SolveArgs a)
 {
     bwdt_body<M, KIND, CT, V>(a, blockIdx.x, blockIdx.y, threadIdx.x);
 }
 template <int M, int KIND, int CT, bool ADD, typename V>
-__global__ __launch_bounds__(WG) void kb_fwdt(const SolveArgs *tab, const int4 *work)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void kb_fwdt(const SolveArgs *tab, const int4 *work)
 {
     const int4 w = work[blockIdx.x];
     const SolveArgs a = tab[w.x];
     fwdt_body<M, KIND, CT, ADD, V>(a, w.y, w.z, threadIdx.x);
 }
 template <int M, int KIND, int CT, typename V>
-__global__ __launch_bounds__(WG) void kb_bwdt(const SolveArgs *tab, const int4 *work)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void kb_bwdt(const SolveArgs *tab, const int4 *work)
 {
     const int4 w = work[blockIdx.x];
     const SolveArgs a = tab[w.x];

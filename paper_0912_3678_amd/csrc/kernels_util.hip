@@ -14,6 +14,17 @@ __device__ __forceinline__ unsigned long long dbits(double v)
     return (unsigned long long)__double_as_longlong(v);
 }
 
+// *p = max(*p, v) for ordered bit patterns of non-negative doubles, skipping
+// the atomic when the value already there is at least v: maxima only grow,
+// so a stale read can cost an atomic but never lose one, and the many
+// workgroups of a reduction that finish together mostly read instead of
+// contending for the same few words
+__device__ __forceinline__ void max_bits(unsigned long long *p, double v)
+{
+    const unsigned long long b = dbits(v);
+    if (b > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, b);
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
@@ -114,7 +125,7 @@ __global__ __launch_bounds__(256) void k_residual(int kind, int m_rt, int64_t nb
     __shared__ double sh[4];
     if (wantA) {   // uniform per workgroup
         const double a = block_max(ma, sh);
-        if (threadIdx.x == 0) atomicMax(normA, dbits(a));
+        if (threadIdx.x == 0) max_bits(normA, a);
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
@@ -122,175 +133,258 @@ __global__ __launch_bounds__(256) void k_residual(int kind, int m_rt, int64_t nb
         const double b = block_max(mx[c], sh);
         const double d = block_max(mf[c], sh);
         if (threadIdx.x == 0 && c < nc) {
-            atomicMax(norms + 3 * (c0 + c) + 0, dbits(a));
-            atomicMax(norms + 3 * (c0 + c) + 1, dbits(b));
-            atomicMax(norms + 3 * (c0 + c) + 2, dbits(d));
+            max_bits(norms + 3 * (c0 + c) + 0, a);
+            max_bits(norms + 3 * (c0 + c) + 1, b);
+            max_bits(norms + 3 * (c0 + c) + 2, d);
         }
     }
 }
 
 // The residual r = f - A x and the norms of eta on the matrix cores (FP64
-// v_mfma_f64_16x16x4f64), for block sizes MB = 4, 8, 16, 32.  A wave takes
-// a group of RG = max(16, MB) consecutive rows: the group's rows of A, over
-// the window of RG + 2 MB columns its blocks touch (block columns of its
-// first block row - 1 through its last + 1), are loaded once into registers
-// as the A operands of RG/16 row tiles x (RG + 2 MB)/4 steps (K index of step
-// s and lane group g: window column 4s + g), entries outside the three block
-// diagonals zero; then every column tile of 16 right-hand sides is one chain
-// of steps whose B operand is the x window, and r = f - acc in the result
-// layout (lane (n, g): rows 4q + g of the tile, column n).  So A is read once
-// per 64 right-hand sides (blockIdx.y), and a lane issues one x load per
-// matrix-core step instead of one per multiply-add.  The BABD corner C (block
-// row 0 against x[nb-1]) is a further chain in the group holding row 0.
-// ||A||_inf (normA, first column chunk): per row the sum of |A| over its
-// window entries and the corner, summed across the four lane groups.
+// v_mfma_f64_16x16x4f64), for block sizes MB = 4, 8, 16, 32.
+//
+// A step is S = max(16, MB) consecutive rows (one block row for MB = 32);
+// its rows of A touch the window of S + 2 MB columns from the block column
+// before its first block row to the one after its last.  Per row tile of 16
+// rows the window's A entries are the A operands of KS = (S + 2 MB) / 4
+// steps (K index of step p and lane group g: window column 4p + g; entries
+// outside the block diagonals zero), the x rows of the window for one tile
+// of 16 right-hand sides the B operands, and r = f - acc comes out in the
+// result layout (lane (n, g): rows 4q + g of the tile, column n); the steps
+// run as two accumulator chains (even and odd) added at the end.
+//
+// A wave walks a run of consecutive steps for one column tile and keeps the
+// x window in registers: the next step's window is this one shifted by S
+// rows, so per step only S new rows of x are loaded and x comes from memory
+// once per run (plus a window's halo at the run's start), A and f once, r
+// is written once.  The loads of a step (A, the new x rows, f) are
+// independent and issued together.  The BABD corner C (block row 0 against
+// x[nb-1]) is a further chain in the step holding row 0.  ||A||_inf
+// (wantA): per row of the tile-0 runs, the sum of |A| over its window entries
+// and the corner, summed across the four lane groups.
+//
+// Per column of the chunk the wave keeps its running maxima of |r|, |x|,
+// |f| in its own LDS row (entry (3J + t) 16 + n); the workgroup combines its
+// waves' rows and posts one maximum per column and norm.
+constexpr int kResCT = 4;     // column tiles per chunk (64 right-hand sides)
+constexpr int kResRun = 8;    // steps per run
+
+struct ResShared {
+    double col[4][3 * kResCT * 16];
+    double a[4];
+};
+
+__device__ __forceinline__ void res_begin(ResShared &sh, double &ma)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e = lane; e < 3 * kResCT * 16; e += 64) sh.col[wv][e] = 0.0;
+    ma = 0.0;
+}
+
+// the workgroup's waves, then one maximum per column and norm
+__device__ __forceinline__ void res_end(const ResidualArgs &a, int chunk, bool wantA,
+                                        ResShared &sh, double ma)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (wantA) {
+        ma = wave_max(ma);
+        if (lane == 0) sh.a[wv] = ma;
+    }
+    __syncthreads();
+    const int cb = chunk * 16 * kResCT;
+    for (int e = threadIdx.x; e < 3 * kResCT * 16; e += blockDim.x) {
+        const int J = e / 48, t = (e / 16) % 3, col = cb + 16 * J + (e & 15);
+        if (col < a.nrhs) {
+            const double v =
+                fmax(fmax(sh.col[0][e], sh.col[1][e]), fmax(sh.col[2][e], sh.col[3][e]));
+            max_bits(a.norms + 3 * col + t, v);
+        }
+    }
+    if (wantA && threadIdx.x == 0)
+        max_bits(a.normA, fmax(fmax(sh.a[0], sh.a[1]), fmax(sh.a[2], sh.a[3])));
+}
+
+// The runs of steps s0 .. s1 - 1 x the column tiles of the chunk: unit u
+// (run u / nt, tile u % nt), the workgroup's waves taking every fourth unit
+// (the waves on one run take its tiles together, sharing A in the cache).
 template <int MB>
-__global__ __launch_bounds__(256) void k_residual_mma(int kind, int64_t nb,
-                                                      const double *__restrict__ D,
-                                                      const double *__restrict__ Lo,
-                                                      const double *__restrict__ Up,
-                                                      const double *__restrict__ C, int nrhs,
-                                                      const double *__restrict__ f, int64_t ldf,
-                                                      const double *__restrict__ x, int64_t ldx,
-                                                      double *__restrict__ r, int64_t ldr,
-                                                      unsigned long long *norms,
-                                                      unsigned long long *normA)
+__device__ __forceinline__ void res_item(const ResidualArgs &a, int64_t s0, int64_t s1, int chunk,
+                                         bool wantA, bool write_r, ResShared &sh, double &ma)
 {
     typedef double v4 __attribute__((ext_vector_type(4)));
-    constexpr int TI = MB > 16 ? MB / 16 : 1;   // row tiles per group
-    constexpr int RG = 16 * TI;                 // rows per group
-    constexpr int KS = (RG + 2 * MB) / 4;       // steps over the column window
-    constexpr int KC = MB / 4;                  // steps of the corner chain
-    constexpr int CT = 4;                       // column tiles per chunk
-    constexpr int UJ = MB > 16 ? 1 : CT;        // their loop: unrolled below 32 x 32
+    constexpr int S = MB > 16 ? MB : 16;          // rows per step
+    constexpr int TI = S / 16;                     // row tiles per step
+    constexpr int KS = (S + 2 * MB) / 4;           // window steps
+    constexpr int KN = S / 4;                      // new window steps per step
+    constexpr int OWN = MB / 4;                    // first window step of the step's own rows
+    constexpr int KC = MB / 4;                     // steps of the corner chain
     constexpr int SH = MB == 4 ? 2 : MB == 8 ? 3 : MB == 16 ? 4 : 5;
     constexpr int64_t MM = (int64_t)MB * MB;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
-    const int64_t N = (int64_t)MB * nb;
-    const int64_t groups = (N + RG - 1) / RG;
-    const int cb = blockIdx.y * (16 * CT);
-    const bool wantA = normA != nullptr && blockIdx.y == 0;
-
-    // A(i, j) of the block tridiagonal (kind 0) or bidiagonal (kind 1)
-    // pattern, zero outside it and outside the matrix
-    auto a_at = [&](int64_t i, int64_t j) -> double {
-        if (i >= N || j < 0 || j >= N) return 0.0;
-        const int64_t k = i >> SH, kc = j >> SH;
-        const int64_t off = (i & (MB - 1)) + (j & (MB - 1)) * (int64_t)MB;
-        if (kc == k) return D[k * MM + off];
-        if (kc == k - 1) return Lo[(k - 1) * MM + off];
-        if (kc == k + 1 && kind == 0) return Up[k * MM + off];
-        return 0.0;
-    };
-
-    // per column of the chunk, this wave's running maxima of |r|, |x|, |f|
-    // (entry (3J + t) 16 + n of its LDS row; only the wave itself touches it)
-    __shared__ double sh[4][3 * CT * 16];
-    __shared__ double sha[4];
-    double ma = 0.0;
-    for (int e = lane; e < 3 * CT * 16; e += 64) sh[wv][e] = 0.0;
-
-    for (int64_t grp = (int64_t)blockIdx.x * 4 + wv; grp < groups;
-         grp += (int64_t)gridDim.x * 4) {
-        const int64_t row0 = grp * RG, w0 = row0 - MB;   // first row; first window column
-        const bool corner = kind == 1 && row0 == 0;      // wave-uniform
-        double a[TI][KS];
-#pragma unroll
-        for (int I = 0; I < TI; ++I)
-#pragma unroll
-            for (int st = 0; st < KS; ++st) a[I][st] = a_at(row0 + 16 * I + n, w0 + 4 * st + g);
-        // the corner's A operand: C(16I + n, 4st + g) for rows of block row 0
-        auto c_at = [&](int I, int st) -> double {
-            const int i = 16 * I + n, j = 4 * st + g;
-            return i < MB ? C[i + (int64_t)j * MB] : 0.0;
+    const int kind = a.kind, nrhs = a.nrhs;
+    const int64_t nb = a.nb, N = (int64_t)MB * nb;
+    const double *__restrict__ D = a.D;
+    const double *__restrict__ Lo = a.Lo;
+    const double *__restrict__ Up = a.Up;
+    const double *__restrict__ C = a.C;
+    const int64_t ldf = a.ldf, ldx = a.ldx, ldr = a.ldr;
+    const int cb = chunk * (16 * kResCT);
+    const int nt = min(kResCT, (nrhs - cb + 15) / 16);   // column tiles of this chunk
+    const int64_t runs = (s1 - s0 + kResRun - 1) / kResRun;
+    for (int64_t u = wv; u < runs * nt; u += 4) {
+        const int64_t sa = s0 + (u / nt) * kResRun, se = min(sa + kResRun, s1);
+        const int J = (int)(u % nt);
+        const int c0 = cb + 16 * J;
+        const bool act = c0 + n < nrhs;
+        const int64_t cc = act ? c0 + n : c0;    // an existing column (loads in bounds)
+        const double *__restrict__ xc = a.x + cc * ldx;
+        const double *__restrict__ fc = a.f + cc * ldf;
+        // window row p of the step at row0: x rows row0 - MB + 4p + g
+        auto xload = [&](int64_t row0, int p) -> double {
+            const int64_t j0 = row0 - MB + 4 * p;   // uniform; a multiple of 4
+            return (act && j0 >= 0 && j0 < N) ? xc[j0 + g] : 0.0;
         };
-        if (wantA) {
+        double b[KS];
 #pragma unroll
-            for (int I = 0; I < TI; ++I) {
-                double sa = 0.0;
+        for (int p = 0; p < KS; ++p) b[p] = xload(sa * S, p);
+        for (int64_t st = sa; st < se; ++st) {
+            const int64_t row0 = st * S;
+            if (st > sa) {
 #pragma unroll
-                for (int st = 0; st < KS; ++st) sa += fabs(a[I][st]);
-                if (corner)
+                for (int p = 0; p < KS - KN; ++p) b[p] = b[p + KN];
 #pragma unroll
-                    for (int st = 0; st < KC; ++st) sa += fabs(c_at(I, st));
-                sa += __shfl_xor(sa, 16, 64);
-                sa += __shfl_xor(sa, 32, 64);
-                ma = fmax(ma, sa);
+                for (int p = KS - KN; p < KS; ++p) b[p] = xload(row0, p);
             }
-        }
-#pragma unroll UJ
-        for (int J = 0; J < CT; ++J) {
-            const int c0 = cb + 16 * J;
-            if (c0 >= nrhs) break;   // wave-uniform
+            const int64_t kw = (row0 >> SH) - 1;   // block column of the window's start
+            const bool corner = kind == 1 && row0 == 0;
             double mr = 0.0, mx = 0.0, mf = 0.0;
-            const bool act = c0 + n < nrhs;
-            const int64_t cc = act ? c0 + n : c0;   // an existing column (loads in bounds)
-            double b[KS];
-#pragma unroll
-            for (int st = 0; st < KS; ++st) {
-                const int64_t j = w0 + 4 * st + g;
-                b[st] = (act && j >= 0 && j < N) ? x[j + cc * ldx] : 0.0;
-            }
-            v4 acc[TI];
 #pragma unroll
             for (int I = 0; I < TI; ++I) {
-                acc[I] = v4{0.0, 0.0, 0.0, 0.0};
+                // this lane's row i = row0 + 16I + n in block row ki: step p
+                // reads D, Lo or Up of block row ki by kc - ki, column
+                // (4p & (MB - 1)) + g of the block
+                const int64_t i = row0 + 16 * I + n, ki = i >> SH;
+                const bool rowok = i < N;
+                const int64_t lane_off = (i & (MB - 1)) + (int64_t)g * MB;
+                const double *pD = D + ki * MM + lane_off;
+                const double *pL = Lo + (ki > 0 ? ki - 1 : 0) * MM + lane_off;
+                const double *pU = kind == 0 ? Up + ki * MM + lane_off : nullptr;
+                double av[KS], fv[4];
 #pragma unroll
-                for (int st = 0; st < KS; ++st)
-                    acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I][st], b[st], acc[I], 0, 0, 0);
-            }
-            if (corner) {
-#pragma unroll
-                for (int st = 0; st < KC; ++st) {
-                    const double bc = act ? x[(nb - 1) * MB + 4 * st + g + cc * ldx] : 0.0;
-#pragma unroll
-                    for (int I = 0; I < TI; ++I)
-                        acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(c_at(I, st), bc, acc[I], 0, 0, 0);
+                for (int p = 0; p < KS; ++p) {
+                    const int64_t kc = kw + ((4 * p) >> SH);
+                    const int64_t co = (int64_t)((4 * p) & (MB - 1)) * MB;
+                    const int64_t d = kc - ki;
+                    double v = 0.0;
+                    if (rowok && kc >= 0 && kc < nb) {
+                        if (d == 0) v = pD[co];
+                        else if (d == -1) v = pL[co];
+                        else if (d == 1 && kind == 0) v = pU[co];
+                    }
+                    av[p] = v;
                 }
-            }
-            // the group's own rows of x are window steps MB/4 .. MB/4 + RG/4 - 1
+                const int64_t rt = row0 + 16 * I + g;   // rows rt + 4q of the result
 #pragma unroll
-            for (int st = MB / 4; st < MB / 4 + RG / 4; ++st) mx = fmax(mx, fabs(b[st]));
+                for (int q = 0; q < 4; ++q)
+                    fv[q] = (act && rt + 4 * q < N) ? fc[rt + 4 * q] : 0.0;
+                // the corner's A operand: C(i, 4p + g) for rows of block row 0
+                auto c_at = [&](int p) -> double {
+                    return i < MB ? C[i + (int64_t)(4 * p + g) * MB] : 0.0;
+                };
+                if (wantA && J == 0) {
+                    double sa_ = 0.0;
 #pragma unroll
-            for (int I = 0; I < TI; ++I)
+                    for (int p = 0; p < KS; ++p) sa_ += fabs(av[p]);
+                    if (corner)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t row = row0 + 16 * I + 4 * q + g;
-                    if (act && row < N) {
-                        const double fv = f[row + cc * ldf];
-                        const double rv = fv - acc[I][q];
-                        if (r) r[row + cc * ldr] = rv;
-                        mr = fmax(mr, fabs(rv));
-                        mf = fmax(mf, fabs(fv));
+                        for (int p = 0; p < KC; ++p) sa_ += fabs(c_at(p));
+                    sa_ += __shfl_xor(sa_, 16, 64);
+                    sa_ += __shfl_xor(sa_, 32, 64);
+                    ma = fmax(ma, sa_);
+                }
+                v4 acc0 = v4{0.0, 0.0, 0.0, 0.0}, acc1 = v4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int p = 0; p + 1 < KS; p += 2) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], b[p], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p + 1], b[p + 1], acc1, 0, 0, 0);
+                }
+                if constexpr (KS % 2)
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[KS - 1], b[KS - 1], acc0, 0, 0, 0);
+                if (corner) {
+#pragma unroll
+                    for (int p = 0; p < KC; ++p) {
+                        const double bc = act ? xc[(nb - 1) * MB + 4 * p + g] : 0.0;
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(c_at(p), bc, acc0, 0, 0, 0);
                     }
                 }
+                const v4 acc = acc0 + acc1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t row = rt + 4 * q;
+                    if (act && row < N) {
+                        const double rv = fv[q] - acc[q];
+                        if (write_r) a.r[row + cc * ldr] = rv;
+                        mr = fmax(mr, fabs(rv));
+                        mf = fmax(mf, fabs(fv[q]));
+                    }
+                }
+            }
+            // the step's own rows of x: window steps OWN .. OWN + KN - 1
+#pragma unroll
+            for (int p = OWN; p < OWN + KN; ++p) mx = fmax(mx, fabs(b[p]));
             // column n's maxima over the four lane groups, into the wave's row
             double v[3] = {mr, mx, mf};
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
                 v[t] = fmax(v[t], __shfl_xor(v[t], 16, 64));
                 v[t] = fmax(v[t], __shfl_xor(v[t], 32, 64));
-                double &cell = sh[wv][(3 * J + t) * 16 + n];
+                double &cell = sh.col[wv][(3 * J + t) * 16 + n];
                 if (g == 0) cell = fmax(cell, v[t]);
             }
         }
     }
-    // the workgroup's waves, then one atomic per column and norm
-    if (wantA) {
-        ma = wave_max(ma);
-        if (lane == 0) sha[wv] = ma;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 3 * CT * 16; e += blockDim.x) {
-        const int J = e / 48, t = (e / 16) % 3, col = cb + 16 * J + (e & 15);
-        if (col < nrhs) {
-            const double v = fmax(fmax(sh[0][e], sh[1][e]), fmax(sh[2][e], sh[3][e]));
-            atomicMax(norms + 3 * col + t, dbits(v));
-        }
-    }
-    if (wantA && threadIdx.x == 0)
-        atomicMax(normA, dbits(fmax(fmax(sha[0], sha[1]), fmax(sha[2], sha[3]))));
+}
+
+// steps of S rows in a system (see res_item)
+__host__ __device__ constexpr int res_step_rows(int m) { return m > 16 ? m : 16; }
+constexpr int kResItemSteps = 4 * kResRun;   // steps per workgroup item
+
+// one system: workgroup b takes items b, b + gridDim.x, ... of kResItemSteps
+// steps; blockIdx.y = the chunk of 64 right-hand sides
+template <int MB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 16 ? 2 : MB > 8 ? 3 : 4)))
+void k_residual_mma(ResidualArgs a)
+{
+    __shared__ ResShared sh;
+    double ma;
+    res_begin(sh, ma);
+    const bool wantA = a.normA != nullptr && blockIdx.y == 0;
+    const int64_t steps = ((int64_t)MB * a.nb + res_step_rows(MB) - 1) / res_step_rows(MB);
+    for (int64_t s0 = (int64_t)blockIdx.x * kResItemSteps; s0 < steps;
+         s0 += (int64_t)gridDim.x * kResItemSteps)
+        res_item<MB>(a, s0, min(s0 + kResItemSteps, steps), blockIdx.y, wantA, a.r != nullptr,
+                     sh, ma);
+    res_end(a, blockIdx.y, wantA, sh, ma);
+}
+
+// a batch: workgroup w serves system work[w].x, steps work[w].y .. work[w].z
+// - 1 in chunk work[w].w; systems whose live flag is 0 are skipped; wantA
+// and write_r as flags (bit 0, bit 1)
+template <int MB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MB > 16 ? 2 : MB > 8 ? 3 : 4)))
+void kb_residual_mma(const ResidualArgs *tab, const int4 *work, const unsigned char *live,
+                     int flags)
+{
+    __shared__ ResShared sh;
+    const int4 w = work[blockIdx.x];
+    if (!live[w.x]) return;   // uniform per workgroup
+    const ResidualArgs a = tab[w.x];
+    const bool wantA = (flags & 1) && a.normA != nullptr && w.w == 0;
+    double ma;
+    res_begin(sh, ma);
+    res_item<MB>(a, w.y, w.z, w.w, wantA, (flags & 2) != 0, sh, ma);
+    res_end(a, w.w, wantA, sh, ma);
 }
 
 __global__ void k_axpy(int64_t n, const double *__restrict__ d, int64_t ldd,
@@ -452,23 +546,18 @@ hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const d
     const int64_t n = (int64_t)m * nb;
     if (nrhs < 1) return hipSuccess;
     if (m == 4 || m == 8 || m == 16 || m == 32) {
-        auto mma = [&](auto mb) {
-            constexpr int MB = decltype(mb)::value;
-            constexpr int RG = MB > 16 ? MB : 16;
-            const int64_t groups = (n + RG - 1) / RG;
-            int64_t wg = (groups + 3) / 4;
-            if (wg > 1024) wg = 1024;
-            hipLaunchKernelGGL((k_residual_mma<MB>), dim3((unsigned)wg, (nrhs + 63) / 64), dim3(256),
-                               0, s, kind, nb, D, Lo, Up, C, nrhs, f, ldf, x, ldx, r, ldr, norms,
-                               normA);
-            return hipGetLastError();
-        };
+        const ResidualArgs a{kind, m, nb, D, Lo, Up, C, nrhs, f, ldf, x, ldx, r, ldr, norms, normA};
+        const int64_t steps = (n + res_step_rows(m) - 1) / res_step_rows(m);
+        int64_t wg = (steps + kResItemSteps - 1) / kResItemSteps;
+        if (wg > 2048) wg = 2048;
+        const dim3 grid((unsigned)wg, (nrhs + 16 * kResCT - 1) / (16 * kResCT));
         switch (m) {
-        case 4: return mma(std::integral_constant<int, 4>{});
-        case 8: return mma(std::integral_constant<int, 8>{});
-        case 16: return mma(std::integral_constant<int, 16>{});
-        default: return mma(std::integral_constant<int, 32>{});
+        case 4: hipLaunchKernelGGL((k_residual_mma<4>), grid, dim3(256), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_residual_mma<8>), grid, dim3(256), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_residual_mma<16>), grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_residual_mma<32>), grid, dim3(256), 0, s, a); break;
         }
+        return hipGetLastError();
     }
     // columns per thread: one, four, or eight (A read once per chunk); the
     // block sizes of the workloads get a fully unrolled row loop
@@ -491,6 +580,26 @@ hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const d
     if (nrhs == 1) return by_m(std::integral_constant<int, 1>{});
     if (nrhs <= 4) return by_m(std::integral_constant<int, 4>{});
     return by_m(std::integral_constant<int, 8>{});
+}
+
+bool residual_batched(int m) { return m == 4 || m == 8 || m == 16 || m == 32; }
+int residual_step_rows(int m) { return res_step_rows(m); }
+int residual_item_steps() { return kResItemSteps; }
+
+hipError_t launch_residual_batch(int m, const ResidualArgs *tab, const int4 *work, int nwg,
+                                 const unsigned char *live, bool wantA, bool write_r,
+                                 hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    const int flags = (wantA ? 1 : 0) | (write_r ? 2 : 0);
+    switch (m) {
+    case 4: hipLaunchKernelGGL((kb_residual_mma<4>), dim3(nwg), dim3(256), 0, s, tab, work, live, flags); break;
+    case 8: hipLaunchKernelGGL((kb_residual_mma<8>), dim3(nwg), dim3(256), 0, s, tab, work, live, flags); break;
+    case 16: hipLaunchKernelGGL((kb_residual_mma<16>), dim3(nwg), dim3(256), 0, s, tab, work, live, flags); break;
+    case 32: hipLaunchKernelGGL((kb_residual_mma<32>), dim3(nwg), dim3(256), 0, s, tab, work, live, flags); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, double *x,

@@ -162,6 +162,33 @@ hipError_t launch_pad_blocks(int m, int M, int64_t count, const double *src, dou
 hipError_t launch_pad_rhs(int m, int M, int64_t nb, int32_t nrhs, const double *src,
                           int64_t lds, double *dst, int64_t ldd, bool to_padded,
                           hipStream_t s);
+// One system's operands of the residual (see launch_residual).
+struct ResidualArgs {
+    int kind, m;
+    int64_t nb;
+    const double *D, *Lo, *Up, *C;
+    int nrhs;
+    const double *f;
+    int64_t ldf;
+    const double *x;
+    int64_t ldx;
+    double *r;
+    int64_t ldr;
+    unsigned long long *norms, *normA;
+};
+// block sizes with a grouped (batched) residual launch
+bool residual_batched(int m);
+// The grouped residual's work units: a system of block size m is cut into
+// steps of residual_step_rows(m) rows; workgroup w serves system work[w].x,
+// its steps work[w].y .. work[w].z - 1 (at most residual_item_steps()) and
+// column chunk work[w].w (64 right-hand sides); systems with live[sys] == 0
+// are skipped.  wantA: ||A||_inf of the chunk-0 workgroups into normA;
+// write_r: store r (else norms only).
+int residual_step_rows(int m);
+int residual_item_steps();
+hipError_t launch_residual_batch(int m, const ResidualArgs *tab, const int4 *work, int nwg,
+                                 const unsigned char *live, bool wantA, bool write_r,
+                                 hipStream_t s);
 // r = f - A x (FP64; r may be null: norms only) with the max-abs norms of r,
 // x, f per right-hand side accumulated into norms[3*c + {0,1,2}], and, when
 // normA is not null, ||A||_inf into *normA (ordered uint64 bit patterns of

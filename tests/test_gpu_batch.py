@@ -187,6 +187,42 @@ def test_batch_fp32_ir():
     del keep
 
 
+@pytest.mark.parametrize("mode", ["fp32ir", "fp64_eta"])
+def test_batch_residual_passes_equal_alone(mode):
+    """The batch's residual passes (one grouped launch per block size 4, 8,
+    16, 32; per-system launches for the others) compute what the
+    single-system residual computes: with FP32 + refinement every solution,
+    iteration count and eta equals the system solved alone, bit for bit, and
+    with PF_FLAG_ETA in FP64 every eta does."""
+    import torch
+    opts = pf.make_opts(prec=pf.PF_FP32_IR) if mode == "fp32ir" else \
+        pf.make_opts(flags=pf.PF_FLAG_ETA)
+    specs = [sp for sp in MIXED if sp[1] > 2]   # block sizes 3 and up (two on the grouped path)
+    systems = _systems(specs)
+    mats, keep, fs, xs = _device(systems)
+    infos, _ = pf.pf_solve_batch(mats, opts, [f.shape[0] for _, f in systems], fs, xs)
+    torch.cuda.synchronize()
+    for i, ((s, f), A, fd, xd, inf) in enumerate(zip(systems, mats, fs, xs, infos)):
+        tag = f"{mode} sys {i} {s.kind} m={s.m} nb={s.nb} k={f.shape[0]}"
+        if f.shape[0] == 0:
+            assert bool(xd.isnan().all()), f"{tag}: nrhs=0 output touched"
+            continue
+        xa = torch.full_like(fd, np.nan)
+        F = pf.pf_factor(A, opts)
+        try:
+            ia = pf.pf_solve(F, fd, xa)
+            torch.cuda.synchronize()
+        finally:
+            pf.pf_destroy(F)
+        _say(tag, "batch", inf.as_dict(), "alone", ia.as_dict())
+        assert inf.status == 0 and ia.status == 0, tag
+        assert np.array_equal(xd.cpu().numpy(), xa.cpu().numpy()), f"{tag}: batch != alone"
+        assert inf.eta == ia.eta and inf.refine_iters == ia.refine_iters, tag
+        assert 0 <= inf.eta <= G.ETA_TOL, tag
+        G.check(s, xd.cpu().numpy().T, f=f.T, tag=tag)
+    del keep
+
+
 def test_batch_singular_member_reported_alone():
     import torch
     systems = _systems([("btri", 4, 200, 1, 71), ("btri", 4, 200, 1, 72), ("babd", 4, 50, 1, 73)])
