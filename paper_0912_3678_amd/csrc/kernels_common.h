@@ -82,6 +82,28 @@ __device__ __forceinline__ Geo geometry(int64_t nb, int64_t p, int64_t part,
     return g;
 }
 
+// The geometry of a partition that is the same in every lane of the wave
+// (one partition per wave, or the first of a workgroup's): taken from the
+// first lane, so that what is built from it -- buffer descriptors above all
+// -- stays in scalar registers.  (Read from an explicit separator list, the
+// values come from a vector load, which the compiler cannot know to be
+// uniform; a descriptor built from them would otherwise be rebuilt lane by
+// lane around every buffer access.)
+template <int KIND>
+__device__ __forceinline__ Geo geometry_wave(int64_t nb, int64_t p, int64_t part,
+                                             const int64_t *sep)
+{
+    Geo g = geometry<KIND>(nb, p, part, sep);
+    // on every path: a value merged from the list's branch counts as
+    // non-uniform whichever branch ran
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)g.start);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)g.start >> 32));
+    g.start = (int64_t)(((uint64_t)hi << 32) | lo);
+    g.len = __builtin_amdgcn_readfirstlane(g.len);
+    g.kmax = __builtin_amdgcn_readfirstlane(g.kmax);
+    return g;
+}
+
 // A partition's pivot-block failures: the first one (smallest level and
 // block) goes to the status word; with a list (enlarged reduced systems)
 // every failing partition also appends its first failing block, which the

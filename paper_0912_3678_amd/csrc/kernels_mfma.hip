@@ -81,8 +81,8 @@ __device__ __forceinline__ void btri_mfma_body(const LevelArgs &a, const SolveAr
     // The wave's partitions.  A partition past the last one shadows the first
     // (same rows, every output dropped), so both have lengths within one.
     const int64_t nb = a.nb;
-    const Geo G0 = geometry<0>(nb, a.p, pblock * PPW, a.sep);
-    const Geo G1r = geometry<0>(nb, a.p, pblock * PPW + 1, a.sep);
+    const Geo G0 = geometry_wave<0>(nb, a.p, pblock * PPW, a.sep);
+    const Geo G1r = geometry_wave<0>(nb, a.p, pblock * PPW + 1, a.sep);
     const bool sh1 = !G1r.valid;
     const Geo G1 = sh1 ? G0 : G1r;
     const Geo &Gg = gp ? G1 : G0, &Gm = mp ? G1 : G0;

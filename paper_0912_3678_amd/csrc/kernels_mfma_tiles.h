@@ -246,7 +246,7 @@ __device__ __forceinline__ void btri_mfmat_body(const LevelArgs &a, const SolveA
     V *SE = S0 + M * RS;      // E by logical rows; then D' handed over
 
     const int64_t nb = a.nb;
-    const Geo G = geometry<0>(nb, a.p, part, a.sep);
+    const Geo G = geometry_wave<0>(nb, a.p, part, a.sep);
     const int64_t gb = G.start > 0 ? G.start - 1 : 0;
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
@@ -431,7 +431,7 @@ __device__ __forceinline__ void fwdt_body(const SolveArgs &a, int64_t part, int 
     constexpr uint32_t BB = MM * 8, BF = MM * sizeof(V);
     const int m = lane >> 4, n = lane & 15;
     const int64_t nb = a.nb;
-    const Geo G = geometry<KIND>(nb, a.p, part, a.sep);
+    const Geo G = geometry_wave<KIND>(nb, a.p, part, a.sep);
     const int64_t gb = G.start > 0 ? G.start - 1 : 0;
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rE = buf_rsrc((const V *)a.E + gb * MM, nr * BF);
@@ -494,7 +494,7 @@ __device__ __forceinline__ void bwdt_body(const SolveArgs &a, int64_t part, int 
     constexpr uint32_t BF = MM * sizeof(V);
     const int m = lane >> 4, n = lane & 15;
     const int64_t nb = a.nb;
-    const Geo G = geometry<KIND>(nb, a.p, part, a.sep);
+    const Geo G = geometry_wave<KIND>(nb, a.p, part, a.sep);
     const int64_t gb = G.start > 0 ? G.start - 1 : 0;
     const uint64_t nr = (uint64_t)(nb - gb);
     const auto rZ = buf_rsrc((const V *)a.Z + gb * MM, nr * BF);
@@ -636,7 +636,7 @@ __device__ __forceinline__ void babd_mfma16_body(const LevelArgs &a, const Solve
     V *SE = lds + (kBQ + q) * BSL;     // E_q by logical rows
 
     const int64_t nb = a.nb;
-    const Geo G = geometry<1>(nb, a.p, part, a.sep);
+    const Geo G = geometry_wave<1>(nb, a.p, part, a.sep);
     const int64_t gb = G.start - 1;         // the left separator (G.start >= 1)
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);

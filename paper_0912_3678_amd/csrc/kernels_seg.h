@@ -78,7 +78,7 @@ __device__ __forceinline__ void btri_seg_body(const LevelArgs &a, const SolveArg
     // the workgroup's first partition: every row a partition touches lies at
     // or past the base (its left separator's couplings included), and rows
     // past an array's end read zero, as a missing operand must.
-    const int64_t s0 = geometry<0>(nb, a.p, pblock * PPW, a.sep).start;
+    const int64_t s0 = geometry_wave<0>(nb, a.p, pblock * PPW, a.sep).start;
     const int64_t gb = s0 > 0 ? s0 - 1 : 0;
     constexpr uint32_t BB = MM * 8, BT = MM * sizeof(T);
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void babd_seg_body(const LevelArgs &a, const SolveArg
     // raw buffers based one block row before the workgroup's first partition
     // (its left separator); rows past an array's end read zero
     const int64_t nb = a.nb;
-    const int64_t gb = geometry<1>(nb, a.p, pblock * PPW, a.sep).start - 1;
+    const int64_t gb = geometry_wave<1>(nb, a.p, pblock * PPW, a.sep).start - 1;
     constexpr uint32_t BB = MM * 8, BT = MM * sizeof(T);
     const uint64_t nr = (uint64_t)(nb - gb), nr1 = nb - 1 > gb ? (uint64_t)(nb - 1 - gb) : 0;
     const auto rD = buf_rsrc(a.D + gb * MM, nr * BB);
