@@ -962,42 +962,56 @@ def serving_summary(args):
     (block sizes 8, 16, 32; N lognormal, median 2^14, clamped to 2^20; 30 %
     repeat right-hand sides on kept factors) through the request scheduler
     under a 250 GB budget: saturation first, then Poisson arrivals at 0.8 x
-    that rate."""
-    out = _serving(args, count=args.serve_count, n_hi=2 ** 20, budget=250e9, pool_n=64,
-                   fracs=(0.8,))
+    that rate; FP64, and FP32 factors + FP64 refinement (key fp32ir)."""
+    res = {}
+    for prec in ("fp64", "fp32ir"):
+        out = _serving(args, count=args.serve_count, n_hi=2 ** 20, budget=250e9, pool_n=64,
+                       fracs=(0.8,), prec=prec)
+        res[prec] = _serving_line(args, out)
+    line = dict(res["fp64"])
+    line["fp32ir"] = res["fp32ir"]
+    return line
+
+
+def _serving_line(args, out):
     load = out["load"][-1]
-    return {"workload": "serving_stream", "requests": args.serve_count, "n_max": 2 ** 20,
-            "budget_GB": 250, "pool_matrices": 64,
+    return {"workload": "serving_stream", "prec": out["prec"], "requests": args.serve_count,
+            "n_max": 2 ** 20, "budget_GB": 250, "pool_matrices": 64,
             "saturation_req_s": round(out["saturation"]["throughput_req_s"], 1),
             "saturation_unknowns_s": out["saturation"]["unknowns_per_s"],
             "at_qps": round(load["qps"], 1), "p50_ms": load["p50_ms"], "p99_ms": load["p99_ms"],
             "unknowns_per_s": load["unknowns_per_s"], "eta_max_sample":
                 max(out["saturation"]["eta_max_sample"], load["eta_max_sample"]),
             "bad_status": out["saturation"]["bad_status"] + load["bad_status"],
-            "host_submit_max_ms": load["host_submit_max_ms"]}
+            "host_submit_max_ms": load["host_submit_max_ms"],
+            "host_setup_ms_max": load["host_setup_ms_max"],
+            "refine_iters": load["refine_iters"], "reserved_GB": out["reserved_GB"]}
 
 
 def run_serving(args):
     out = _serving(args, count=args.count or 240, n_hi=args.n_hi or 2 ** 20,
-                   budget=args.budget_gb * 1e9, pool_n=64, fracs=(0.5, 0.8))
+                   budget=args.budget_gb * 1e9, pool_n=64, fracs=(0.5, 0.8),
+                   prec=args.prec or "fp64")
     sat, runs = out["saturation"], out["load"]
     ok = all(r["bad_status"] == 0 and r["eta_max_sample"] <= 1e-12 for r in [sat] + runs)
     return {
         "metric": "p50/p99 solve latency under load; unknowns solved/sec at residual<=1e-12",
         "value": runs[-1]["unknowns_per_s"] if ok else 0.0, "unit": "unknowns/s",
         "n_gpus": 1, "steps": len(runs) and runs[-1]["requests"], "warmup": 0, "ms_per_step": None,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 factors + f64 refinement" if out["prec"] == "fp32ir" else "f64",
         "data": "synthetic",
         "config": {"workload": "serving_stream", "requests": args.count or 240,
                    "pool": out["pool"], "n_max": args.n_hi or 2 ** 20,
                    "budget_GB": args.budget_gb},
-        "saturation": sat, "load": runs,
+        "saturation": sat, "load": runs, "reserved_GB": out["reserved_GB"],
+        "reserve_s": out["reserve_s"],
         "latency_ms": {"p50": runs[-1]["p50_ms"], "p99": runs[-1]["p99_ms"],
                        "at_qps": runs[-1]["qps"]},
     }
 
 
-def _serving(args, count, n_hi, budget, pool_n, fracs):
+def _serving(args, count, n_hi, budget, pool_n, fracs, prec="fp64"):
     """Request stream through the scheduler.  A pool of matrices drawn from
     the workload's law is generated on the device once; each new request
     factors one of them (the scheduler does not know they repeat), 30 % of
@@ -1023,7 +1037,16 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
 
     # one server for every stream of the run: its memory pool, grown by the
     # first (saturation) stream, is reused by the later ones
-    S = pf.Server(budget, max_inflight=16, nstreams=4)
+    opts = pf.make_opts(prec=pf.PF_FP32_IR if prec == "fp32ir" else pf.PF_FP64)
+    S = pf.Server(budget, opts, max_inflight=16, nstreams=4)
+    # map the stream's device memory ahead (a server's start-up, not timed):
+    # every new request keeps its factor until the end of its pass
+    per = [pf.pf_factor_bytes(A, opts) + pf.pf_solve_bytes_per_rhs(A, opts) for A, _, _, _ in pool]
+    need = sum(per[i % len(pool)] for i, r in enumerate(wl.serving_stream(count, 1e9, n_max=n_hi))
+               if not r["repeat"])
+    t_r = time.perf_counter()
+    S.reserve(min(budget, int(need * 1.1)))
+    reserve_s = time.perf_counter() - t_r
 
     def run_stream(qps):
         stream = wl.serving_stream(count, qps if qps else 1e9, n_max=n_hi)
@@ -1085,13 +1108,17 @@ def _serving(args, count, n_hi, budget, pool_n, fracs):
                 "host_launch_ms_max": round(st["launch_ms_max"], 2),
                 "host_submit_ms": round(host_submit * 1e3, 1),
                 "host_submit_max_ms": round(max(submit_ms), 2),
-                "host_submit_slowest": [int(i) for i in np.argsort(submit_ms)[-5:]]}
+                "host_submit_slowest": [int(i) for i in np.argsort(submit_ms)[-5:]],
+                "refine_iters": {str(v): sum(1 for i in infos if i.refine_iters == v)
+                                 for v in sorted({i.refine_iters for i in infos})}}
 
     sat = run_stream(0)
     rate = sat["throughput_req_s"]
     runs = [run_stream(frac * rate) for frac in fracs]
     S.destroy()
-    return {"saturation": sat, "load": runs, "pool": len(pool)}
+    return {"saturation": sat, "load": runs, "pool": len(pool), "prec": prec,
+            "reserved_GB": round(min(budget, int(need * 1.1)) / 1e9, 2),
+            "reserve_s": round(reserve_s, 3)}
 
 
 if __name__ == "__main__":

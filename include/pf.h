@@ -524,12 +524,15 @@ int pf_server_wait(pf_server_t S, int64_t ticket, pf_info *info);
  * when the request is done. */
 int pf_server_times(pf_server_t S, int64_t ticket, double *submit_ms, double *start_ms,
                     double *done_ms);
-/* Map `bytes` (<= budget) of the server's memory pool ahead of the requests:
- * factor memory comes from a pool of the server's own that keeps up to the
- * budget mapped once used, so later allocations are pool lookups rather than
- * fresh device mappings (which cost host time that lands in a request's
- * latency).  Synchronizes one of the server's streams.  Returns 0, -k,
- * PF_ENOMEM or PF_EHIP. */
+/* Allocate `bytes` (<= budget) of device memory once, ahead of the
+ * requests (a server's start-up): the server carves request memory from it
+ * with a sub-allocator of its own (best fit, coalescing; a range freed on one
+ * stream goes to another only behind an event wait), so no request's
+ * allocation reaches the driver, whose mappings of fresh device memory have
+ * cost hundreds of milliseconds of host time inside single requests.  What
+ * does not fit falls back to the server's memory pool (release threshold =
+ * the budget).  Once per server (-3 after that); blocks the host for the
+ * allocation.  Returns 0, -k, PF_ENOMEM or PF_EHIP. */
 int pf_server_reserve(pf_server_t S, size_t bytes);
 /* Drop a kept factor (after the requests queued on it). */
 int pf_server_release(pf_server_t S, int64_t factor);

@@ -14,10 +14,11 @@
 // (they share its workspace).  Nothing here waits on the host for device
 // work except pf_server_wait.
 //
-// Factor memory comes from a memory pool of the server's own whose release
-// threshold is the budget: what retired requests give back stays mapped for
-// the next ones, so a new request's allocation is a pool lookup instead of a
-// fresh mapping of device memory (pf_server_reserve maps it ahead).
+// Request memory comes from one device allocation made at start-up
+// (pf_server_reserve), carved by a sub-allocator of the server's own, so no
+// request's allocation reaches the driver; what does not fit there comes
+// from a memory pool of the server's own whose release threshold is the
+// budget (what retired requests give back stays mapped for the next ones).
 #include "pf.h"
 #include "pf_internal.h"
 
@@ -56,7 +57,8 @@ struct Ticket {
     bool ir = false;
     int iters = 0, slow = 0;
     double eta = INFINITY, prev = INFINITY;
-    unsigned long long *hnorms = nullptr;   // 3 nrhs + 1 pinned words
+    unsigned long long *hnorms = nullptr;   // 3 nrhs + 1 pinned words (a server slot)
+    size_t hcap = 0;                        // the slot's words
     hipEvent_t ev_norms = nullptr;
 };
 
@@ -74,9 +76,27 @@ struct Resident {
 
 }  // namespace
 
+// One device allocation carved for the requests (pf_server_reserve): free
+// ranges by offset, coalesced; a range freed on a stream is pending until an
+// event recorded behind the free has fired, and is handed out before that
+// only to a stream told to wait for the event -- nothing here waits on the
+// host, and no request's allocation reaches the driver.
+struct Slab {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free;   // offset -> bytes
+    struct Pending {
+        size_t off, bytes;
+        hipEvent_t ev;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;   // events to record frees with
+};
+
 struct pf_server_s {
     size_t budget = 0, used = 0;
-    hipMemPool_t pool = nullptr;     // factor memory (release threshold = budget)
+    Slab slab;                       // reserved memory (pf_server_reserve)
+    hipMemPool_t pool = nullptr;     // other factor memory (release threshold = budget)
     Allocator al;                    // hands the pool to new handles
     double setup_ms_max = 0, setup_ms_total = 0;     // host: handle set-up + allocation
     double launch_ms_max = 0, launch_ms_total = 0;   // host: a request's whole launch
@@ -92,20 +112,123 @@ struct pf_server_s {
     int inflight = 0;
     std::map<int64_t, Resident> resident;  // keyed by the ticket that factored it
     int64_t evictions = 0, completed = 0;
+    // pinned host slots for the residual norms of refined requests: taken
+    // and given back per request, allocated only when none is large enough
+    // (pinning and unpinning host memory can wait for the whole device)
+    std::vector<std::pair<unsigned long long *, size_t>> pin_free;
+    std::vector<unsigned long long *> pin_all;
 };
 
 namespace {
 
+constexpr size_t kSlabAlign = 256;
+
+size_t slab_round(size_t bytes) { return (bytes + kSlabAlign - 1) / kSlabAlign * kSlabAlign; }
+
+void slab_insert(Slab &B, size_t off, size_t bytes)
+{
+    auto next = B.free.lower_bound(off);
+    if (next != B.free.end() && off + bytes == next->first) {
+        bytes += next->second;
+        next = B.free.erase(next);
+    }
+    if (next != B.free.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+            prev->second += bytes;
+            return;
+        }
+    }
+    B.free.emplace(off, bytes);
+}
+
+// ranges whose free has completed on the device become free
+void slab_reclaim(Slab &B)
+{
+    for (size_t i = 0; i < B.pending.size();) {
+        if (hipEventQuery(B.pending[i].ev) == hipSuccess) {
+            slab_insert(B, B.pending[i].off, B.pending[i].bytes);
+            B.spare.push_back(B.pending[i].ev);
+            B.pending[i] = B.pending.back();
+            B.pending.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
+// the smallest free range of at least `bytes` (best fit), split from its start
+void *slab_alloc(Slab &B, size_t bytes, hipStream_t s)
+{
+    if (!B.base) return nullptr;
+    bytes = slab_round(bytes);
+    slab_reclaim(B);
+    auto best = B.free.end();
+    for (auto it = B.free.begin(); it != B.free.end(); ++it)
+        if (it->second >= bytes && (best == B.free.end() || it->second < best->second)) best = it;
+    if (best != B.free.end()) {
+        const size_t off = best->first, have = best->second;
+        B.free.erase(best);
+        if (have > bytes) B.free.emplace(off + bytes, have - bytes);
+        return B.base + off;
+    }
+    // a range whose free is still in flight: this stream waits for it
+    size_t pick = B.pending.size();
+    for (size_t i = 0; i < B.pending.size(); ++i)
+        if (B.pending[i].bytes >= bytes &&
+            (pick == B.pending.size() || B.pending[i].bytes < B.pending[pick].bytes))
+            pick = i;
+    if (pick == B.pending.size()) return nullptr;
+    Slab::Pending P = B.pending[pick];
+    if (hipStreamWaitEvent(s, P.ev, 0) != hipSuccess) return nullptr;
+    if (P.bytes > bytes) {   // the rest stays pending behind the same event
+        B.pending[pick].off = P.off + bytes;
+        B.pending[pick].bytes = P.bytes - bytes;
+    } else {
+        B.spare.push_back(P.ev);
+        B.pending[pick] = B.pending.back();
+        B.pending.pop_back();
+    }
+    return B.base + P.off;
+}
+
+bool slab_free(Slab &B, void *p, size_t bytes, hipStream_t s)
+{
+    char *c = (char *)p;
+    if (!B.base || c < B.base || c >= B.base + B.size) return false;
+    hipEvent_t ev = nullptr;
+    if (!B.spare.empty()) {
+        ev = B.spare.back();
+        B.spare.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+    }
+    const size_t off = (size_t)(c - B.base);
+    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+        // no event: the range comes back once the stream has drained
+        if (hipStreamSynchronize(s) == hipSuccess) slab_insert(B, off, slab_round(bytes));
+        if (ev) B.spare.push_back(ev);
+        return true;
+    }
+    B.pending.push_back({off, slab_round(bytes), ev});
+    return true;
+}
+
+// the reserved slab first, the server's pool for what does not fit in it
 void *pool_alloc(size_t bytes, void *stream, void *ctx)
 {
+    pf_server_s *S = (pf_server_s *)ctx;
+    if (void *q = slab_alloc(S->slab, bytes, (hipStream_t)stream)) return q;
     void *p = nullptr;
-    if (hipMallocFromPoolAsync(&p, bytes, (hipMemPool_t)ctx, (hipStream_t)stream) != hipSuccess)
+    if (hipMallocFromPoolAsync(&p, bytes, S->pool, (hipStream_t)stream) != hipSuccess)
         return nullptr;
     return p;
 }
-void pool_free(void *p, size_t, void *stream, void *)
+void pool_free(void *p, size_t bytes, void *stream, void *ctx)
 {
-    hipFreeAsync(p, (hipStream_t)stream);
+    pf_server_s *S = (pf_server_s *)ctx;
+    if (slab_free(S->slab, p, bytes, (hipStream_t)stream)) return;
+    (void)hipFreeAsync(p, (hipStream_t)stream);
 }
 
 size_t request_bytes(const pf_server_s *S, const pf_request &r)
@@ -138,6 +261,36 @@ bool make_room(pf_server_s *S, size_t need)
         ++S->evictions;
     }
     return true;
+}
+
+// a pinned slot of at least `words` words (smallest free one that fits)
+bool pin_take(pf_server_s *S, size_t words, unsigned long long **p, size_t *cap)
+{
+    size_t best = S->pin_free.size();
+    for (size_t i = 0; i < S->pin_free.size(); ++i)
+        if (S->pin_free[i].second >= words &&
+            (best == S->pin_free.size() || S->pin_free[i].second < S->pin_free[best].second))
+            best = i;
+    if (best < S->pin_free.size()) {
+        *p = S->pin_free[best].first;
+        *cap = S->pin_free[best].second;
+        S->pin_free.erase(S->pin_free.begin() + (long)best);
+        return true;
+    }
+    const size_t c = std::max<size_t>(words, 512);
+    void *q = nullptr;
+    if (hipHostMalloc(&q, c * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+        return false;
+    S->pin_all.push_back((unsigned long long *)q);
+    *p = (unsigned long long *)q;
+    *cap = c;
+    return true;
+}
+void pin_give(pf_server_s *S, Ticket &T)
+{
+    if (T.hnorms) S->pin_free.emplace_back(T.hnorms, T.hcap);
+    T.hnorms = nullptr;
+    T.hcap = 0;
 }
 
 // One refinement decision for a request whose residual norms have arrived:
@@ -196,8 +349,7 @@ void retire(pf_server_s *S)
                 T.info.refine_iters = T.iters;
                 T.info.eta = T.eta;
                 if (T.info.status == PF_OK) T.info.status = ir_status;
-                hipHostFree(T.hnorms);
-                T.hnorms = nullptr;
+                pin_give(S, T);
             }
         }
         T.state = 2;
@@ -243,9 +395,7 @@ void retire(pf_server_s *S)
 int start_refinement(pf_server_s *S, int64_t id, Ticket &T, hipStream_t s)
 {
     const pf_request &r = T.req;
-    if (hipHostMalloc((void **)&T.hnorms, (3 * (size_t)r.nrhs + 1) * sizeof(unsigned long long),
-                      hipHostMallocDefault) != hipSuccess)
-        return PF_EHIP;
+    if (!pin_take(S, 3 * (size_t)r.nrhs + 1, &T.hnorms, &T.hcap)) return PF_EHIP;
     if (hipEventCreateWithFlags(&T.ev_norms, hipEventDisableTiming) != hipSuccess) return PF_EHIP;
     const int rc = ir_queue_residual(T.F, r.nrhs, r.f, r.ldf, r.x, r.ldx, s, T.hnorms);
     if (rc) return rc;
@@ -325,11 +475,9 @@ void fail(pf_server_s *S, Ticket &T, int rc)
     if (T.ev_done) hipEventDestroy(T.ev_done);
     if (T.ev_ready) hipEventDestroy(T.ev_ready);
     if (T.ev_norms) hipEventDestroy(T.ev_norms);
-    if (T.hnorms) hipHostFree(T.hnorms);
+    pin_give(S, T);
     T.ev_start = T.ev_done = T.ev_ready = T.ev_norms = nullptr;
-    T.hnorms = nullptr;
     T.ir = false;
-    (void)S;
 }
 
 // Admit queued requests in arrival order; one that does not fit yet stays
@@ -421,7 +569,7 @@ int pf_server_create(size_t budget_bytes, const pf_opts *opts, int32_t max_infli
         }
         S->al.alloc = pool_alloc;
         S->al.free = pool_free;
-        S->al.ctx = (void *)S->pool;
+        S->al.ctx = (void *)S;
     }
     const int ns = nstreams ? nstreams : 4;
     for (int i = 0; i < ns; ++i) {
@@ -570,11 +718,13 @@ int pf_server_reserve(pf_server_t S, size_t bytes)
     if (!S) return -1;
     if (bytes > S->budget) return -2;
     if (bytes == 0) return 0;
-    hipStream_t s = S->streams[0];
+    if (S->slab.base) return -3;   // once per server
     void *p = nullptr;
-    const hipError_t e = hipMallocFromPoolAsync(&p, bytes, S->pool, s);
+    const hipError_t e = hipMalloc(&p, slab_round(bytes));
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP;
-    if (hipFreeAsync(p, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return PF_EHIP;
+    S->slab.base = (char *)p;
+    S->slab.size = slab_round(bytes);
+    S->slab.free.emplace(0, S->slab.size);
     return 0;
 }
 
@@ -588,7 +738,6 @@ void pf_server_destroy(pf_server_t S)
         if (T.ev_done) hipEventDestroy(T.ev_done);
         if (T.ev_ready) hipEventDestroy(T.ev_ready);
         if (T.ev_norms) hipEventDestroy(T.ev_norms);
-        if (T.hnorms) hipHostFree(T.hnorms);
         if (T.state == 2 && T.req.factor < 0 && !T.req.keep) continue;   // freed at retire
         if (T.state == 1 && T.req.factor < 0 && !T.req.keep) destroy_async(T.F);
     }
@@ -599,7 +748,11 @@ void pf_server_destroy(pf_server_t S)
         hipStreamDestroy(s);
     }
     if (S->epoch) hipEventDestroy(S->epoch);
+    for (auto &P : S->slab.pending) hipEventDestroy(P.ev);
+    for (hipEvent_t ev : S->slab.spare) hipEventDestroy(ev);
+    if (S->slab.base) hipFree(S->slab.base);
     if (S->pool) hipMemPoolDestroy(S->pool);
+    for (unsigned long long *p : S->pin_all) hipHostFree(p);
     delete S;
 }
 

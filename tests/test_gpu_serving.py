@@ -51,7 +51,11 @@ def _alone_repeat(A, fd):
     return x.cpu().numpy()
 
 
-def test_serving_mix_equals_alone_with_queueing_and_eviction():
+@pytest.mark.parametrize("reserve", [False, True])
+def test_serving_mix_equals_alone_with_queueing_and_eviction(reserve):
+    """reserve: the request memory is carved from one allocation made up
+    front (pf_server_reserve), ranges freed by one request going to the
+    next; any overlap between live ranges would corrupt a solution."""
     import torch
     specs = [(8, 3000, 1), (16, 500, 1), (4, 2000, 2), (3, 900, 1), (8, 5000, 1), (32, 40, 1),
              (8, 700, 3), (16, 1200, 1), (2, 4000, 1), (8, 2500, 1)]
@@ -65,6 +69,10 @@ def test_serving_mix_equals_alone_with_queueing_and_eviction():
     sizes = [pf.pf_factor_bytes(A) + pf.pf_solve_bytes_per_rhs(A) * k for _, A, _, k in systems]
     budget = int(max(sizes) * 2.5)
     S = pf.Server(budget, max_inflight=4, nstreams=3)
+    if reserve:
+        S.reserve(budget)
+        with pytest.raises(pf.PFError):   # once per server
+            S.reserve(1 << 20)
     try:
         reqs = []    # (ticket, system index, f numpy, f device, x device, kind)
         for i, (s, A, keep, k) in enumerate(systems):
@@ -160,7 +168,8 @@ def test_autotune_choice_solves(kind, m, nb):
     del keep
 
 
-def test_serving_fp32_refined_mix_equals_alone():
+@pytest.mark.parametrize("reserve", [False, True])
+def test_serving_fp32_refined_mix_equals_alone(reserve):
     """PF_FP32_IR requests: the refinement runs from the scheduler's polling,
     step for step what pf_solve's loop does, so each solution equals the
     same refined solve made alone bit for bit, with its iteration count and
@@ -176,6 +185,8 @@ def test_serving_fp32_refined_mix_equals_alone():
     sizes = [pf.pf_factor_bytes(A, opts) + pf.pf_solve_bytes_per_rhs(A, opts) * k
              for _, A, _, k in systems]
     S = pf.Server(int(max(sizes) * 3), opts, max_inflight=4, nstreams=3)
+    if reserve:
+        S.reserve(int(max(sizes) * 3))
 
     def alone(A, fd, repeat):
         x = torch.full_like(fd, np.nan)
