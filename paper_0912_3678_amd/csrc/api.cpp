@@ -1748,7 +1748,13 @@ struct pf_batch_s {
     ResidualArgs *d_rtab = nullptr;
     std::vector<ResGroup> rgroups;
     std::vector<int> rsingle;
-    unsigned char *d_live = nullptr, *h_live = nullptr;   // systems still refining (h: pinned)
+    // systems still refining: device mask; its pinned sources for the
+    // residual pass and for the correction (two, so that the one being
+    // refilled is never the source of a copy still queued)
+    unsigned char *d_live = nullptr, *h_live = nullptr, *h_live2 = nullptr;
+    AxpyArgs *d_atab = nullptr;          // x += d of the refinement, one launch
+    int4 *d_awork = nullptr;
+    int anwg = 0;
     std::vector<void *> own;             // table allocations
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1925,6 +1931,7 @@ void batch_free(pf_batch_s *B)
         if (F) pf_destroy(F);
     for (void *p : B->own) hipFree(p);
     if (B->h_live) hipHostFree(B->h_live);
+    if (B->h_live2) hipHostFree(B->h_live2);
     if (B->arena) arena_release(B->arena, B->cap ? B->cap : B->user);
     if (B->ev) hipEventDestroy(B->ev);
     if (B->cap) hipStreamDestroy(B->cap);
@@ -1998,12 +2005,11 @@ int batch_refine(pf_batch_s *B, hipStream_t s, bool refine, std::vector<double> 
         if (all || !refine) break;
         HIPCHK(issue_solve(B, B->corr, true, s));
         for (int i = 0; i < ns; ++i) {
-            if (done[i]) continue;
-            pf_factor_s *F = B->all[i];
-            const int64_t n = F->nb * F->m;
-            HIPCHK(launch_axpy(n, B->nrhs[i], F->wsD, n, B->x[i], B->ldx[i], s));
-            ++iters[i];
+            B->h_live2[i] = (!done[i] && B->nrhs[i] > 0) ? 1 : 0;
+            if (!done[i]) ++iters[i];
         }
+        HIPCHK(hipMemcpyAsync(B->d_live, B->h_live2, ns, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_axpy_batch(B->d_atab, B->d_awork, B->anwg, B->d_live, s));
     }
     return 0;
 }
@@ -2185,8 +2191,23 @@ int batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const in
         }
         std::vector<unsigned char> live(nsys, 1);
         if (upload(B, live, &B->d_live)) return fail(PF_EHIP);
-        if (hipHostMalloc((void **)&B->h_live, nsys, hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void **)&B->h_live, nsys, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&B->h_live2, nsys, hipHostMallocDefault) != hipSuccess)
             return fail(PF_EHIP);
+        if (o.prec == PF_FP32_IR) {
+            std::vector<AxpyArgs> atab(nsys);
+            std::vector<int4> awork;
+            for (int i = 0; i < nsys; ++i) {
+                pf_factor_s *F = B->all[i];
+                const int64_t n = F->nb * F->m;
+                atab[i] = AxpyArgs{B->x[i], F->wsD, n, B->ldx[i], n, nrhs[i]};
+                const int64_t units = (n * nrhs[i] + kAxpyUnit - 1) / kAxpyUnit;
+                for (int64_t u = 0; u < units; u += 4)
+                    awork.push_back(int4{i, (int)u, (int)std::min<int64_t>(u + 4, units), 0});
+            }
+            if (upload(B, atab, &B->d_atab) || upload(B, awork, &B->d_awork)) return fail(PF_EHIP);
+            B->anwg = (int)awork.size();
+        }
     }
     if (hipStreamSynchronize(us) != hipSuccess) return fail(PF_EHIP);
 

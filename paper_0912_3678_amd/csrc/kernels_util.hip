@@ -387,6 +387,25 @@ void kb_residual_mma(const ResidualArgs *tab, const int4 *work, const unsigned c
     res_end(a, w.w, wantA, sh, ma);
 }
 
+// x += d for the systems of a batch in one launch: workgroup w serves
+// system work[w].x, the elements work[w].y .. work[w].z - 1 of its n x nrhs
+// columns taken as one range (element e: row e mod n, column e / n), in
+// units of kAxpyUnit elements (work[w].y, .z are unit indices); systems whose
+// live flag is 0 are skipped
+__global__ __launch_bounds__(256) void kb_axpy(const AxpyArgs *tab, const int4 *work,
+                                               const unsigned char *live)
+{
+    const int4 w = work[blockIdx.x];
+    if (!live[w.x]) return;
+    const AxpyArgs a = tab[w.x];
+    const int64_t total = a.n * a.nrhs;
+    const int64_t e0 = (int64_t)w.y * kAxpyUnit, e1 = min((int64_t)w.z * kAxpyUnit, total);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int64_t c = e / a.n, i = e - c * a.n;
+        a.x[i + c * a.ldx] += a.d[i + c * a.ldd];
+    }
+}
+
 __global__ void k_axpy(int64_t n, const double *__restrict__ d, int64_t ldd,
                        double *__restrict__ x, int64_t ldx)
 {
@@ -547,9 +566,11 @@ hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const d
     if (nrhs < 1) return hipSuccess;
     if (m == 4 || m == 8 || m == 16 || m == 32) {
         const ResidualArgs a{kind, m, nb, D, Lo, Up, C, nrhs, f, ldf, x, ldx, r, ldr, norms, normA};
+        // one workgroup per item (as the batched launch): the grid's waves
+        // all have their loads in flight at once
         const int64_t steps = (n + res_step_rows(m) - 1) / res_step_rows(m);
         int64_t wg = (steps + kResItemSteps - 1) / kResItemSteps;
-        if (wg > 2048) wg = 2048;
+        if (wg > (1 << 30)) wg = 1 << 30;
         const dim3 grid((unsigned)wg, (nrhs + 16 * kResCT - 1) / (16 * kResCT));
         switch (m) {
         case 4: hipLaunchKernelGGL((k_residual_mma<4>), grid, dim3(256), 0, s, a); break;
@@ -606,6 +627,14 @@ hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, do
                        int64_t ldx, hipStream_t s)
 {
     hipLaunchKernelGGL(k_axpy, dim3(grid1(n, 256), nrhs), dim3(256), 0, s, n, d, ldd, x, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_batch(const AxpyArgs *tab, const int4 *work, int nwg,
+                             const unsigned char *live, hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_axpy, dim3(nwg), dim3(256), 0, s, tab, work, live);
     return hipGetLastError();
 }
 

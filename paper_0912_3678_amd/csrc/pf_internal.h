@@ -198,6 +198,18 @@ hipError_t launch_residual(int kind, int m, int64_t nb, const double *D, const d
                            int64_t ldf, const double *x, int64_t ldx, double *r, int64_t ldr,
                            unsigned long long *norms, unsigned long long *normA, hipStream_t s);
 // x += d
+// x += d for many systems in one launch (see kb_axpy): per system its
+// operands; workgroup w serves system work[w].x, element units work[w].y ..
+// work[w].z - 1 of kAxpyUnit elements of its n x nrhs columns
+struct AxpyArgs {
+    double *x;
+    const double *d;
+    int64_t n, ldx, ldd;
+    int nrhs;
+};
+constexpr int64_t kAxpyUnit = 65536;
+hipError_t launch_axpy_batch(const AxpyArgs *tab, const int4 *work, int nwg,
+                             const unsigned char *live, hipStream_t s);
 hipError_t launch_axpy(int64_t n, int32_t nrhs, const double *d, int64_t ldd, double *x,
                        int64_t ldx, hipStream_t s);
 // Fill count 64-bit words with a value (kernel, capture-safe).
