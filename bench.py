@@ -69,7 +69,9 @@ def parse():
     ap.add_argument("--n-hi", type=int, default=0,
                     help="batch / serving: largest block count (default 2^16 / 2^20)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: memory budget")
-    ap.add_argument("--autotune", action="store_true", help="batch: PF_FLAG_AUTOTUNE")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batch: the planner's launch shapes instead of the autotuner's "
+                         "(PF_FLAG_AUTOTUNE, tuned per shape class at batch creation)")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (batch 20, others 50)")
     ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (batch 2, others 5)")
     ap.add_argument("--N", type=int, default=65536)
