@@ -79,6 +79,14 @@ __global__ __launch_bounds__(kCrThreads) void k_tri_cr_whole(int nb, int p, cons
     }
     const int tpp = kCrThreads / p;
     const int part = tid / tpp, lt = tid % tpp;
+    // partitions that each lie within one wave (16, 32 or 64 of them, and
+    // up to 64 lanes each) need only their own wave's ordering between the
+    // rounds; the workgroup meets where the reduced system is formed
+    const bool wave_local = 64 % tpp == 0;   // uniform
+    auto round_sync = [&]() {
+        if (wave_local) wave_sync();
+        else __syncthreads();
+    };
     const bool mine = part < p;
     const int pm = mine ? part : 0;
     const bool hasL = mine && part > 0, hasR = mine && part < p - 1;
@@ -146,8 +154,9 @@ __global__ __launch_bounds__(kCrThreads) void k_tri_cr_whole(int nb, int p, cons
                 A[kj] = a; B[kj] = b; C[kj] = c; F[kj] = ff;
             }
         }
-        __syncthreads();
+        round_sync();
     }
+    __syncthreads();
 
     // the reduced system on the separators: row j (separator j = right
     // boundary of partition j - 1 and left boundary of partition j), by
@@ -209,7 +218,7 @@ __global__ __launch_bounds__(kCrThreads) void k_tri_cr_whole(int nb, int p, cons
                 F[kl] = (F[kl] - A[kl] * F[base + l - h] - C[kl] * F[base + q]) * recip(B[kl]);
             }
         }
-        __syncthreads();
+        round_sync();
     }
     if (bad != ~0ull) atomicMin(&sbad, bad);
     __syncthreads();
