@@ -61,7 +61,8 @@ typedef enum { PF_FP64 = 0, PF_FP32_IR = 1 } pf_prec;
 enum {
     PF_OK = 0,
     PF_ESINGULAR = 1,   /* exactly zero pivot inside a pivot block            */
-    PF_ENOCONV = 2,     /* refinement stagnated or hit max_refine            */
+    PF_ENOCONV = 2,     /* refinement stagnated, hit max_refine, or met a
+                           non-finite residual                              */
     PF_ENOMEM = 3,      /* a device allocation ran out of memory             */
     PF_EHIP = 4,        /* a HIP runtime call failed (any other error of an
                            allocation included): pf_last_hip_error        */

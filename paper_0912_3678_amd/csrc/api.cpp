@@ -1214,7 +1214,8 @@ int solve_call(pf_factor_s *F, int32_t nrhs, const double *f, int64_t ldf, doubl
     for (;;) {
         if ((rc = compute_eta(F, nrhs, f, ldf, x, ldx, F->wsR, n, s, &eta))) return rc;
         if (eta <= F->opts.tol) break;
-        if (iters >= F->opts.max_refine) { status = PF_ENOCONV; break; }
+        // a non-finite residual (a zero pivot's infinities, say) no step mends
+        if (iters >= F->opts.max_refine || !std::isfinite(eta)) { status = PF_ENOCONV; break; }
         slow = (eta > 0.5 * prev) ? slow + 1 : 0;
         if (slow >= 2) { status = PF_ENOCONV; break; }
         prev = eta;
@@ -1996,7 +1997,11 @@ int batch_refine(pf_batch_s *B, hipStream_t s, bool refine, std::vector<double> 
             eta[i] = w;
             if (!refine) continue;   // eta only (FP64 with PF_FLAG_ETA)
             if (w <= B->opts.tol) { done[i] = 1; continue; }
-            if (iters[i] >= B->opts.max_refine) { done[i] = 1; status[i] = PF_ENOCONV; continue; }
+            if (iters[i] >= B->opts.max_refine || !std::isfinite(w)) {
+                done[i] = 1;
+                status[i] = PF_ENOCONV;
+                continue;
+            }
             slow[i] = (w > 0.5 * prev[i]) ? slow[i] + 1 : 0;
             if (slow[i] >= 2) { done[i] = 1; status[i] = PF_ENOCONV; continue; }
             prev[i] = w;

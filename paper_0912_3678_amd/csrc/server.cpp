@@ -305,7 +305,7 @@ void refine_step(pf_server_s *S, int64_t id, Ticket &T)
     int status = PF_OK;
     bool done = true;
     if (T.eta <= o.tol) {
-    } else if (T.iters >= o.max_refine) {
+    } else if (T.iters >= o.max_refine || !std::isfinite(T.eta)) {
         status = PF_ENOCONV;
     } else {
         T.slow = (T.eta > 0.5 * T.prev) ? T.slow + 1 : 0;

@@ -93,3 +93,16 @@ def test_fp32_batch_equals_alone():
     assert all(i.eta <= G.ETA_TOL and i.refine_iters >= 1 for i in infos)
     _check_against_alone_and_oracle(systems, mats, fs, xs, opts, "fp32 batch")
     del keep
+
+
+@pytest.mark.parametrize("kind", ["btri", "babd"])
+def test_fp32_refinement_stops_on_a_zero_pivot(kind):
+    """A zero pivot block makes the FP32 solution non-finite: the refinement
+    stops at once (no step mends a non-finite residual) and the status is
+    the zero pivot's."""
+    s = wl.random_btri(300, 16, seed=77) if kind == "btri" else wl.random_babd(300, 16, seed=77)
+    s.D[0 if kind == "btri" else 1] = 0.0   # the first pivot block of partition 0
+    x, info, _ = G.gpu_solve(s, pf.make_opts(prec=pf.PF_FP32_IR, partitions=4))
+    _say(kind, info.as_dict())
+    assert info.status == pf.PF_ESINGULAR
+    assert info.refine_iters == 0
