@@ -69,9 +69,9 @@ def parse():
     ap.add_argument("--n-hi", type=int, default=0,
                     help="batch / serving: largest block count (default 2^16 / 2^20)")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: memory budget")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="batch: the planner's launch shapes instead of the autotuner's "
-                         "(PF_FLAG_AUTOTUNE, tuned per shape class at batch creation)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch: the autotuner's launch shapes (PF_FLAG_AUTOTUNE, tuned per "
+                         "shape class at batch creation) instead of the batch planner's")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (batch 20, others 50)")
     ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (batch 2, others 5)")
     ap.add_argument("--N", type=int, default=65536)
@@ -156,9 +156,10 @@ def source_hash(kernel_name):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_name):
+def load_traffic(kernel_name, grid=None):
     """HBM traffic measured by rocprofv3 counters for the kernel's current
-    sources, if recorded (profiles/traffic.json), else None."""
+    sources (and, when given, the same grid in threads), if recorded
+    (profiles/traffic.json), else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -167,6 +168,8 @@ def load_traffic(kernel_name):
         return None
     ent = rec.get("kernels", {}).get(kernel_name)
     if not ent or ent.get("source_hash") != source_hash(kernel_name):
+        return None
+    if grid is not None and ent.get("grid") != grid:
         return None
     return ent
 
@@ -823,7 +826,8 @@ def run_batch(args):
     precs = [args.prec] if args.prec else ["fp64", "fp32ir"]
     res = {}
     for prec in precs:
-        opts = pf.make_opts(prec=pf.PF_FP32_IR if prec == "fp32ir" else pf.PF_FP64, flags=flags)
+        opts = pf.make_opts(prec=pf.PF_FP32_IR if prec == "fp32ir" else pf.PF_FP64, flags=flags,
+                            block_rows=args.block_rows, coarse_rows=args.coarse_rows)
         t_c = time.perf_counter()
         B = pf.Batch(mats, opts, nrhs, fs, xs)
         create_s = time.perf_counter() - t_c
@@ -861,7 +865,7 @@ def run_batch(args):
     byt, fl, bound = batch_launch_roofline(dom, m_true)
     t = dom["ms"] * 1e-3
     kname = batch_kernel_name(dom)
-    traffic = load_traffic(kname)
+    traffic = load_traffic(kname, grid=dom["workgroups"] * 64)
     if bound == "mfma":
         peak = FP32_PEAK_TFLOPS if dom["f32"] else FP64_PEAK_TFLOPS
         roof = {"bound": "mfma", "achieved": round(fl / t / 1e12, 3), "peak": peak,
@@ -882,6 +886,13 @@ def run_batch(args):
         f_sys = 12.7 * m ** 3 * nb + 10 * m * m * nb * k
         t_roof += max(b_sys / (HBM_PEAK_GBS * 1e9), f_sys / (FP64_PEAK_TFLOPS * 1e12))
     for r in res.values():
+        # kernel time per block size, finest level and reduced levels apart
+        by_m = {}
+        for L in r["launches"]:
+            e = by_m.setdefault(str(L["m"]), {"level0_ms": 0.0, "reduced_ms": 0.0})
+            e["level0_ms" if L["level"] == 0 else "reduced_ms"] += L["ms"]
+        r["kernel_ms_by_m"] = {k: {kk: round(vv, 3) for kk, vv in v.items()}
+                               for k, v in sorted(by_m.items(), key=lambda kv: int(kv[0]))}
         r["launches"] = sorted(
             [{"kernel": batch_kernel_name(L), "phase": L["phase"], "level": L["level"],
               "m": L["m"], "rows": L["rows"], "rhs_rows": L["rhs_rows"],
@@ -902,6 +913,7 @@ def run_batch(args):
                    "matrix_GB": round(sum(3 * m * m * 8 * nb for m, nb, _, _ in specs) / 1e9, 2),
                    "rhs_GB": round(sum(8 * m * nb * k for m, nb, k, _ in specs) / 1e9, 2),
                    "autotune": bool(args.autotune),
+                   "block_rows": args.block_rows, "coarse_rows": args.coarse_rows,
                    "step": "pf_batch_run: factor + solve of every system, grouped launches "
                            "replayed from a HIP graph"},
         "eta_max": main["eta_max"],

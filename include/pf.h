@@ -275,6 +275,15 @@ void pf_autotune_clear(void);
  * systems spread over the workgroups of that launch.  The factor and solve
  * sequence of the whole batch is recorded once into a HIP graph and replayed.
  *
+ * Partitions (Sec. 2): with opts->block_rows and opts->partitions 0, the
+ * systems of one kind and block size m > 1 whose chain length the autotuner
+ * leaves open share a finest-level chain length: the longest, from the
+ * one-system default up to 64 blocks, that leaves at least 16384 partitions
+ * in their grouped launch (a batch has parallelism to spare where one system
+ * does not, and longer chains shrink the reduced levels).  A small batch keeps
+ * the one-system plan, and pf_batch_factor's handles report the plan used
+ * (pf_factor_level).
+ *
  * pf_batch_create: A, nrhs, f, ldf, x, ldx are HOST arrays of nsys entries
  * describing DEVICE buffers (layouts as for pf_factor / pf_solve; nrhs[i] may
  * be 0).  The batch keeps these pointers: pf_batch_run factors every A[i] as

@@ -2,9 +2,12 @@
 launches, recorded into a HIP graph and replayed.
 
 Every system of a batch runs the same per-partition work as when it is
-solved alone (same plan, same kernels' arithmetic), so batch results must
-equal the single-system results bit for bit; each is also held to the
-oracle's acceptance bounds."""
+solved alone with the same plan (the kernels' arithmetic is the same), so
+batch results must equal the single-system results bit for bit; each is
+also held to the oracle's acceptance bounds.  A small batch keeps the
+one-system plan; a batch whose systems of one block size hold enough block
+rows lengthens their finest-level chains, and its systems are compared with
+solo solves given that chain length."""
 import numpy as np
 import pytest
 
@@ -253,4 +256,39 @@ def test_batch_mixed_block_sizes_workload_subset():
     torch.cuda.synchronize()
     assert all(i.status == 0 for i in infos)
     _check_against_alone_and_oracle(systems, mats, fs, xs, None, "subset")
+    del keep
+
+
+def test_batch_long_chains_equal_alone_with_their_plan():
+    """m = 4 systems with 560 000 block rows in all: the batch planner
+    doubles their finest-level chain from 16 to 32 blocks (560 000 / 33 is at
+    least 16384 partitions, 560 000 / 65 is not), while the small m = 32
+    system keeps the one-system plan.  The handed-out factors report those
+    plans, and each system equals its solo solve with the same chain length,
+    bit for bit, within the oracle's bounds."""
+    import torch
+    specs = [("btri", 4, 300000, 2, 61), ("btri", 4, 200000, 1, 62), ("btri", 4, 60000, 3, 63),
+             ("btri", 32, 100, 2, 64)]
+    chain = [32, 32, 32, 0]
+    systems = _systems(specs)
+    mats, keep, fs, xs = _device(systems)
+    _say("long chains", [(s.kind, s.m, s.nb, f.shape[0]) for s, f in systems])
+    B = pf.Batch(mats, None, [f.shape[0] for _, f in systems], fs, xs)
+    try:
+        B.run()
+        torch.cuda.synchronize()
+        for i, ((s, f), A, fd, xd) in enumerate(zip(systems, mats, fs, xs)):
+            o = pf.make_opts(block_rows=chain[i])
+            F = B.factor(i)
+            try:
+                got = pf.pf_factor_levels(F)
+            finally:
+                pf.pf_destroy(F)
+            assert got == pf.pf_plan(A, o), f"sys {i}: batch plan {got[:2]}"
+            xa = _alone(A, fd, o)
+            xb = xd.cpu().numpy()
+            assert np.array_equal(xb, xa.cpu().numpy()), f"sys {i}: batch != alone"
+            G.check(s, xb.T, f=f.T, tag=f"long chains sys {i} m={s.m} nb={s.nb}")
+    finally:
+        B.destroy()
     del keep
