@@ -135,7 +135,9 @@ typedef struct {
     int32_t prec;       /* pf_prec                                            */
     int32_t max_refine; /* PF_FP32_IR iteration cap; <= 0 means 10           */
     int32_t block_rows; /* blocks per partition at the finest level when
-                           partitions == 0; 0 = autotuned table               */
+                           partitions == 0; 0 = the planner's table (Sec. 2
+                           leaves p free), doubled up to 64 while the level
+                           keeps at least 16384 partitions (m > 1)            */
     int32_t flags;      /* PF_FLAG_*                                          */
     int32_t coarse_rows;/* blocks per partition on the reduced levels; 0 = table */
     int32_t lane_entries;/* finest level, segment lane mapping: block entries per

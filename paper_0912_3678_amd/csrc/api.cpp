@@ -175,6 +175,30 @@ int target_rows(int kind, int M, bool f32, int level, const pf_opts &o)
     return 3;
 }
 
+// The finest level's chains grow past the table where the level has
+// partitions to spare: doubled, up to kSpareMaxChain blocks, while at least
+// kSpareMinParts partitions remain (sixteen per SIMD of the GPU).  Longer
+// chains cost the finest level little and shrink every reduced level (one
+// system of 2^20 blocks, factor and solve: 32.2 -> 29.8 ms for m = 32 and
+// 5.87 -> 5.14 ms for m = 16 with the rule's 32 blocks instead of 4; 1.35 ->
+// 1.32 ms for m = 8 with 32 instead of 16; the bidiagonal-plus-corner form,
+// m = 16, 2^18 blocks, FP32 factors and refinement: 3.17 -> 3.03 ms with 8
+// instead of 4).  Batches apply the
+// same rule to the rows of each grouped launch (batch_chain_lengths).
+// Scalar systems keep the table: their LDS-staged kernels bound the chain.
+constexpr int kSpareMaxChain = 64;
+constexpr int64_t kSpareMinParts = 16384;
+int spare_chain(int L, int64_t rows)
+{
+    while (2 * L <= kSpareMaxChain && rows / (2 * L + 1) >= kSpareMinParts) L *= 2;
+    return L;
+}
+int finest_chain(int kind, int M, bool f32, int64_t nb, const pf_opts &o)
+{
+    const int L = target_rows(kind, M, f32, 0, o);
+    return (o.block_rows > 0 || M == 1) ? L : spare_chain(L, nb);
+}
+
 constexpr int64_t kTail = 6;   // block tridiagonal systems this small: one chain
 
 // Scalar tridiagonal systems of at most kTriCrMaxRows rows in FP64 are
@@ -260,7 +284,8 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o,
             int64_t p;
             if (lvl == 0 && o.partitions > 0) p = o.partitions;
             else {
-                const int L = target_rows(kind, M, f32, lvl, o);
+                const int L = lvl == 0 ? finest_chain(kind, M, f32, cur, o)
+                                       : target_rows(kind, M, f32, lvl, o);
                 p = (cur - 1) / (L + 1);
                 p = std::max<int64_t>(p, 1);
                 p = std::min<int64_t>(p, (cur - 1) / 2);
@@ -286,7 +311,8 @@ std::vector<PlanLevel> make_plan(int kind, int64_t nb, int M, const pf_opts &o,
         else if (lvl == 0 && tri_cr_default(M, cur, o)) p = tri_cr_parts(cur);
         else if (cur <= kTail || (M == 1 && lvl > 0 && cur <= kTriMaxChain)) p = 1;
         else {
-            const int L = target_rows(kind, M, f32, lvl, o);
+            const int L = lvl == 0 ? finest_chain(kind, M, f32, cur, o)
+                                   : target_rows(kind, M, f32, lvl, o);
             p = (cur + 1) / (L + 1);
             p = std::max<int64_t>(p, 2);
             p = std::min<int64_t>(p, (cur + 1) / 2);
@@ -2024,20 +2050,14 @@ int batch_refine(pf_batch_s *B, hipStream_t s, bool refine, std::vector<double> 
 // errors are numbered as pf_solve_batch numbers them (existing = 10).
 // Finest-level chain length in a batch.  One grouped launch runs the
 // partitions of every system with the same kind and block size, so a batch
-// has parallelism to spare where one system of the same shape does not:
-// longer chains there cost the finest level little and shrink every reduced
-// level (block size 32, 139 systems, 1.38 M block rows: 63.8 ms of kernel
-// time with 4 blocks per partition, 57.0 with 32, 57.0 with 64, 57.9 with
-// 128).  Each group takes the longest chain, from the one-system default up
-// to kBatchMaxChain blocks, that leaves its launch at least kBatchMinParts
-// partitions (sixteen per SIMD of the GPU; on the 512-system batch this
-// picks 64 for every block size, within 1 % of the measured best, 32 or 64,
-// of each).  Systems whose
-// chain length is fixed -- by the caller, the autotuner or a partition count
-// -- keep it, and so do scalar systems, whose LDS-staged kernels bound the
-// chain.
-constexpr int kBatchMaxChain = 64;
-constexpr int64_t kBatchMinParts = 16384;
+// has parallelism to spare where one system of the same shape does not: each
+// such group takes spare_chain over the block rows of all its systems (block
+// size 32, 139 systems, 1.38 M block rows: 63.8 ms of kernel time with 4
+// blocks per partition, 57.0 with 32, 57.0 with 64, 57.9 with 128; on the
+// 512-system batch the rule picks 64 for every block size, within 1 % of the
+// measured best, 32 or 64, of each).  Systems whose chain length is fixed --
+// by the caller, the autotuner or a partition count -- keep it, and so do
+// scalar systems.
 void batch_chain_lengths(int32_t nsys, const pf_matrix *A, const pf_opts &o,
                          pf_factor_s *const *existing, std::vector<pf_opts> &os)
 {
@@ -2051,8 +2071,7 @@ void batch_chain_lengths(int32_t nsys, const pf_matrix *A, const pf_opts &o,
         if (open(i)) rows[{A[i].kind, padded_block(A[i].m)}] += A[i].nb;
     for (const auto &g : rows) {
         const int kind = g.first.first, M = g.first.second;
-        int L = target_rows(kind, M, o.prec == PF_FP32_IR, 0, o);
-        while (2 * L <= kBatchMaxChain && g.second / (2 * L + 1) >= kBatchMinParts) L *= 2;
+        const int L = spare_chain(target_rows(kind, M, o.prec == PF_FP32_IR, 0, o), g.second);
         for (int i = 0; i < nsys; ++i)
             if (open(i) && A[i].kind == kind && padded_block(A[i].m) == M) os[i].block_rows = L;
     }

@@ -102,9 +102,33 @@ def test_plan_finest_chain_lengths():
         return pf.pf_plan(_mat(kind, m, nb), pf.make_opts(prec=prec))[0][2]
     assert p0(pf.PF_BTRI, 8, 65537) == (65537 + 1) // 17
     assert p0(pf.PF_BABD, 16, 262145) == (262145 - 1) // 17
-    assert p0(pf.PF_BABD, 16, 262145, pf.PF_FP32_IR) == (262145 - 1) // 5
+    # FP32 factors of this form: 4 blocks in the table, doubled to 8 because
+    # 262144 / 9 partitions leave room (the chain rule below)
+    assert p0(pf.PF_BABD, 16, 262145, pf.PF_FP32_IR) == (262145 - 1) // 9
     assert p0(pf.PF_BTRI, 16, 65537) == (65537 + 1) // 5
     assert p0(pf.PF_BABD, 12, 262145) == (262145 - 1) // 17    # padded to 16
+
+
+def test_plan_finest_chain_grows_with_spare_partitions():
+    """The finest level keeps the table's chain until it has partitions to
+    spare: the chain doubles, up to 64 blocks, while at least 16384
+    partitions remain.  Scalar systems and an explicit block_rows keep
+    theirs."""
+    n20 = 1 << 20
+
+    def p0(kind, m, nb, **kw):
+        return pf.pf_plan(_mat(kind, m, nb), pf.make_opts(**kw))[0][2]
+    # m = 32: table 4; 2^20 blocks: 8, 16, 32 (2^20 / 33 >= 16384), not 64
+    assert p0(pf.PF_BTRI, 32, 65537) == 65538 // 5
+    assert p0(pf.PF_BTRI, 32, n20) == (n20 + 1) // 33
+    # m = 8: table 16; 2^20 blocks: 32, not 64 (2^20 / 65 < 16384)
+    assert p0(pf.PF_BTRI, 8, n20) == (n20 + 1) // 33
+    # the bidiagonal-plus-corner form (table 16 in FP64): 32
+    assert p0(pf.PF_BABD, 16, n20 + 1) == n20 // 33
+    # an explicit chain length, and scalar systems, are kept
+    assert p0(pf.PF_BTRI, 32, n20, block_rows=4) == (n20 + 1) // 5
+    assert p0(pf.PF_BTRI, 1, 1 << 24) == pf.pf_plan(
+        _mat(pf.PF_BTRI, 1, 1 << 24), pf.make_opts(block_rows=16))[0][2]
 
 
 def test_plan_reduced_chain_lengths():

@@ -322,6 +322,33 @@ def test_p_invariance(m, p):
     G.check(s, x, tag=f"p={p}")
 
 
+@pytest.mark.parametrize("m,kind", [(8, "btri"), (16, "btri"), (32, "btri"), (16, "babd")])
+@pytest.mark.parametrize("br", [32, 64])
+def test_long_finest_chains(m, kind, br):
+    """Chains of 32 and 64 blocks at the finest level (the planner's choice
+    for systems with partitions to spare) on the matrix-core kernels, against
+    the oracle."""
+    import torch
+    nb = 2000 if m < 32 else 1200
+    s = wl.random_btri(nb, m, seed=43 + m) if kind == "btri" else wl.random_babd(nb, m, seed=43 + m)
+    x, info, levels = G.gpu_solve(s, pf.make_opts(block_rows=br))
+    assert info.status == 0
+    G.check(s, x, tag=f"{kind} m={m} block_rows={br} levels={levels[:2]}")
+    # the fused factor-and-solve call (its finest level sweeps forward in the
+    # factor kernel where it can)
+    A, keep = G.to_device(s)
+    F = pf.pf_factor(A, pf.make_opts(block_rows=br))
+    try:
+        fd = G.rhs_to_device(s.f)
+        xd = torch.full_like(fd, np.nan)
+        assert pf.pf_factor_solve(F, fd, xd).status == 0
+        torch.cuda.synchronize()
+    finally:
+        pf.pf_destroy(F)
+    del keep
+    G.check(s, xd.cpu().numpy().T.reshape(x.shape), tag=f"fused {kind} m={m} block_rows={br}")
+
+
 @pytest.mark.parametrize("br", [1, 2, 3, 5, 16, 40])
 def test_block_rows_invariance(br):
     s = wl.random_btri(3001, 4, seed=42)
