@@ -286,19 +286,25 @@ def run_bvp(args):
         pf.pf_solve(F, f, x, want_info=False)
 
     def timed(step):
+        # throughput: K steps back to back between two synchronizations;
+        # then the same K steps again, each between its own two events, for
+        # the per-step latencies (the event commands would otherwise sit
+        # between the steps of the timed run)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         for a, b in evs:
             a.record()
             step()
             b.record()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         return wall * 1e3 / args.steps, np.array([a.elapsed_time(b) for a, b in evs])
 
     split_ms, _ = timed(step_split)
