@@ -44,12 +44,13 @@ def test_tri_cr_one_launch(nb, p):
     G.check(s, x[0], tag=f"cr nb={nb} p={p}")
 
 
-def test_tri_cr_poisson_closed_form():
+@pytest.mark.parametrize("p", [16, 64])
+def test_tri_cr_poisson_closed_form(p):
     """The discrete Poisson matrix (tridiag(-1, 2, -1), f = 1) at n = 4096
-    with 16 partitions: x_i = i (n + 1 - i) / 2."""
+    with 16 and 64 partitions: x_i = i (n + 1 - i) / 2."""
     s = wl.poisson(4096)
-    x, info, levels = _run(s, s.f.reshape(-1, 1), pf.make_opts(partitions=16), False)
-    assert info.status == 0 and levels[0][2] == 16
+    x, info, levels = _run(s, s.f.reshape(-1, 1), pf.make_opts(partitions=p), False)
+    assert info.status == 0 and levels[0][2] == p
     i = np.arange(1, 4097)
     exact = i * (4097 - i) / 2.0
     rel = np.abs(x[0] - exact).max() / exact.max()
@@ -88,10 +89,11 @@ def test_tri_cr_then_solve_refactors():
     del keep
 
 
-def test_tri_cr_zero_pivot():
+@pytest.mark.parametrize("p", [16, 64])
+def test_tri_cr_zero_pivot(p):
     """A zero diagonal entry at the first row of partition 7 (eliminated in
     the first round as it stands) is reported with that block."""
-    nb, p = 4096, 16
+    nb = 4096
     s = wl.scalar_tridiagonal(nb, seed=wl.seed_for(1, 320))
     nint = nb - (p - 1)
     q, rem = divmod(nint, p)
