@@ -769,10 +769,18 @@ int compute_eta(pf_factor_s *F, int nrhs, const double *f, int64_t ldf, const do
     return 0;
 }
 
+// The handle's device status word into info (PF_EHIP when it cannot be read).
 void read_status(pf_factor_s *F, pf_info *info)
 {
     unsigned long long st = ~0ull;
-    hipMemcpy(&st, F->d_status, sizeof st, hipMemcpyDeviceToHost);
+    const hipError_t e = hipMemcpy(&st, F->d_status, sizeof st, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        info->status = PF_EHIP;
+        info->bad_level = 0;
+        info->bad_block = -1;
+        return;
+    }
     if (st != ~0ull) {
         info->status = PF_ESINGULAR;
         info->bad_level = (int32_t)(st >> 40);

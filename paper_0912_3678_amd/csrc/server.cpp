@@ -323,7 +323,7 @@ void refine_step(pf_server_s *S, int64_t id, Ticket &T)
     }
     T.ir = false;
     T.info.status = status;   // kept; the device status word is read at retirement
-    hipEventRecord(T.ev_done, s);
+    if (hipEventRecord(T.ev_done, s) != hipSuccess) T.info.status = PF_EHIP;
     const int64_t home = r.factor >= 0 ? r.factor : (r.keep ? id : -1);
     if (home >= 0) S->resident[home].refining = false;
 }

@@ -99,7 +99,11 @@ extern "C" int pf_autotune(const pf_matrix *A, const pf_opts *base, int32_t nrhs
         hipFreeAsync(f, s);
         return PF_ENOMEM;
     }
-    launch_fill_u64((unsigned long long *)f, n * nrhs, 0x3FF0000000000000ull, s);   // f = 1
+    if (launch_fill_u64((unsigned long long *)f, n * nrhs, 0x3FF0000000000000ull, s) != hipSuccess) {   // f = 1
+        hipFreeAsync(f, s);
+        hipFreeAsync(x, s);
+        return PF_EHIP;
+    }
 
     // candidate mappings of the finest level: the segment widths with a
     // kernel for this block size, and rows
