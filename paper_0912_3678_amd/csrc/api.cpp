@@ -1861,13 +1861,24 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
         maxL = std::max(maxL, F->lv.size());
     }
     auto emit = [&](int phase, size_t l) {
+        // partitions per (kind, block size, precision, ADD) class of the
+        // level: the launches of a class share them
+        std::map<std::tuple<int, int, int, int>, int64_t> parts;
+        auto cls = [&](int i) {
+            const Level &L = B->all[i]->lv[l];
+            const int add = (phase == 1 && L.kind == PF_BTRI && args[i][l].Fadd) ? 1 : 0;
+            return std::make_tuple(L.kind, B->all[i]->M, L.f32 ? 1 : 0, add);
+        };
+        for (int i = 0; i < B->nsys; ++i)
+            if (l < B->all[i]->lv.size() && B->nrhs[i] > 0) parts[cls(i)] += B->all[i]->lv[l].p;
         std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
         for (int i = 0; i < B->nsys; ++i) {
             const pf_factor_s *F = B->all[i];
             if (l >= F->lv.size() || B->nrhs[i] == 0) continue;
             const Level &L = F->lv[l];
-            const int add = (phase == 1 && L.kind == PF_BTRI && args[i][l].Fadd) ? 1 : 0;
-            groups[{L.kind, F->M, L.f32 ? 1 : 0, add, solve_cols(F->M, L.f32, B->nrhs[i])}].push_back(i);
+            const auto c = cls(i);
+            groups[{L.kind, F->M, L.f32 ? 1 : 0, std::get<3>(c),
+                    solve_cols(F->M, L.f32, B->nrhs[i], parts[c])}].push_back(i);
         }
         for (auto &kv : groups) {
             BatchLaunch bl{phase, std::get<0>(kv.first), std::get<1>(kv.first),

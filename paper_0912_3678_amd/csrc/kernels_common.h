@@ -355,7 +355,8 @@ hipError_t dispatch_M(int M, F &&f)
 template <typename F>
 hipError_t dispatch_KC(int KC, F &&f)
 {
-    return KC == 1 ? f(std::integral_constant<int, 1>{}) : f(std::integral_constant<int, 4>{});
+    return KC == 1 ? f(std::integral_constant<int, 1>{})
+           : KC == 4 ? f(std::integral_constant<int, 4>{}) : f(std::integral_constant<int, 8>{});
 }
 
 inline dim3 grid_for(int M, int64_t p, int nrhs, int KC)

@@ -37,7 +37,10 @@ __global__ __launch_bounds__(WG) void kb_bwd(const SolveArgs *tab, const int4 *w
 }  // namespace
 
 int groups_per_wg(int M) { return WG / M; }
-int rhs_chunk(int nrhs) { return nrhs == 1 ? 1 : 4; }
+int rhs_chunk(int nrhs, int64_t parts)
+{
+    return nrhs == 1 ? 1 : (nrhs <= 4 || parts < kWideParts) ? 4 : 8;
+}
 
 template <int KIND, bool FWD>
 static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t s)
@@ -45,7 +48,7 @@ static hipError_t launch_solve(int M, bool f32, const SolveArgs &a, hipStream_t 
     if (solve_tiled(M, f32)) return launch_solvet(M, KIND, FWD, KIND == 0 && a.Fadd, f32, a, s);
     return dispatch_M(M, [&](auto mc) {
         constexpr int MV = decltype(mc)::value;
-        return dispatch_KC(rhs_chunk(a.nrhs), [&](auto kcc) {
+        return dispatch_KC(rhs_chunk(a.nrhs, a.p), [&](auto kcc) {
             constexpr int KC = decltype(kcc)::value;
             const dim3 grid = grid_for(MV, a.p, a.nrhs, KC);
             const bool add = KIND == 0 && a.Fadd;

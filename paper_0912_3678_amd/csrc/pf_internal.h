@@ -140,12 +140,17 @@ hipError_t launch_babd_bwd(int M, bool f32, const SolveArgs &a, hipStream_t s);
 // Batched launches: one launch serves every entry of a device table; work[w]
 // = (table entry, partition block, right-hand-side block, unused) for
 // workgroup w.  A solve partition block is groups_per_wg(M) partitions, a
-// right-hand-side block rhs_chunk(nrhs) columns; a factor work item covers
+// right-hand-side block rhs_chunk(nrhs, parts) columns; a factor work item covers
 // groups_per_wg(M) (rows) or seg_partitions_per_wg(M, E) (segments)
 // partitions.  Entries of one launch share kind, M, the mapping, precision,
 // the ADD variant and (solves) the chunk size.
 int groups_per_wg(int M);
-int rhs_chunk(int nrhs);
+// Right-hand-side columns per solve work item (vector-ALU solves): 1, 4, or 8
+// for more than four columns when the launch holds at least kWideParts
+// partitions (the factor rows are then read half as often; with fewer
+// partitions the columns are the launch's parallelism).
+constexpr int64_t kWideParts = 8192;
+int rhs_chunk(int nrhs, int64_t parts);
 hipError_t launch_factor_batch(int kind, int M, bool f32, bool add, const LevelArgs *tab,
                                const int4 *work, int nwg, hipStream_t s);
 hipError_t launch_seg_factor_batch(int kind, int M, int E, bool f32, bool add, const LevelArgs *tab,
@@ -276,9 +281,9 @@ int tuned_opts(const pf_matrix *A, const pf_opts &o, int nrhs, hipStream_t s, pf
 // workgroup and right-hand-side columns per workgroup (M = 16 and 32 with
 // FP64 factors: the matrix-core kernels)
 inline int solve_groups_per_wg(int M, bool f32) { return solve_tiled(M, f32) ? 1 : groups_per_wg(M); }
-inline int solve_cols(int M, bool f32, int nrhs)
+inline int solve_cols(int M, bool f32, int nrhs, int64_t parts)
 {
-    return solve_tiled(M, f32) ? solve32_cols(nrhs) : rhs_chunk(nrhs);
+    return solve_tiled(M, f32) ? solve32_cols(nrhs) : rhs_chunk(nrhs, parts);
 }
 
 }  // namespace pf
