@@ -761,7 +761,9 @@ __global__ __launch_bounds__(WG) void kb_babd_mfma16(const LevelArgs *tab, const
 template <typename F>
 hipError_t dispatch_CT(int cols, F &&f)
 {
-    return cols <= 16 ? f(std::integral_constant<int, 1>{}) : f(std::integral_constant<int, 2>{});
+    return cols <= 16   ? f(std::integral_constant<int, 1>{})
+           : cols <= 32 ? f(std::integral_constant<int, 2>{})
+                        : f(std::integral_constant<int, 4>{});
 }
 template <typename F>
 hipError_t dispatch_T(int M, F &&f)
@@ -831,21 +833,25 @@ template <typename V> struct Tiles {
     static hipError_t solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
     {
         if (a.nrhs < 1) return hipErrorInvalidValue;
-        const int cols = a.nrhs <= 16 ? 16 : 32;
+        const int cols = solve32_cols(M, a.nrhs, a.p);
         const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
         return dispatch_T(M, [&](auto mc) {
             constexpr int MV = decltype(mc)::value;
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
-                if (fwd) {
-                    if (kind == 1) launch_k(k_fwdt<MV, 1, CT, false, V>, grid, dim3(WG), s, a);
-                    else if (add) launch_k(k_fwdt<MV, 0, CT, true, V>, grid, dim3(WG), s, a);
-                    else launch_k(k_fwdt<MV, 0, CT, false, V>, grid, dim3(WG), s, a);
+                if constexpr (MV == 32 && CT == 4) {
+                    return hipErrorInvalidValue;   // 32 columns at most for 32 x 32 blocks
                 } else {
-                    if (kind == 1) launch_k(k_bwdt<MV, 1, CT, V>, grid, dim3(WG), s, a);
-                    else launch_k(k_bwdt<MV, 0, CT, V>, grid, dim3(WG), s, a);
+                    if (fwd) {
+                        if (kind == 1) launch_k(k_fwdt<MV, 1, CT, false, V>, grid, dim3(WG), s, a);
+                        else if (add) launch_k(k_fwdt<MV, 0, CT, true, V>, grid, dim3(WG), s, a);
+                        else launch_k(k_fwdt<MV, 0, CT, false, V>, grid, dim3(WG), s, a);
+                    } else {
+                        if (kind == 1) launch_k(k_bwdt<MV, 1, CT, V>, grid, dim3(WG), s, a);
+                        else launch_k(k_bwdt<MV, 0, CT, V>, grid, dim3(WG), s, a);
+                    }
+                    return hipGetLastError();
                 }
-                return hipGetLastError();
             });
         });
     }
@@ -857,18 +863,22 @@ template <typename V> struct Tiles {
             constexpr int MV = decltype(mc)::value;
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
-                if (fwd) {
-                    if (kind == 1)
-                        launch_k(kb_fwdt<MV, 1, CT, false, V>, dim3(nwg), dim3(WG), s, tab, work);
-                    else if (add)
-                        launch_k(kb_fwdt<MV, 0, CT, true, V>, dim3(nwg), dim3(WG), s, tab, work);
-                    else
-                        launch_k(kb_fwdt<MV, 0, CT, false, V>, dim3(nwg), dim3(WG), s, tab, work);
+                if constexpr (MV == 32 && CT == 4) {
+                    return hipErrorInvalidValue;   // 32 columns at most for 32 x 32 blocks
                 } else {
-                    if (kind == 1) launch_k(kb_bwdt<MV, 1, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
-                    else launch_k(kb_bwdt<MV, 0, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    if (fwd) {
+                        if (kind == 1)
+                            launch_k(kb_fwdt<MV, 1, CT, false, V>, dim3(nwg), dim3(WG), s, tab, work);
+                        else if (add)
+                            launch_k(kb_fwdt<MV, 0, CT, true, V>, dim3(nwg), dim3(WG), s, tab, work);
+                        else
+                            launch_k(kb_fwdt<MV, 0, CT, false, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    } else {
+                        if (kind == 1) launch_k(kb_bwdt<MV, 1, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
+                        else launch_k(kb_bwdt<MV, 0, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    }
+                    return hipGetLastError();
                 }
-                return hipGetLastError();
             });
         });
     }

@@ -35,8 +35,14 @@ hipError_t launch_mfma_babd16_factor_batch(bool f32, const LevelArgs *tab, const
                : Tiles<double>::babd16_factor_batch(tab, work, nwg, s);
 }
 
-// columns a workgroup of the tiled solve kernels covers
-int solve32_cols(int nrhs) { return nrhs <= 16 ? 16 : 32; }
+// columns a workgroup of the tiled solve kernels covers: 16 or 32, and 64
+// for 16 x 16 blocks in launches of at least kWideParts partitions (the
+// factor blocks of a block row then read once for up to 64 columns)
+int solve32_cols(int M, int nrhs, int64_t parts)
+{
+    if (nrhs <= 16) return 16;
+    return (M == 16 && nrhs > 32 && parts >= kWideParts) ? 64 : 32;
+}
 
 hipError_t launch_solvet(int M, int kind, bool fwd, bool add, bool f32, const SolveArgs &a,
                          hipStream_t s)
