@@ -833,14 +833,14 @@ template <typename V> struct Tiles {
     static hipError_t solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
     {
         if (a.nrhs < 1) return hipErrorInvalidValue;
-        const int cols = solve32_cols(M, a.nrhs, a.p);
+        const int cols = solve32_cols(M, sizeof(V) == 4, a.nrhs, a.p);
         const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
         return dispatch_T(M, [&](auto mc) {
             constexpr int MV = decltype(mc)::value;
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
-                if constexpr (MV == 32 && CT == 4) {
-                    return hipErrorInvalidValue;   // 32 columns at most for 32 x 32 blocks
+                if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
+                    return hipErrorInvalidValue;   // 32 columns at most for FP64 32 x 32 blocks
                 } else {
                     if (fwd) {
                         if (kind == 1) launch_k(k_fwdt<MV, 1, CT, false, V>, grid, dim3(WG), s, a);
@@ -863,8 +863,8 @@ template <typename V> struct Tiles {
             constexpr int MV = decltype(mc)::value;
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
-                if constexpr (MV == 32 && CT == 4) {
-                    return hipErrorInvalidValue;   // 32 columns at most for 32 x 32 blocks
+                if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
+                    return hipErrorInvalidValue;   // 32 columns at most for FP64 32 x 32 blocks
                 } else {
                     if (fwd) {
                         if (kind == 1)
