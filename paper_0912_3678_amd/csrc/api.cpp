@@ -1878,7 +1878,8 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
             const Level &L = F->lv[l];
             const auto c = cls(i);
             groups[{L.kind, F->M, L.f32 ? 1 : 0, std::get<3>(c),
-                    solve_cols(F->M, L.f32, B->nrhs[i], parts[c])}].push_back(i);
+                    solve_cols(F->M, L.f32, phase == 2 && L.kind == PF_BTRI, B->nrhs[i], parts[c])}]
+                .push_back(i);
         }
         for (auto &kv : groups) {
             BatchLaunch bl{phase, std::get<0>(kv.first), std::get<1>(kv.first),

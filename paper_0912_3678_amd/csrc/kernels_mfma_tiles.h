@@ -833,14 +833,18 @@ template <typename V> struct Tiles {
     static hipError_t solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
     {
         if (a.nrhs < 1) return hipErrorInvalidValue;
-        const int cols = solve32_cols(M, sizeof(V) == 4, a.nrhs, a.p);
+        const int cols = solve32_cols(M, sizeof(V) == 4, kind == 0 && !fwd, a.nrhs, a.p);
         const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
         return dispatch_T(M, [&](auto mc) {
             constexpr int MV = decltype(mc)::value;
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
                 if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
-                    return hipErrorInvalidValue;   // 32 columns at most for FP64 32 x 32 blocks
+                    // FP64 32 x 32 blocks: 64 columns only for the block
+                    // tridiagonal back substitution (the others would spill)
+                    if (fwd || kind != 0) return hipErrorInvalidValue;
+                    launch_k(k_bwdt<MV, 0, CT, V>, grid, dim3(WG), s, a);
+                    return hipGetLastError();
                 } else {
                     if (fwd) {
                         if (kind == 1) launch_k(k_fwdt<MV, 1, CT, false, V>, grid, dim3(WG), s, a);
@@ -864,7 +868,9 @@ template <typename V> struct Tiles {
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
                 if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
-                    return hipErrorInvalidValue;   // 32 columns at most for FP64 32 x 32 blocks
+                    if (fwd || kind != 0) return hipErrorInvalidValue;   // as in solvet
+                    launch_k(kb_bwdt<MV, 0, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    return hipGetLastError();
                 } else {
                     if (fwd) {
                         if (kind == 1)
