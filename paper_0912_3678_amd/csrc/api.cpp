@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -1760,6 +1761,11 @@ struct pf_batch_s {
     hipStream_t user = nullptr;         // the caller's stream at creation
     hipStream_t cap = nullptr;          // internal stream the graph is recorded on
     hipEvent_t ev = nullptr;
+    // branches of the recorded graph: one stream and join event per block
+    // size, whose launches depend on no other block size's
+    std::vector<hipStream_t> lane;
+    std::vector<hipEvent_t> lane_ev;
+    hipEvent_t fork = nullptr;
     Arena *arena = nullptr;
     std::vector<pf_factor_s *> F;       // per system (null once handed out, or the caller's)
     std::vector<pf_factor_s *> all;     // per system, for the recorded work
@@ -1906,16 +1912,21 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
     for (size_t l = maxL; l-- > 0;) emit(2, l);
 }
 
-hipError_t issue_factor(pf_batch_s *B, hipStream_t s, BatchTimes *T = nullptr)
+// Status words cleared and padded copies of the matrices made: what every
+// factor launch of the batch depends on.
+hipError_t factor_prologue(pf_batch_s *B, hipStream_t s)
 {
     hipError_t e = launch_fill_u64(B->d_words, B->nsys, ~0ull, s);
     if (e == hipSuccess) e = launch_fill_u64(B->d_words + B->nsys, B->nsys, 0ull, s);
     for (int i = 0; i < B->nsys; ++i)
         if (e == hipSuccess && !B->ext[i] && B->all[i]->M != B->all[i]->m)
             e = launch_pad_matrix(B->all[i], s);
-    for (const auto &bl : B->flaunch)
-        if (e == hipSuccess)
-            e = timed_launch(T, bl, [&] { return
+    return e;
+}
+
+hipError_t factor_launch(pf_batch_s *B, const BatchLaunch &bl, hipStream_t s, BatchTimes *T)
+{
+    return timed_launch(T, bl, [&] { return
               bl.seg == kMapMfma ? launch_mfma_factor_batch(B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
                 : bl.seg == kMapMfma32
                     ? launch_mfma32_factor_batch(bl.add, bl.f32, B->d_lev, B->d_lwork + bl.work, bl.nwg, s)
@@ -1927,33 +1938,81 @@ hipError_t issue_factor(pf_batch_s *B, hipStream_t s, BatchTimes *T = nullptr)
                                                    B->d_lwork + bl.work, bl.nwg, s)
                          : launch_factor_batch(bl.kind, bl.M, bl.f32, bl.add, B->d_lev,
                                                B->d_lwork + bl.work, bl.nwg, s); });
+}
+
+hipError_t issue_factor(pf_batch_s *B, hipStream_t s, BatchTimes *T = nullptr)
+{
+    hipError_t e = factor_prologue(B, s);
+    for (const auto &bl : B->flaunch)
+        if (e == hipSuccess) e = factor_launch(B, bl, s, T);
     return e;
 }
 
-hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t s,
-                       BatchTimes *T = nullptr)
+// right-hand sides of systems with a padded block size into their padded
+// workspace (before the solve launches), solutions back (after)
+hipError_t solve_pad(pf_batch_s *B, bool corr, bool in, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     for (int i = 0; i < B->nsys && e == hipSuccess; ++i) {
         pf_factor_s *F = B->all[i];
         if (F->M == F->m || B->nrhs[i] == 0) continue;
         const int64_t n = F->nb * F->m;
-        e = launch_pad_rhs(F->m, F->M, F->nb, B->nrhs[i], corr ? F->wsR : B->f[i],
-                           corr ? n : B->ldf[i], F->wsPadF, F->nb * F->M, true, s);
+        if (in)
+            e = launch_pad_rhs(F->m, F->M, F->nb, B->nrhs[i], corr ? F->wsR : B->f[i],
+                               corr ? n : B->ldf[i], F->wsPadF, F->nb * F->M, true, s);
+        else
+            e = launch_pad_rhs(F->m, F->M, F->nb, B->nrhs[i], F->wsPadX, F->nb * F->M,
+                               corr ? F->wsD : B->x[i], corr ? n : B->ldx[i], false, s);
     }
+    return e;
+}
+
+hipError_t solve_launch(const SolveSet &S, const BatchLaunch &bl, hipStream_t s, BatchTimes *T)
+{
+    return timed_launch(T, bl, [&] {
+        return launch_solve_batch(bl.kind, bl.phase == 1, bl.M, bl.f32, bl.add, bl.KC, S.d_tab,
+                                  S.d_work + bl.work, bl.nwg, s);
+    });
+}
+
+hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t s,
+                       BatchTimes *T = nullptr)
+{
+    hipError_t e = solve_pad(B, corr, true, s);
     for (const auto &bl : S.launches)
-        if (e == hipSuccess)
-            e = timed_launch(T, bl, [&] {
-                return launch_solve_batch(bl.kind, bl.phase == 1, bl.M, bl.f32, bl.add, bl.KC,
-                                          S.d_tab, S.d_work + bl.work, bl.nwg, s);
-            });
-    for (int i = 0; i < B->nsys && e == hipSuccess; ++i) {
-        pf_factor_s *F = B->all[i];
-        if (F->M == F->m || B->nrhs[i] == 0) continue;
-        const int64_t n = F->nb * F->m;
-        e = launch_pad_rhs(F->m, F->M, F->nb, B->nrhs[i], F->wsPadX, F->nb * F->M,
-                           corr ? F->wsD : B->x[i], corr ? n : B->ldx[i], false, s);
+        if (e == hipSuccess) e = solve_launch(S, bl, s, T);
+    if (e == hipSuccess) e = solve_pad(B, corr, false, s);
+    return e;
+}
+
+// The recorded graph: the prologues on s, then the systems of each block
+// size on a branch of their own -- their factor launches level by level,
+// then their solve launches -- the branches joined back into s before the
+// solutions are unpadded.  Launch for launch the work of issue_factor and
+// issue_solve; the block sizes only no longer wait for each other.  (Not
+// the kinds: the last level of a bidiagonal-plus-corner system is block
+// tridiagonal, in the launches of that kind.)
+hipError_t issue_branches(pf_batch_s *B, hipStream_t s)
+{
+    hipError_t e = factor_prologue(B, s);
+    if (e == hipSuccess) e = solve_pad(B, false, true, s);
+    if (e == hipSuccess) e = hipEventRecord(B->fork, s);
+    std::map<int, size_t> cls;
+    for (const auto &bl : B->flaunch) cls.emplace(bl.M, cls.size());
+    for (const auto &bl : B->sol.launches) cls.emplace(bl.M, cls.size());
+    for (const auto &c : cls) {
+        if (e != hipSuccess) break;
+        if (c.second >= B->lane.size()) return hipErrorInvalidValue;
+        hipStream_t ls = B->lane[c.second];
+        e = hipStreamWaitEvent(ls, B->fork, 0);
+        for (const auto &bl : B->flaunch)
+            if (e == hipSuccess && bl.M == c.first) e = factor_launch(B, bl, ls, nullptr);
+        for (const auto &bl : B->sol.launches)
+            if (e == hipSuccess && bl.M == c.first) e = solve_launch(B->sol, bl, ls, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(B->lane_ev[c.second], ls);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, B->lane_ev[c.second], 0);
     }
+    if (e == hipSuccess) e = solve_pad(B, false, false, s);
     return e;
 }
 
@@ -1974,6 +2033,9 @@ void batch_free(pf_batch_s *B)
     if (B->cap) hipStreamSynchronize(B->cap);
     if (B->exec) hipGraphExecDestroy(B->exec);
     if (B->graph) hipGraphDestroy(B->graph);
+    for (hipStream_t ls : B->lane) hipStreamDestroy(ls);
+    for (hipEvent_t le : B->lane_ev) hipEventDestroy(le);
+    if (B->fork) hipEventDestroy(B->fork);
     for (auto *F : B->F)
         if (F) pf_destroy(F);
     for (void *p : B->own) hipFree(p);
@@ -2292,11 +2354,25 @@ int batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const in
     }
     if (hipStreamSynchronize(us) != hipSuccess) return fail(PF_EHIP);
 
-    // record factor + solve once; pf_batch_run replays it
+    // record factor + solve once, one branch per block size;
+    // pf_batch_run replays it
+    {
+        std::set<int> cls;
+        for (const auto &bl : B->flaunch) cls.insert(bl.M);
+        for (const auto &bl : B->sol.launches) cls.insert(bl.M);
+        if (hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) != hipSuccess) return fail(PF_EHIP);
+        for (size_t c = 0; c < cls.size(); ++c) {
+            hipStream_t ls = nullptr;
+            hipEvent_t le = nullptr;
+            if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) return fail(PF_EHIP);
+            B->lane.push_back(ls);
+            if (hipEventCreateWithFlags(&le, hipEventDisableTiming) != hipSuccess) return fail(PF_EHIP);
+            B->lane_ev.push_back(le);
+        }
+    }
     if (hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(PF_EHIP);
-    hipError_t e = issue_factor(B, B->cap);
-    if (e == hipSuccess) e = issue_solve(B, B->sol, false, B->cap);
+    hipError_t e = issue_branches(B, B->cap);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
     B->graph = g;
