@@ -275,7 +275,9 @@ void pf_autotune_clear(void);
  * per-partition work of one level and phase goes into one kernel launch per
  * launch variant (kind, block size, precision), the partitions of all
  * systems spread over the workgroups of that launch.  The factor and solve
- * sequence of the whole batch is recorded once into a HIP graph and replayed.
+ * sequence of the whole batch is recorded once into a HIP graph and replayed;
+ * the launches of each block size form a branch of their own, so different
+ * block sizes run side by side.
  *
  * Partitions (Sec. 2): with opts->block_rows and opts->partitions 0, the
  * systems of one kind and block size m > 1 whose chain length the autotuner
