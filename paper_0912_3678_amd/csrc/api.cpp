@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <set>
 #include <tuple>
@@ -1997,7 +1998,8 @@ hipError_t issue_branches(pf_batch_s *B, hipStream_t s)
     hipError_t e = factor_prologue(B, s);
     if (e == hipSuccess) e = solve_pad(B, false, true, s);
     if (e == hipSuccess) e = hipEventRecord(B->fork, s);
-    std::map<int, size_t> cls;
+    // largest block size first: its branch is the longest
+    std::map<int, size_t, std::greater<int>> cls;
     for (const auto &bl : B->flaunch) cls.emplace(bl.M, cls.size());
     for (const auto &bl : B->sol.launches) cls.emplace(bl.M, cls.size());
     for (const auto &c : cls) {
