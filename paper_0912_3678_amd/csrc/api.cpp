@@ -1993,28 +1993,32 @@ hipError_t issue_solve(pf_batch_s *B, const SolveSet &S, bool corr, hipStream_t 
 // issue_solve; the block sizes only no longer wait for each other.  (Not
 // the kinds: the last level of a bidiagonal-plus-corner system is block
 // tridiagonal, in the launches of that kind.)
-hipError_t issue_branches(pf_batch_s *B, hipStream_t s)
+// (With factor == false: the solve set S alone, as the refinement's
+// correction solves are issued, on the same branch streams, eagerly.)
+hipError_t issue_branches(pf_batch_s *B, hipStream_t s, bool factor, const SolveSet &S, bool corr)
 {
-    hipError_t e = factor_prologue(B, s);
-    if (e == hipSuccess) e = solve_pad(B, false, true, s);
+    hipError_t e = factor ? factor_prologue(B, s) : hipSuccess;
+    if (e == hipSuccess) e = solve_pad(B, corr, true, s);
     if (e == hipSuccess) e = hipEventRecord(B->fork, s);
     // largest block size first: its branch is the longest
     std::map<int, size_t, std::greater<int>> cls;
-    for (const auto &bl : B->flaunch) cls.emplace(bl.M, cls.size());
-    for (const auto &bl : B->sol.launches) cls.emplace(bl.M, cls.size());
+    if (factor)
+        for (const auto &bl : B->flaunch) cls.emplace(bl.M, cls.size());
+    for (const auto &bl : S.launches) cls.emplace(bl.M, cls.size());
     for (const auto &c : cls) {
         if (e != hipSuccess) break;
         if (c.second >= B->lane.size()) return hipErrorInvalidValue;
         hipStream_t ls = B->lane[c.second];
         e = hipStreamWaitEvent(ls, B->fork, 0);
-        for (const auto &bl : B->flaunch)
-            if (e == hipSuccess && bl.M == c.first) e = factor_launch(B, bl, ls, nullptr);
-        for (const auto &bl : B->sol.launches)
-            if (e == hipSuccess && bl.M == c.first) e = solve_launch(B->sol, bl, ls, nullptr);
+        if (factor)
+            for (const auto &bl : B->flaunch)
+                if (e == hipSuccess && bl.M == c.first) e = factor_launch(B, bl, ls, nullptr);
+        for (const auto &bl : S.launches)
+            if (e == hipSuccess && bl.M == c.first) e = solve_launch(S, bl, ls, nullptr);
         if (e == hipSuccess) e = hipEventRecord(B->lane_ev[c.second], ls);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, B->lane_ev[c.second], 0);
     }
-    if (e == hipSuccess) e = solve_pad(B, false, false, s);
+    if (e == hipSuccess) e = solve_pad(B, corr, false, s);
     return e;
 }
 
@@ -2118,7 +2122,7 @@ int batch_refine(pf_batch_s *B, hipStream_t s, bool refine, std::vector<double> 
             all = false;
         }
         if (all || !refine) break;
-        HIPCHK(issue_solve(B, B->corr, true, s));
+        HIPCHK(issue_branches(B, s, false, B->corr, true));
         for (int i = 0; i < ns; ++i) {
             B->h_live2[i] = (!done[i] && B->nrhs[i] > 0) ? 1 : 0;
             if (!done[i]) ++iters[i];
@@ -2374,7 +2378,7 @@ int batch_create(int32_t nsys, const pf_matrix *A, const pf_opts *opts, const in
     }
     if (hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(PF_EHIP);
-    hipError_t e = issue_branches(B, B->cap);
+    hipError_t e = issue_branches(B, B->cap, true, B->sol, false);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
     B->graph = g;
