@@ -921,7 +921,7 @@ def run_batch(args):
                    "autotune": bool(args.autotune),
                    "block_rows": args.block_rows, "coarse_rows": args.coarse_rows,
                    "step": "pf_batch_run: factor + solve of every system, grouped launches "
-                           "replayed from a HIP graph"},
+                           "replayed from a HIP graph with one branch per block size"},
         "eta_max": main["eta_max"],
         "latency_ms": main["latency_ms"],
         "step_roofline": {"t_roof_ms": round(t_roof * 1e3, 2),
