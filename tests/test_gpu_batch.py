@@ -292,3 +292,28 @@ def test_batch_long_chains_equal_alone_with_their_plan():
     finally:
         B.destroy()
     del keep
+
+
+@pytest.mark.timeout(600)
+def test_batch_wide_launches_read_factors_once():
+    """Launches of 8192 partitions or more take 8 right-hand-side columns per
+    work item in the vector-ALU sweeps (m = 4 and 8, more than 4 columns)
+    and 64 per wave in the matrix-core sweeps of m = 16 and the m = 32 back
+    substitution (more than 32 columns).  Each system against the oracle,
+    and against its solo solve (whose launches are narrower) to rounding."""
+    import torch
+    specs = [("btri", 8, 75000, 12, 81), ("btri", 8, 75000, 6, 82), ("btri", 4, 75000, 9, 83),
+             ("btri", 4, 75000, 5, 84), ("btri", 16, 42000, 40, 85), ("btri", 32, 42000, 33, 86)]
+    systems = _systems(specs)
+    mats, keep, fs, xs = _device(systems)
+    _say("wide launches", [(s.m, s.nb, f.shape[0]) for s, f in systems])
+    infos, _ = pf.pf_solve_batch(mats, None, [f.shape[0] for _, f in systems], fs, xs)
+    torch.cuda.synchronize()
+    assert all(i.status == 0 for i in infos)
+    for i, ((s, f), A, fd, xd) in enumerate(zip(systems, mats, fs, xs)):
+        xb = xd.cpu().numpy()
+        xa = _alone(A, fd, None).cpu().numpy()
+        assert np.abs(xb - xa).max() <= 1e-12 * np.abs(xa).max(), f"sys {i}: batch vs alone"
+        xo = G.oracle_solve(s, f.T)
+        _say("wide", i, s.m, G.check(s, xb.T, f=f.T, xref=xo, tag=f"wide sys {i} m={s.m}"))
+    del keep
