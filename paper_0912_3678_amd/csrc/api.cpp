@@ -1702,7 +1702,8 @@ int pf_abd_to_btri(int32_t m, int64_t N, int32_t qa, const double *Ba, const dou
 
 // ===========================================================================
 // Batches: many independent systems, one launch per (level, phase, launch
-// key), the whole factor + solve sequence recorded into one HIP graph.
+// key), the whole factor + solve sequence recorded into one HIP graph with a
+// branch per block size (issue_branches).
 namespace {
 
 struct BatchLaunch {
