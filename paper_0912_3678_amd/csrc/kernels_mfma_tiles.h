@@ -455,7 +455,36 @@ __device__ __forceinline__ void fwdt_body(const SolveArgs &a, int64_t part, int 
         if constexpr (ADD) fp[j] = cadd<T>(fp[j], cload<T, V>(a.Fadd + G.start * M + cf[j], act[j] && G.valid, m));
         gl[j] = czero<T, V>();
     }
-    for (int k = 0; k < G.len; ++k) {
+    // 32 x 32 factors with 64 columns: one factor block in registers at a
+    // time (t_k for every tile, then R_k, then A(g+1,g)), so that the four
+    // tiles' f', t and g fit beside it
+    constexpr bool kStaged = M == 32 && CT == 4 && KIND == 0;
+    for (int k = 0; kStaged && k < G.len; ++k) {
+        const int64_t g = G.start + k;
+        const uint32_t row = rel + (uint32_t)k;
+        const bool nx = g + 1 < nb;
+        Col t[CT];
+        {
+            const Q eT = qload<false, T, V, V>(rE, row * BF, m, n);
+#pragma unroll
+            for (int j = 0; j < CT; ++j) t[j] = mmc(eT, fp[j], czero<T, V>());   // t_k = E_k f'_k
+        }
+#pragma unroll
+        for (int j = 0; j < CT; ++j) cstore<T>(a.Y + g * M + cy[j], act[j], t[j], m);
+        if (G.hasL) {
+            const Q nrt = qneg<T>(qload<false, T, V, V>(rR, row * BF, m, n));
+#pragma unroll
+            for (int j = 0; j < CT; ++j) gl[j] = mmc(nrt, t[j], gl[j]);         // g_sL -= R_k t_k
+        }
+        const Q nlo = qneg<T>(qload<true, T, V>(rL, row * BB, m, n));
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            Col fn = cload<T, V>(a.F + (g + 1) * M + cf[j], act[j] && nx, m);
+            if constexpr (ADD) fn = cadd<T>(fn, cload<T, V>(a.Fadd + (g + 1) * M + cf[j], act[j] && nx, m));
+            fp[j] = mmc(nlo, t[j], fn);                                          // f'_{k+1}
+        }
+    }
+    for (int k = 0; !kStaged && k < G.len; ++k) {
         const int64_t g = G.start + k;
         const uint32_t row = rel + (uint32_t)k;
         const Q eT = qload<false, T, V, V>(rE, row * BF, m, n);     // E_g^T (E row-major)
@@ -833,17 +862,19 @@ template <typename V> struct Tiles {
     static hipError_t solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
     {
         if (a.nrhs < 1) return hipErrorInvalidValue;
-        const int cols = solve32_cols(M, sizeof(V) == 4, kind == 0 && !fwd, a.nrhs, a.p);
+        const int cols = solve32_cols(M, sizeof(V) == 4, kind == 0, a.nrhs, a.p);
         const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
         return dispatch_T(M, [&](auto mc) {
             constexpr int MV = decltype(mc)::value;
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
                 if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
-                    // FP64 32 x 32 blocks: 64 columns only for the block
-                    // tridiagonal back substitution (the others would spill)
-                    if (fwd || kind != 0) return hipErrorInvalidValue;
-                    launch_k(k_bwdt<MV, 0, CT, V>, grid, dim3(WG), s, a);
+                    // FP64 32 x 32 blocks: 64 columns only for block
+                    // tridiagonal levels (the bidiagonal ones would spill)
+                    if (kind != 0) return hipErrorInvalidValue;
+                    if (!fwd) launch_k(k_bwdt<MV, 0, CT, V>, grid, dim3(WG), s, a);
+                    else if (add) launch_k(k_fwdt<MV, 0, CT, true, V>, grid, dim3(WG), s, a);
+                    else launch_k(k_fwdt<MV, 0, CT, false, V>, grid, dim3(WG), s, a);
                     return hipGetLastError();
                 } else {
                     if (fwd) {
@@ -868,8 +899,10 @@ template <typename V> struct Tiles {
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
                 if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
-                    if (fwd || kind != 0) return hipErrorInvalidValue;   // as in solvet
-                    launch_k(kb_bwdt<MV, 0, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    if (kind != 0) return hipErrorInvalidValue;   // as in solvet
+                    if (!fwd) launch_k(kb_bwdt<MV, 0, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    else if (add) launch_k(kb_fwdt<MV, 0, CT, true, V>, dim3(nwg), dim3(WG), s, tab, work);
+                    else launch_k(kb_fwdt<MV, 0, CT, false, V>, dim3(nwg), dim3(WG), s, tab, work);
                     return hipGetLastError();
                 } else {
                     if (fwd) {
