@@ -298,9 +298,9 @@ def test_batch_long_chains_equal_alone_with_their_plan():
 def test_batch_wide_launches_read_factors_once():
     """Launches of 8192 partitions or more take 8 right-hand-side columns per
     work item in the vector-ALU sweeps (m = 4 and 8, more than 4 columns)
-    and 64 per wave in the matrix-core sweeps of m = 16 and the m = 32 back
-    substitution (more than 32 columns).  Each system against the oracle,
-    and against its solo solve (whose launches are narrower) to rounding."""
+    and 64 per wave in the matrix-core sweeps of m = 16 and the m = 32 block
+    tridiagonal sweeps, forward and back (more than 32 columns).  Each system
+    against the oracle, and against its solo solve to rounding."""
     import torch
     specs = [("btri", 8, 75000, 12, 81), ("btri", 8, 75000, 6, 82), ("btri", 4, 75000, 9, 83),
              ("btri", 4, 75000, 5, 84), ("btri", 16, 42000, 40, 85), ("btri", 32, 42000, 33, 86)]
