@@ -1886,7 +1886,7 @@ void build_solve_tables(pf_batch_s *B, const std::vector<const double *> &rhs,
             const Level &L = F->lv[l];
             const auto c = cls(i);
             groups[{L.kind, F->M, L.f32 ? 1 : 0, std::get<3>(c),
-                    solve_cols(F->M, L.f32, L.kind == PF_BTRI, B->nrhs[i], parts[c])}]
+                    solve_cols(F->M, L.f32, L.kind == PF_BTRI && !std::get<3>(c), B->nrhs[i], parts[c])}]
                 .push_back(i);
         }
         for (auto &kv : groups) {

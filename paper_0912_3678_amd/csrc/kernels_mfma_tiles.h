@@ -862,7 +862,7 @@ template <typename V> struct Tiles {
     static hipError_t solvet(int M, int kind, bool fwd, bool add, const SolveArgs &a, hipStream_t s)
     {
         if (a.nrhs < 1) return hipErrorInvalidValue;
-        const int cols = solve32_cols(M, sizeof(V) == 4, kind == 0, a.nrhs, a.p);
+        const int cols = solve32_cols(M, sizeof(V) == 4, kind == 0 && !(fwd && add), a.nrhs, a.p);
         const dim3 grid((unsigned)a.p, (unsigned)((a.nrhs + cols - 1) / cols));
         return dispatch_T(M, [&](auto mc) {
             constexpr int MV = decltype(mc)::value;
@@ -870,10 +870,10 @@ template <typename V> struct Tiles {
                 constexpr int CT = decltype(ct)::value;
                 if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
                     // FP64 32 x 32 blocks: 64 columns only for block
-                    // tridiagonal levels (the bidiagonal ones would spill)
-                    if (kind != 0) return hipErrorInvalidValue;
+                    // tridiagonal sweeps of one right-hand side (the
+                    // bidiagonal ones and an added second one would spill)
+                    if (kind != 0 || (fwd && add)) return hipErrorInvalidValue;
                     if (!fwd) launch_k(k_bwdt<MV, 0, CT, V>, grid, dim3(WG), s, a);
-                    else if (add) launch_k(k_fwdt<MV, 0, CT, true, V>, grid, dim3(WG), s, a);
                     else launch_k(k_fwdt<MV, 0, CT, false, V>, grid, dim3(WG), s, a);
                     return hipGetLastError();
                 } else {
@@ -899,9 +899,8 @@ template <typename V> struct Tiles {
             return dispatch_CT(cols, [&](auto ct) {
                 constexpr int CT = decltype(ct)::value;
                 if constexpr (MV == 32 && CT == 4 && sizeof(V) == 8) {
-                    if (kind != 0) return hipErrorInvalidValue;   // as in solvet
+                    if (kind != 0 || (fwd && add)) return hipErrorInvalidValue;   // as in solvet
                     if (!fwd) launch_k(kb_bwdt<MV, 0, CT, V>, dim3(nwg), dim3(WG), s, tab, work);
-                    else if (add) launch_k(kb_fwdt<MV, 0, CT, true, V>, dim3(nwg), dim3(WG), s, tab, work);
                     else launch_k(kb_fwdt<MV, 0, CT, false, V>, dim3(nwg), dim3(WG), s, tab, work);
                     return hipGetLastError();
                 } else {

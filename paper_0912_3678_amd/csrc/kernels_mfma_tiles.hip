@@ -38,13 +38,14 @@ hipError_t launch_mfma_babd16_factor_batch(bool f32, const LevelArgs *tab, const
 // columns a workgroup of the tiled solve kernels covers: 16 or 32, and 64
 // in launches of at least kWideParts partitions (the factor blocks of a block
 // row then read once for up to 64 columns) for 16 x 16 blocks, FP32 factors
-// of 32 x 32 blocks and block tridiagonal levels with FP64 32 x 32 factors
-// (the bidiagonal FP64 32 x 32 sweeps would not fit the registers)
-int solve32_cols(int M, bool f32, bool btri, int nrhs, int64_t parts)
+// of 32 x 32 blocks and, with FP64 32 x 32 factors, block tridiagonal sweeps
+// of one right-hand side (wide64: not a bidiagonal level, whose sweeps would
+// not fit the registers, nor a forward sweep that adds a second one)
+int solve32_cols(int M, bool f32, bool wide64, int nrhs, int64_t parts)
 {
     if (nrhs <= 16) return 16;
     if (nrhs <= 32 || parts < kWideParts) return 32;
-    return (M == 16 || f32 || btri) ? 64 : 32;
+    return (M == 16 || f32 || wide64) ? 64 : 32;
 }
 
 hipError_t launch_solvet(int M, int kind, bool fwd, bool add, bool f32, const SolveArgs &a,

@@ -105,9 +105,9 @@ hipError_t launch_mfma_babd16_factor(const LevelArgs &a, const SolveArgs *sv, bo
 hipError_t launch_mfma_babd16_factor_batch(bool f32, const LevelArgs *tab, const int4 *work,
                                            int nwg, hipStream_t s);
 // matrix-core forward sweep / back substitution for M = 16, 32 (FP64 or FP32
-// factors): one partition per workgroup, solve32_cols(M, f32, btri,
+// factors): one partition per workgroup, solve32_cols(M, f32, wide64,
 // nrhs, parts) right-hand sides each
-int solve32_cols(int M, bool f32, bool btri, int nrhs, int64_t parts);
+int solve32_cols(int M, bool f32, bool wide64, int nrhs, int64_t parts);
 hipError_t launch_solvet(int M, int kind, bool fwd, bool add, bool f32, const SolveArgs &a,
                          hipStream_t s);
 hipError_t launch_solvet_batch(int M, int kind, bool fwd, bool add, bool f32, int cols,
@@ -281,9 +281,9 @@ int tuned_opts(const pf_matrix *A, const pf_opts &o, int nrhs, hipStream_t s, pf
 // workgroup and right-hand-side columns per workgroup (M = 16 and 32 with
 // FP64 factors: the matrix-core kernels)
 inline int solve_groups_per_wg(int M, bool f32) { return solve_tiled(M, f32) ? 1 : groups_per_wg(M); }
-inline int solve_cols(int M, bool f32, bool btri, int nrhs, int64_t parts)
+inline int solve_cols(int M, bool f32, bool wide64, int nrhs, int64_t parts)
 {
-    return solve_tiled(M, f32) ? solve32_cols(M, f32, btri, nrhs, parts)
+    return solve_tiled(M, f32) ? solve32_cols(M, f32, wide64, nrhs, parts)
                                : rhs_chunk(nrhs, parts);
 }
 
